@@ -1,0 +1,247 @@
+/*
+ * sfairsc.h — C ABI of the s-FairSC GPU library (AMD MI355X / gfx950).
+ *
+ * Scalable fair spectral clustering (Wang, Lu, Davidson and Bai, "Scalable
+ * Spectral Clustering with Group Fairness Constraints", AISTATS 2023).
+ *
+ * Problem (Section 2.2, eq. normal-prob-fair): given an undirected graph with
+ * weighted adjacency W (w_ij >= 0, w_ii = 0), degrees d = W 1, Laplacian
+ * L = D - W and a partition of the vertices into h groups, find the k
+ * eigenpairs of smallest eigenvalue of L restricted to null(F^T), where F is
+ * the n x (h-1) group-fairness matrix of Lemma 2.1 (F_0 = G - 1 z^T with
+ * z = G^T 1 / n, first h-1 columns).
+ *
+ *   normalized = 1: the paper's Alg. 3.  X = D^{1/2} H, C = D^{-1/2} F,
+ *                   L_n = D^{-1/2} L D^{-1/2}; outputs H = D^{-1/2} X
+ *                   (H^T D H = I, F^T H = 0).
+ *   normalized = 0: the same derivation with D replaced by I in the
+ *                   constraint: C = F, operator L, H = X (H^T H = I).
+ *
+ * Method (Section 3.3-3.4, Alg. 3): the k smallest eigenpairs of the deflated
+ * operator L^sigma = P (L_n - sigma I) P + sigma I (eq. asigma), with
+ * P = I - C (C^T C)^{-1} C^T applied from the group labels (eq. mv-Pw) and
+ * sigma = ||L_n||_1 (Appendix B.3), found by a block Krylov-Schur
+ * (thick-restart Lanczos) eigensolver; then k-means on the rows of H
+ * (Alg. 3 step 4).  Proposition 3.3 makes these exactly the fair solution.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented "device" must point to GPU memory on the current
+ *     HIP device; "host" pointers to CPU memory.
+ *   - Dense blocks: "row-major n x b" means element (i, j) at [i * b + j];
+ *     "column-major n x k" means element (i, j) at [j * n + i].
+ *   - All work is enqueued on `stream` (0 = the null stream) and is
+ *     asynchronous unless stated; functions that return host values
+ *     synchronise `stream` before returning.
+ *   - Every function returns SFAIRSC_OK (0) or a negative status; on error
+ *     sfairsc_last_error() gives a message (per host thread).  No C++
+ *     exception crosses this interface.
+ *   - A graph handle is not thread-safe: calls on one handle must not
+ *     overlap.  Calls on distinct handles may.
+ */
+#ifndef SFAIRSC_H
+#define SFAIRSC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+    SFAIRSC_OK = 0,
+    SFAIRSC_E_ARG = -1,           /* invalid argument or malformed CSR           */
+    SFAIRSC_E_ASYM = -2,          /* W not symmetric (structure or value)        */
+    SFAIRSC_E_EMPTY_GROUP = -3,   /* some group has no vertex (eq. groupdef)     */
+    SFAIRSC_E_ISOLATED = -4,      /* d_i = 0 with normalized = 1 (D must be p.d.) */
+    SFAIRSC_E_NOT_CONVERGED = -5, /* outputs hold the best current pairs         */
+    SFAIRSC_E_DEGENERATE = -6,    /* reserved                                    */
+    SFAIRSC_E_HIP = -7,           /* a HIP runtime call failed                   */
+    SFAIRSC_E_NOMEM = -8          /* device allocation failed                    */
+};
+
+enum { SFAIRSC_F32 = 0, SFAIRSC_F64 = 1 };              /* value dtypes */
+enum { SFAIRSC_PREC_FP64 = 0, SFAIRSC_PREC_MIXED = 1 }; /* arithmetic   */
+
+typedef struct sfairsc_graph* sfairsc_graph_t;
+
+/* ---- graph ----------------------------------------------------------- */
+
+/*
+ * Build a graph handle (Alg. 3 steps 1-2: L, L_n and C; Lemma 2.1: F).
+ *
+ * rowptr  device int32[n+1]   CSR row pointers of W, rowptr[0] = 0,
+ *                             rowptr[n] = nnz, non-decreasing.
+ * colidx  device int32[nnz]   column indices, strictly increasing in a row,
+ *                             no diagonal entry (w_ii = 0).
+ * values  device [nnz]        w_ij >= 0, finite; float (value_dtype =
+ *                             SFAIRSC_F32) or double (SFAIRSC_F64).  Both
+ *                             stored copies (i,j) and (j,i) must be present
+ *                             and bitwise equal.
+ * group   device int32[n]     group label of each vertex in [0, h); every
+ *                             group non-empty.  h >= 1 (h = 1 is plain
+ *                             spectral clustering, Alg. 1).
+ * normalized                  1: Alg. 3 (L_n, C = D^{-1/2} F); 0: L, C = F.
+ *
+ * The library copies every input into its own device buffers, so the caller
+ * may free them once this returns.  Validation runs on the device; the call
+ * synchronises `stream`.  Errors: E_ARG (sizes, ranges, CSR structure,
+ * non-finite or negative weights, h > 32), E_ASYM, E_EMPTY_GROUP,
+ * E_ISOLATED (normalized only), E_NOMEM, E_HIP.  *out is NULL on error.
+ */
+int sfairsc_graph_create(sfairsc_graph_t* out, int64_t n, int64_t nnz,
+                         const int32_t* rowptr, const int32_t* colidx,
+                         const void* values, int value_dtype,
+                         const int32_t* group, int32_t h, int normalized,
+                         hipStream_t stream);
+
+/* Release every device buffer of the handle (synchronises the device). */
+void sfairsc_graph_destroy(sfairsc_graph_t g);
+
+typedef struct sfairsc_graph_stats {
+    int64_t n, nnz;
+    int32_t h, normalized, value_dtype, reserved;
+    double sigma;      /* ||L_n||_1 (normalized) or ||L||_1 = 2 max_i d_i   */
+    double min_degree, max_degree;
+} sfairsc_graph_stats;
+
+/* Host copy of the handle's scalar properties (no device work). */
+int sfairsc_graph_query(sfairsc_graph_t g, sfairsc_graph_stats* out);
+
+/* ---- operator (Section 3.4, implementation issues (i)-(ii)) ----------- */
+
+/*
+ * Y = L^sigma X = P (L_n (P X)) - sigma P X + sigma X   (eq. asigma).
+ *
+ * X, Y   device double, row-major n x b, 1 <= b <= 32, must not overlap.
+ * precision  SFAIRSC_PREC_FP64: all arithmetic in double.
+ *            SFAIRSC_PREC_MIXED: P X is rounded to float and the sparse
+ *            product L_n (P X) runs in float with float accumulation; the
+ *            projections and the deflation stay in double.
+ * sigma  shift; <= 0 selects the handle's ||L_n||_1.
+ * Asynchronous.  Errors: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_apply_operator(sfairsc_graph_t g, const double* X, double* Y,
+                           int32_t b, int precision, double sigma,
+                           hipStream_t stream);
+
+/*
+ * T = L_n X (normalized) or T = L X (unnormalized) with no projection: the
+ * sparse product alone (the matrix-vector product of Section 3.4 (i)).
+ * X, T   device row-major n x b, 1 <= b <= 32, float for SFAIRSC_PREC_MIXED
+ *        and double for SFAIRSC_PREC_FP64; must not overlap.
+ * Asynchronous.  Errors: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_spmm(sfairsc_graph_t g, const void* X, void* T, int32_t b,
+                 int precision, hipStream_t stream);
+
+/* ---- eigensolver (Alg. 3 step 3) -------------------------------------- */
+
+typedef struct sfairsc_eigs_opts {
+    int32_t block_width;   /* b in {4, 8, 16, 32}; 0 = automatic          */
+    int32_t max_basis;     /* basis columns before a restart (<= 192);
+                              0 = automatic                                */
+    int32_t max_restarts;  /* 0 = automatic (2000)                        */
+    int32_t keep;          /* Ritz vectors kept at a restart; 0 = auto    */
+    uint64_t seed;         /* seed of the random start block              */
+    double sigma;          /* Hotelling shift; <= 0 selects ||L_n||_1     */
+    int32_t certify;       /* 1: recompute the final residuals with an
+                              FP64 operator application                   */
+    int32_t time_kernels;  /* 1: time every SpMM launch with HIP events
+                              (reported in sfairsc_eigs_info)             */
+    const double* x0;      /* optional device row-major n x b0 warm start */
+    int32_t b0;            /* columns of x0 (0 = none), <= block width    */
+    int32_t reserved;
+} sfairsc_eigs_opts;
+
+typedef struct sfairsc_eigs_info {
+    int32_t restarts;          /* Rayleigh-Ritz / restart cycles           */
+    int32_t converged;         /* wanted pairs meeting the tolerance       */
+    int32_t block_steps;       /* block Krylov expansions                  */
+    int32_t breakdowns;        /* rank-deficient residual blocks repaired  */
+    int64_t operator_applies;  /* columns multiplied by L^sigma            */
+    int64_t spmm_launches[2];  /* [0] FP64 SpMM launches, [1] FP32         */
+    double spmm_ms[2];         /* summed SpMM kernel time (time_kernels)   */
+    double max_rel_residual;   /* max_i ||L^s x_i - theta_i x_i|| / sigma  */
+    double sigma;              /* shift used                               */
+    double gap_ratio;          /* (theta_{k+1} - theta_k) / sigma, last RR */
+    double phase1_ms;          /* mixed precision: host wall time of the
+                                  FP32-SpMM phase; 0 otherwise             */
+} sfairsc_eigs_info;
+
+/* Fill *opts with the defaults (all automatic, seed 0, certify 1). */
+void sfairsc_eigs_opts_init(sfairsc_eigs_opts* opts);
+
+/*
+ * The k smallest eigenpairs of L^sigma (Proposition 3.3: for sigma above
+ * the k-th fair eigenvalue they are the fair eigenpairs).
+ *
+ * k        1 <= k <= n - h + 1 and k <= 64.
+ * tol      pair i is converged when ||L^sigma x_i - theta_i x_i||_2 <=
+ *          tol * sigma (a backward error, as ||L^sigma||_2 = sigma).
+ * precision SFAIRSC_PREC_FP64, or SFAIRSC_PREC_MIXED: the basis is built
+ *          with float sparse products; if the FP64 residuals then miss tol
+ *          the solve continues with double sparse products, warm-started
+ *          from the float result, so both precisions meet the same tol.
+ * opts     may be NULL (defaults).
+ * eigvals  host double[k], ascending.
+ * H        device double, column-major n x k: H = D^{-1/2} X (normalized)
+ *          or X; each column's largest-magnitude entry is positive (lowest
+ *          index on ties).
+ * info     may be NULL.
+ * Synchronises `stream`.  Returns SFAIRSC_E_NOT_CONVERGED (outputs and info
+ * still written: the best current pairs) if max_restarts is reached.  The
+ * handle keeps its workspace for later calls (no allocation after the
+ * first call of a given shape).  Errors also: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_eigs(sfairsc_graph_t g, int32_t k, double tol, int precision,
+                 const sfairsc_eigs_opts* opts, double* eigvals, double* H,
+                 sfairsc_eigs_info* info, hipStream_t stream);
+
+/* ---- clustering (Alg. 3 step 4) -------------------------------------- */
+
+/*
+ * k-means on the n rows of H (device double, column-major n x kdim,
+ * 1 <= kdim <= 64): k-means++ seeding driven by SplitMix64 uniforms
+ * (restart r, draw t uses output r * 2^32 + t + 1 of the stream seeded with
+ * `seed`), Lloyd iterations until no label changes or max_iter (0 = 300),
+ * best inertia of n_restarts, labels renumbered by first appearance.
+ * labels   device int32[n].
+ * inertia  host double (may be NULL).
+ * 2 <= n_clusters <= min(64, n).  Synchronises `stream`.
+ * Errors: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_labels(sfairsc_graph_t g, const double* H, int32_t kdim,
+                   int32_t n_clusters, int32_t n_restarts, uint64_t seed,
+                   int32_t max_iter, int32_t* labels, double* inertia,
+                   hipStream_t stream);
+
+/* ---- differentiation -------------------------------------------------- */
+
+/*
+ * Gradient of f(W) = sum_{i<=k} lambda_i (the k smallest fair eigenvalues,
+ * unnormalized variant) with respect to every stored value w_ij, by the
+ * envelope theorem applied to Theorem 2.1 / Proposition 3.3:
+ *     grad[e] = 0.5 * sum_l (H[i,l] - H[j,l])^2   for stored entry e = (i,j),
+ * so the two stored copies of an edge together carry d f / d w_ij.
+ * sigma is held constant.  Valid when lambda_k < lambda_{k+1}.
+ * H          device double, column-major n x k (from sfairsc_eigs).
+ * grad       device [nnz] in the handle's value dtype.
+ * Errors: E_ARG (normalized handles: not supported), E_HIP.  Asynchronous.
+ */
+int sfairsc_eigsum_backward(sfairsc_graph_t g, const double* H, int32_t k,
+                            void* grad, hipStream_t stream);
+
+/* ---- diagnostics ------------------------------------------------------ */
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* sfairsc_last_error(void);
+
+/* Library version string. */
+const char* sfairsc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFAIRSC_H */

@@ -1,0 +1,270 @@
+"""s-FairSC on AMD MI355X: Python binding of the HIP library libsfairsc.so.
+
+Scalable fair spectral clustering (Wang, Lu, Davidson and Bai, AISTATS 2023):
+the k smallest eigenpairs of the graph Laplacian restricted to the nullspace
+of the group-fairness constraint F^T (Alg. 3), computed with the deflated
+operator L^sigma = P (L_n - sigma I) P + sigma I (eq. asigma) inside a block
+Krylov-Schur eigensolver, then k-means on the rows of H.
+
+This module only marshals arguments (torch tensors -> device pointers and
+the current HIP stream); all arithmetic runs in the library's kernels.  It
+raises ImportError when the library is missing; there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    E_ARG,
+    E_ASYM,
+    E_EMPTY_GROUP,
+    E_HIP,
+    E_ISOLATED,
+    E_NOMEM,
+    E_NOT_CONVERGED,
+    OK,
+    PREC_FP64,
+    PREC_MIXED,
+    SfairscError,
+)
+
+__all__ = [
+    "Graph",
+    "EigsResult",
+    "FairEigSum",
+    "SfairscError",
+    "version",
+    "PREC_FP64",
+    "PREC_MIXED",
+]
+
+_lib.lib()  # fail loudly at import if the HIP library is missing
+
+
+def version() -> str:
+    return _lib.lib().sfairsc_version().decode()
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(precision) -> int:
+    if precision in ("fp64", PREC_FP64):
+        return PREC_FP64
+    if precision in ("mixed", PREC_MIXED):
+        return PREC_MIXED
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+def _dev(x, dtype, device) -> torch.Tensor:
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device=device, dtype=dtype).contiguous()
+
+
+@dataclass
+class EigsResult:
+    eigenvalues: np.ndarray  # (k,) ascending
+    H: torch.Tensor  # (n, k) float64 on the device (column-major storage)
+    info: dict
+    status: int
+
+
+class Graph:
+    """A graph handle: CSR of W (both triangles), group labels, variant.
+
+    rowptr/col int32, values float32 or float64, groups int32 in [0, h); numpy
+    arrays or torch tensors (copied to the GPU).  normalized selects Alg. 3's
+    normalized Laplacian (True) or the unnormalized variant (False).
+    """
+
+    def __init__(self, rowptr, col, values, groups, h: int, normalized: bool, device="cuda", stream=None):
+        self.device = torch.device(device)
+        rp = _dev(rowptr, torch.int32, self.device)
+        ci = _dev(col, torch.int32, self.device)
+        if isinstance(values, np.ndarray):
+            vdt = torch.float32 if values.dtype == np.float32 else torch.float64
+        else:
+            vdt = values.dtype if values.dtype in (torch.float32, torch.float64) else torch.float64
+        va = _dev(values, vdt, self.device)
+        gr = _dev(groups, torch.int32, self.device)
+        self.n = int(rp.numel() - 1)
+        self.nnz = int(ci.numel())
+        self.h = int(h)
+        self.normalized = bool(normalized)
+        self.value_dtype = vdt
+        self._rowptr, self._col, self._groups = rp, ci, gr
+        handle = ctypes.c_void_p()
+        code = _lib.lib().sfairsc_graph_create(
+            ctypes.byref(handle),
+            self.n,
+            self.nnz,
+            _ptr(rp),
+            _ptr(ci),
+            _ptr(va),
+            _lib.F32 if vdt == torch.float32 else _lib.F64,
+            _ptr(gr),
+            self.h,
+            int(self.normalized),
+            _stream(stream),
+        )
+        _lib.check(code)
+        self._h = handle
+
+    @classmethod
+    def from_msbm(cls, g, normalized: bool, device="cuda"):
+        """From an sfairsc_inputs.MSBMGraph."""
+        return cls(g.rowptr, g.col, g.val, g.groups, g.h, normalized, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().sfairsc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stats(self) -> dict:
+        st = _lib.GraphStats()
+        _lib.check(_lib.lib().sfairsc_graph_query(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
+
+    @property
+    def sigma(self) -> float:
+        return self.stats()["sigma"]
+
+    # -- operator ------------------------------------------------------
+    def apply_operator(self, X: torch.Tensor, precision="fp64", sigma: float = 0.0, stream=None) -> torch.Tensor:
+        """Y = L^sigma X for X (n x b, b <= 32) float64 on the device."""
+        X = X.to(self.device, torch.float64).contiguous()
+        if X.dim() == 1:
+            X = X[:, None]
+        Y = torch.empty_like(X)
+        _lib.check(
+            _lib.lib().sfairsc_apply_operator(
+                self._h, _ptr(X), _ptr(Y), X.shape[1], _prec(precision), float(sigma), _stream(stream)
+            )
+        )
+        return Y
+
+    def spmm(self, X: torch.Tensor, precision="fp64", stream=None) -> torch.Tensor:
+        """T = L X (or L_n X): float32 in and out for 'mixed', float64 for 'fp64'."""
+        dt = torch.float32 if _prec(precision) == PREC_MIXED else torch.float64
+        X = X.to(self.device, dt).contiguous()
+        T = torch.empty_like(X)
+        _lib.check(_lib.lib().sfairsc_spmm(self._h, _ptr(X), _ptr(T), X.shape[1], _prec(precision), _stream(stream)))
+        return T
+
+    # -- eigensolver -----------------------------------------------------
+    def eigs(
+        self,
+        k: int,
+        tol: float = 1e-8,
+        precision="fp64",
+        block_width: int = 0,
+        max_basis: int = 0,
+        max_restarts: int = 0,
+        keep: int = 0,
+        seed: int = 0,
+        sigma: float = 0.0,
+        certify: bool = True,
+        time_kernels: bool = False,
+        x0: Optional[torch.Tensor] = None,
+        H_out: Optional[torch.Tensor] = None,
+        raise_not_converged: bool = True,
+        stream=None,
+    ) -> EigsResult:
+        """The k smallest fair eigenpairs (Alg. 3 step 3)."""
+        opts = _lib.EigsOpts()
+        _lib.lib().sfairsc_eigs_opts_init(ctypes.byref(opts))
+        opts.block_width = block_width
+        opts.max_basis = max_basis
+        opts.max_restarts = max_restarts
+        opts.keep = keep
+        opts.seed = seed
+        opts.sigma = sigma
+        opts.certify = int(certify)
+        opts.time_kernels = int(time_kernels)
+        if x0 is not None:
+            x0 = x0.to(self.device, torch.float64).contiguous()
+            opts.x0 = x0.data_ptr()
+            opts.b0 = x0.shape[1]
+        ev = (ctypes.c_double * k)()
+        if H_out is None:
+            buf = torch.empty((k, self.n), dtype=torch.float64, device=self.device)
+        else:
+            buf = H_out
+        info = _lib.EigsInfo()
+        code = _lib.lib().sfairsc_eigs(
+            self._h, k, float(tol), _prec(precision), ctypes.byref(opts), ev, _ptr(buf), ctypes.byref(info),
+            _stream(stream)
+        )
+        allow = () if raise_not_converged else (E_NOT_CONVERGED,)
+        _lib.check(code, allow=allow)
+        return EigsResult(np.array(ev[:]), buf.t(), info.as_dict(), code)
+
+    # -- clustering ------------------------------------------------------
+    def labels(self, H: torch.Tensor, n_clusters: int, n_restarts: int = 10, seed: int = 0, max_iter: int = 300,
+               stream=None):
+        """k-means on the rows of H (n x kdim) -> (labels int32 tensor, inertia)."""
+        Hc = H.to(self.device, torch.float64).t().contiguous()  # column-major storage
+        lab = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        inertia = ctypes.c_double()
+        _lib.check(
+            _lib.lib().sfairsc_labels(
+                self._h, _ptr(Hc), Hc.shape[0], n_clusters, n_restarts, seed, max_iter, _ptr(lab),
+                ctypes.byref(inertia), _stream(stream)
+            )
+        )
+        return lab, inertia.value
+
+    # -- differentiation -------------------------------------------------
+    def eigsum_backward(self, H: torch.Tensor, stream=None) -> torch.Tensor:
+        """Per stored entry: 0.5 * ||H_i - H_j||^2 (gradient of the sum of the
+        k smallest fair eigenvalues w.r.t. the stored weights)."""
+        Hc = H.to(self.device, torch.float64).t().contiguous()
+        grad = torch.empty(self.nnz, dtype=self.value_dtype, device=self.device)
+        _lib.check(_lib.lib().sfairsc_eigsum_backward(self._h, _ptr(Hc), Hc.shape[0], _ptr(grad), _stream(stream)))
+        return grad
+
+
+class FairEigSum(torch.autograd.Function):
+    """f(w) = sum of the k smallest fair eigenvalues of the unnormalized
+    variant, as a function of the stored edge weights w (CSR order).
+
+    forward(values, rowptr, col, groups, h, k, tol) -> scalar tensor.
+    backward: grad_values = grad_out * 0.5 * ||H_i - H_j||^2 per stored entry
+    (hand-written HIP kernel).  Both stored copies of an edge must receive the
+    same perturbation for the result to be a directional derivative.
+    """
+
+    @staticmethod
+    def forward(ctx, values, rowptr, col, groups, h, k, tol=1e-10):
+        g = Graph(rowptr, col, values.detach(), groups, h, normalized=False, device=values.device)
+        res = g.eigs(k, tol=tol, precision="fp64")
+        ctx.graph = g
+        ctx.save_for_backward(res.H)
+        return torch.tensor(float(res.eigenvalues.sum()), dtype=values.dtype, device=values.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (H,) = ctx.saved_tensors
+        grad = ctx.graph.eigsum_backward(H)
+        return grad_out * grad, None, None, None, None, None, None

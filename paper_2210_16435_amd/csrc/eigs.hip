@@ -1,0 +1,935 @@
+// Block Krylov-Schur (thick-restart block Lanczos) for the k smallest
+// eigenpairs of L^sigma (Alg. 3 step 3; the paper calls ARPACK through
+// MATLAB's eigs and needs only products with L^sigma, Section 3.4 (i)).
+//
+// Basis layout: V is n x ld, row-major (row i holds V[i, 0:ld]).  At any time
+// columns [0, c) are the "complete" basis with Rayleigh quotient T_c (device,
+// ld x ld row-major), columns [c, c+b) the next block V_next, and
+//     L^sigma V[:, 0:c] = V[:, 0:c] T_c + V_next R E^T
+// where R (b x b) couples V_next to the last block of the complete basis
+// (E selects it).  One expansion:
+//     Y = L^sigma V_next                 (operator, into columns [c+b, c+2b))
+//     H1 = V^T Y,  Y -= V H1             (classical Gram-Schmidt ...
+//     H2 = V^T Y,  Y -= V H2             ... twice), V = V[:, 0:c+b]
+//     T[0:c+b, c:c+b] = H1 + H2 (and its mirror)
+//     Y = Q R via Cholesky-QR twice      (Gram Y^T Y -> R1, Y R1^{-1}, again)
+// Row-major storage lets every tall-skinny product read each basis row once,
+// contiguously.  After ncv columns: Rayleigh-Ritz on T_c (host, FP64), the
+// residual of Ritz pair i is ||R Z[c-b:c, i]||, and the p smallest Ritz
+// vectors are kept (V <- V Z[:, 0:p]) with T_p = diag(theta).
+//
+// Reductions are two-stage with a fixed combination order: bitwise
+// reproducible results.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace sfairsc {
+
+constexpr int kTsThreads = 256;
+constexpr int kTsRows = 8;
+constexpr int kTsAcc = (kLdMax * kMaxBlock + kTsThreads - 1) / kTsThreads;  // 28
+constexpr int kTsMaxBlocks = 512;
+constexpr int kRotRows = 16;
+constexpr int kStatBlocks = 256;
+constexpr int kStatsDoubles = kStatBlocks * 2 * kMaxK;
+constexpr int kStatsIdx = kStatBlocks * kMaxK;
+
+enum { TS_GRAM = 0, TS_UPD_GRAM = 1, TS_UPD_SYRK = 2, TS_MUL_SYRK = 3, TS_MUL = 4 };
+
+// Tall-skinny kernel over row tiles.  Y = V[:, yoff : yoff+b].
+//   TS_GRAM      part = V[:, 0:cv]^T Y
+//   TS_UPD_GRAM  Y -= V[:, 0:cv] M (M: cv x b); part = V[:, 0:cv]^T Y
+//   TS_UPD_SYRK  Y -= V[:, 0:cv] M;             part = Y^T Y
+//   TS_MUL_SYRK  Y  = Y M (M: b x b);           part = Y^T Y
+//   TS_MUL       Y  = Y M
+// part[block][o] with o = j * Qd + q (Qd = cv for Gram, b for Syrk).
+template <int MODE>
+__global__ __launch_bounds__(kTsThreads) void k_ts(double* __restrict__ V, int ldv, int64_t n, int cv, int yoff,
+                                                    int b, const double* __restrict__ M, double* __restrict__ part,
+                                                    const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ double lds[];
+    constexpr bool kUseV = (MODE == TS_GRAM || MODE == TS_UPD_GRAM || MODE == TS_UPD_SYRK);
+    constexpr bool kUpd = (MODE == TS_UPD_GRAM || MODE == TS_UPD_SYRK);
+    constexpr bool kMul = (MODE == TS_MUL_SYRK || MODE == TS_MUL);
+    constexpr bool kGramOut = (MODE == TS_GRAM || MODE == TS_UPD_GRAM);
+    constexpr bool kSyrkOut = (MODE == TS_UPD_SYRK || MODE == TS_MUL_SYRK);
+    const int cvu = kUseV ? cv : 0;
+    const int W = cvu + b;
+    double* Vs = lds;                         // [kTsRows][W]
+    double* Ms = Vs + kTsRows * W;            // [b][b] (multiply modes)
+    const int msz = kMul ? b * b : 0;
+    double* Yn = Ms + msz;                    // [kTsRows][b]
+    const int tid = threadIdx.x;
+    for (int o = tid; o < msz; o += kTsThreads) Ms[o] = M[o];
+
+    const int Qd = kGramOut ? cv : b;
+    const int O = kGramOut ? cv * b : (kSyrkOut ? b * b : 0);
+    double acc[kTsAcc];
+#pragma unroll
+    for (int u = 0; u < kTsAcc; ++u) acc[u] = 0.0;
+
+    const int64_t ntiles = (n + kTsRows - 1) / kTsRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kTsRows;
+        const int rows = (int)min<int64_t>(kTsRows, n - r0);
+        __syncthreads();  // previous tile's readers are done (and Ms loaded)
+        for (int idx = tid; idx < rows * W; idx += kTsThreads) {
+            int r = idx / W, c = idx - r * W;
+            int src = c < cvu ? c : yoff + (c - cvu);
+            Vs[r * W + c] = V[(r0 + r) * ldv + src];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < rows * b; idx += kTsThreads) {
+            int r = idx / b, j = idx - r * b;
+            const double* vr = Vs + r * W;
+            double y;
+            if (kUpd) {
+                y = vr[cvu + j];
+                for (int q = 0; q < cv; ++q) y -= vr[q] * M[q * b + j];
+            } else if (kMul) {
+                y = 0.0;
+                for (int q = 0; q < b; ++q) y += vr[q] * Ms[q * b + j];
+            } else {
+                y = vr[cvu + j];
+            }
+            Yn[r * b + j] = y;
+            if (kUpd || kMul) V[(r0 + r) * ldv + yoff + j] = y;
+        }
+        __syncthreads();
+        if (kGramOut || kSyrkOut) {
+#pragma unroll
+            for (int u = 0; u < kTsAcc; ++u) {
+                const int o = tid + u * kTsThreads;
+                if (o < O) {
+                    const int j = o / Qd, q = o - j * Qd;
+                    double s = acc[u];
+                    for (int r = 0; r < rows; ++r) {
+                        const double a = kGramOut ? Vs[r * W + q] : Yn[r * b + q];
+                        s += a * Yn[r * b + j];
+                    }
+                    acc[u] = s;
+                }
+            }
+        }
+    }
+    if (kGramOut || kSyrkOut) {
+#pragma unroll
+        for (int u = 0; u < kTsAcc; ++u) {
+            const int o = tid + u * kTsThreads;
+            if (o < O) part[(size_t)blockIdx.x * O + o] = acc[u];
+        }
+    }
+}
+
+// Sum Gram partials over blocks (fixed order).  H (cv x b, row-major) gets
+// the sum; T[q, cact + j] is set (accumulate = 0) or incremented, and for
+// q < cact so is the mirror T[cact + j, q].
+__global__ void k_gram_reduce(const double* __restrict__ part, int nblk, int cv, int b, double* __restrict__ H,
+                              double* __restrict__ T, int ldt, int cact, int accumulate, const int* skip) {
+    if (skip && *skip) return;
+    const int O = cv * b;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= O) return;
+    double s = 0.0;
+    for (int blk = 0; blk < nblk; ++blk) s += part[(size_t)blk * O + o];
+    const int j = o / cv, q = o - j * cv;
+    H[q * b + j] = s;
+    if (!T) return;
+    double* t1 = T + (size_t)q * ldt + cact + j;
+    *t1 = accumulate ? *t1 + s : s;
+    if (q < cact) {
+        double* t2 = T + (size_t)(cact + j) * ldt + q;
+        *t2 = accumulate ? *t2 + s : s;
+    }
+}
+
+// Cholesky of the b x b Gram G = Y^T Y (sum of partials), G = R^T R with R
+// upper triangular; Rinv = R^{-1}.  pass 1: pivots below `thresh` flag a
+// rank-deficient block (flag[0] = 1, flag[1] = cact) and G is saved.
+// pass 2: R = R2 R1 becomes the coupling (Rc) and the diagonal block of T
+// is symmetrised.
+__global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ part, int nblk, int b, int pass,
+                                                double thresh, double* __restrict__ Gsave,
+                                                double* __restrict__ R1, double* __restrict__ Rinv,
+                                                double* __restrict__ Rc, double* __restrict__ T, int ldt, int cact,
+                                                int* flag, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[1024];
+    __shared__ double G[kMaxBlock * kMaxBlock];
+    __shared__ double R[kMaxBlock * kMaxBlock];
+    __shared__ int bad;
+    const int O = b * b;
+    const int P = 1024 / O;
+    const int t = threadIdx.x;
+    {
+        const int o = t % O, sub = t / O;
+        double s = 0.0;
+        if (sub < P)
+            for (int blk = sub; blk < nblk; blk += P) s += part[(size_t)blk * O + o];
+        red[t] = s;
+    }
+    if (t == 0) bad = 0;
+    __syncthreads();
+    if (t < O) {
+        double tot = 0.0;
+        for (int q = 0; q < P; ++q) tot += red[q * O + t];
+        // partial index o = j * b + q  ->  G[q][j]
+        const int j = t / b, q = t - j * b;
+        G[q * b + j] = tot;
+        R[t] = 0.0;
+    }
+    __syncthreads();
+    if (pass == 1 && t < O) Gsave[t] = G[t];
+    for (int k = 0; k < b; ++k) {
+        if (t == 0) {
+            double piv = G[k * b + k];
+            if (!(piv > thresh)) {
+                bad = 1;
+                piv = 1.0;
+            }
+            R[k * b + k] = sqrt(piv);
+        }
+        __syncthreads();
+        if (t > k && t < b) R[k * b + t] = G[k * b + t] / R[k * b + k];
+        __syncthreads();
+        for (int idx = t; idx < b * b; idx += blockDim.x) {
+            const int i = idx / b, j = idx - i * b;
+            if (i > k && j >= i) {
+                G[i * b + j] -= R[k * b + i] * R[k * b + j];
+                G[j * b + i] = G[i * b + j];
+            }
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (t == 0) {
+            flag[0] = 1;
+            flag[1] = cact;
+        }
+        return;
+    }
+    if (t < b) {
+        const int j = t;  // column j of R^{-1} by back substitution
+        double x[kMaxBlock];
+        for (int i = b - 1; i >= 0; --i) {
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int q = i + 1; q <= j; ++q) s -= R[i * b + q] * x[q];
+            x[i] = (i <= j) ? s / R[i * b + i] : 0.0;
+        }
+        for (int i = 0; i < b; ++i) Rinv[i * b + j] = i <= j ? x[i] : 0.0;
+    }
+    if (pass == 1) {
+        if (t < O) R1[t] = R[t];
+    } else {
+        if (t < O) {
+            const int i = t / b, j = t - i * b;
+            double s = 0.0;
+            for (int q = i; q <= j; ++q) s += R[i * b + q] * R1[q * b + j];
+            Rc[t] = (j >= i) ? s : 0.0;
+            if (j > i && T) {
+                double* a = T + (size_t)(cact + i) * ldt + cact + j;
+                double* c = T + (size_t)(cact + j) * ldt + cact + i;
+                const double m = 0.5 * (*a + *c);
+                *a = m;
+                *c = m;
+            }
+        }
+    }
+}
+
+// Rows: out = V[:, 0:c] Q (Q: c x p row-major).  mode 0 (restart, in place):
+// V[:, 0:p] = out and V[:, p:p+b] = old V[:, c:c+b].  mode 1: out written to
+// Xo row-major with leading dimension ldo (optional row scale).
+__global__ __launch_bounds__(256) void k_rotate(double* __restrict__ V, int ldv, int64_t n, int c, int p, int b,
+                                                 const double* __restrict__ Q, int mode, double* __restrict__ Xo,
+                                                 int ldo, const double* __restrict__ scale) {
+    extern __shared__ double Vs[];  // [kRotRows][c + b]
+    const int W = c + b;
+    const int64_t ntiles = (n + kRotRows - 1) / kRotRows;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * kRotRows;
+        const int rows = (int)min<int64_t>(kRotRows, n - r0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < rows * W; idx += blockDim.x) {
+            int r = idx / W, cc = idx - r * W;
+            Vs[r * W + cc] = V[(r0 + r) * ldv + cc];
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < p; q += blockDim.x) {
+            double acc[kRotRows];
+#pragma unroll
+            for (int r = 0; r < kRotRows; ++r) acc[r] = 0.0;
+            for (int t = 0; t < c; ++t) {
+                const double z = Q[t * p + q];
+#pragma unroll
+                for (int r = 0; r < kRotRows; ++r) acc[r] += Vs[r * W + t] * z;
+            }
+            for (int r = 0; r < rows; ++r) {
+                if (mode == 0)
+                    V[(r0 + r) * ldv + q] = acc[r];
+                else
+                    Xo[(r0 + r) * ldo + q] = scale ? acc[r] * scale[r0 + r] : acc[r];
+            }
+        }
+        if (mode == 0)
+            for (int idx = threadIdx.x; idx < rows * b; idx += blockDim.x) {
+                int r = idx / b, j = idx - r * b;
+                V[(r0 + r) * ldv + p + j] = Vs[r * W + c + j];
+            }
+    }
+}
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Uniform(-1, 1) entries for V[:, c0 : c0 + nc] from a counter-based hash.
+__global__ void k_random(double* __restrict__ V, int ldv, int64_t n, int c0, int nc, uint64_t seed, uint64_t salt) {
+    const int64_t total = n * nc;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / nc;
+        int j = (int)(idx - i * nc);
+        uint64_t z = mix64(seed + 0x9E3779B97F4A7C15ull * (uint64_t)(salt * 0x100000001ull + (uint64_t)idx + 1));
+        V[i * ldv + c0 + j] = ((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+    }
+}
+
+// Copy a row-major n x b0 block into V[:, c0 : c0 + b0].
+__global__ void k_copy_in(const double* __restrict__ X, int b0, double* __restrict__ V, int ldv, int64_t n, int c0) {
+    const int64_t total = n * b0;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / b0;
+        int j = (int)(idx - i * b0);
+        V[i * ldv + c0 + j] = X[idx];
+    }
+}
+
+// T[0:p, 0:p] = diag(theta).
+__global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta) {
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * p; idx += gridDim.x * blockDim.x) {
+        int i = idx / p, j = idx - i * p;
+        T[i * ldt + j] = i == j ? theta[i] : 0.0;
+    }
+}
+
+// Per-block partial column sums of squares of (Y - X diag(theta)), and of
+// |X| maxima with their row for the sign convention.  part: [blk][2][k],
+// imax: [blk][k].
+__global__ __launch_bounds__(256) void k_col_stats(const double* __restrict__ X, const double* __restrict__ Y,
+                                                    int ld, int64_t n, int k, const double* __restrict__ theta,
+                                                    double* __restrict__ part, int64_t* __restrict__ imax) {
+    __shared__ double ss[256];
+    __shared__ double mx[256];
+    __shared__ int64_t mi[256];
+    for (int j = 0; j < k; ++j) {
+        double s = 0.0, m = -1.0;
+        int64_t at = INT64_MAX;
+        const double th = theta ? theta[j] : 0.0;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+            const double x = X[i * ld + j];
+            if (Y) {
+                const double r = Y[i * ld + j] - th * x;
+                s += r * r;
+            }
+            const double a = fabs(x);
+            if (a > m) {
+                m = a;
+                at = i;
+            }
+        }
+        ss[threadIdx.x] = s;
+        mx[threadIdx.x] = m;
+        mi[threadIdx.x] = at;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                ss[threadIdx.x] += ss[threadIdx.x + w];
+                const double m2 = mx[threadIdx.x + w];
+                const int64_t i2 = mi[threadIdx.x + w];
+                if (m2 > mx[threadIdx.x] || (m2 == mx[threadIdx.x] && i2 < mi[threadIdx.x])) {
+                    mx[threadIdx.x] = m2;
+                    mi[threadIdx.x] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[(size_t)blockIdx.x * 2 * k + j] = ss[0];
+            part[(size_t)blockIdx.x * 2 * k + k + j] = mx[0];
+            imax[(size_t)blockIdx.x * k + j] = mi[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Column-major output H[:, j] = sign_j * X[:, j] (row-major X, ld).
+__global__ void k_write_out(const double* __restrict__ X, int ld, int64_t n, int k, const double* __restrict__ sgn,
+                            double* __restrict__ H) {
+    const int64_t total = n * k;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int j = (int)(idx / n);
+        int64_t i = idx - (int64_t)j * n;
+        H[idx] = sgn[j] * X[i * ld + j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace {
+
+int grid_for(int64_t work, int per, int cap) {
+    int64_t g = (work + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+struct Solver {
+    sfairsc_graph* g;
+    hipStream_t s;
+    int64_t n;
+    int b, ncv, ld, k;
+    bool mixed;
+    double sigma;
+    double* V;
+    double* T;
+    double* part;
+    int nblk;
+    // small device buffers
+    double *H1, *H2, *Gsave, *R1, *Rinv, *Rc, *theta, *Q, *stats;
+    int64_t* imax;
+    int* flag;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> evs;
+    size_t ev_used = 0;
+    sfairsc_eigs_info* info = nullptr;
+    double thresh = 0.0;
+
+    int setup() {
+        EigWork& w = g->eig;
+        ld = ncv + b;
+        SF_TRY(w.V.ensure((size_t)n * ld * sizeof(double)));
+        SF_TRY(w.T.ensure((size_t)ld * ld * sizeof(double)));
+        nblk = grid_for(n, kTsRows, kTsMaxBlocks);
+        SF_TRY(w.part.ensure((size_t)nblk * (size_t)ld * kMaxBlock * sizeof(double)));
+        const size_t smallsz = 2 * (size_t)kLdMax * kMaxBlock + 5 * (size_t)kMaxBlock * kMaxBlock + kLdMax +
+                               kStatsDoubles + kStatsIdx + 64;
+        SF_TRY(w.small.ensure(smallsz * sizeof(double)));
+        SF_TRY(w.Q.ensure((size_t)kLdMax * kLdMax * sizeof(double)));
+        V = w.V.as<double>();
+        T = w.T.as<double>();
+        part = w.part.as<double>();
+        double* sp = w.small.as<double>();
+        H1 = sp;
+        sp += kLdMax * kMaxBlock;
+        H2 = sp;
+        sp += kLdMax * kMaxBlock;
+        Gsave = sp;
+        sp += kMaxBlock * kMaxBlock;
+        R1 = sp;
+        sp += kMaxBlock * kMaxBlock;
+        Rinv = sp;
+        sp += kMaxBlock * kMaxBlock;
+        Rc = sp;
+        sp += kMaxBlock * kMaxBlock;
+        theta = sp;
+        sp += kLdMax;
+        stats = sp;
+        sp += kStatsDoubles;
+        imax = reinterpret_cast<int64_t*>(sp);
+        sp += kStatsIdx;
+        flag = reinterpret_cast<int*>(sp);
+        sp += 8;
+        ident = nullptr;
+        Q = w.Q.as<double>();
+        SF_HIP(hipMemsetAsync(flag, 0, 8 * sizeof(int), s));
+        SF_HIP(hipMemsetAsync(T, 0, (size_t)ld * ld * sizeof(double), s));
+        return SFAIRSC_OK;
+    }
+
+    size_t ts_lds(int mode, int cv) const {
+        const bool useV = mode <= TS_UPD_SYRK;
+        const int W = (useV ? cv : 0) + b;
+        int msz = mode >= TS_MUL_SYRK ? b * b : 0;
+        return (size_t)(kTsRows * W + msz + kTsRows * b) * sizeof(double);
+    }
+
+    int ts(int mode, int cv, int yoff, const double* M) {
+        const size_t lds = ts_lds(mode, cv);
+        switch (mode) {
+            case TS_GRAM:
+                k_ts<TS_GRAM><<<nblk, kTsThreads, lds, s>>>(V, ld, n, cv, yoff, b, M, part, flag);
+                break;
+            case TS_UPD_GRAM:
+                k_ts<TS_UPD_GRAM><<<nblk, kTsThreads, lds, s>>>(V, ld, n, cv, yoff, b, M, part, flag);
+                break;
+            case TS_UPD_SYRK:
+                k_ts<TS_UPD_SYRK><<<nblk, kTsThreads, lds, s>>>(V, ld, n, cv, yoff, b, M, part, flag);
+                break;
+            case TS_MUL_SYRK:
+                k_ts<TS_MUL_SYRK><<<nblk, kTsThreads, lds, s>>>(V, ld, n, cv, yoff, b, M, part, flag);
+                break;
+            default:
+                k_ts<TS_MUL><<<nblk, kTsThreads, lds, s>>>(V, ld, n, cv, yoff, b, M, part, flag);
+                break;
+        }
+        SF_HIP(hipGetLastError());
+        return SFAIRSC_OK;
+    }
+
+    // CGS2 of Y = V[:, cv : cv+b] against V[:, 0:cv] writing the projection
+    // coefficients into T's column block starting at column cact (when
+    // cact >= 0), then Cholesky-QR twice.  Afterwards V[:, cv:cv+b] is the
+    // orthonormal block and Rc its coupling.
+    int orthonormalize(int cv, int cact) {
+        const int yoff = cv;
+        if (cv > 0) {
+            SF_TRY(ts(TS_GRAM, cv, yoff, nullptr));
+            const int O = cv * b;
+            double* Tw = cact >= 0 ? T : nullptr;
+            k_gram_reduce<<<grid_for(O, 256, 1 << 20), 256, 0, s>>>(part, nblk, cv, b, H1, Tw, ld,
+                                                                  cact >= 0 ? cact : 0, 0, flag);
+            SF_TRY(ts(TS_UPD_GRAM, cv, yoff, H1));
+            k_gram_reduce<<<grid_for(O, 256, 1 << 20), 256, 0, s>>>(part, nblk, cv, b, H2, Tw, ld,
+                                                                  cact >= 0 ? cact : 0, 1, flag);
+            SF_TRY(ts(TS_UPD_SYRK, cv, yoff, H2));
+        } else {
+            SF_TRY(ts(TS_MUL_SYRK, 0, yoff, identity()));
+        }
+        double* Tc = cact >= 0 ? T : nullptr;
+        k_chol<<<1, 1024, 0, s>>>(part, nblk, b, 1, thresh, Gsave, R1, Rinv, Rc, Tc, ld, cact >= 0 ? cact : 0, flag,
+                                  flag);
+        SF_TRY(ts(TS_MUL_SYRK, 0, yoff, Rinv));
+        k_chol<<<1, 1024, 0, s>>>(part, nblk, b, 2, 0.25, Gsave, R1, Rinv, Rc, Tc, ld,
+                                  cact >= 0 ? cact : 0, flag, flag);
+        SF_TRY(ts(TS_MUL, 0, yoff, Rinv));
+        SF_HIP(hipGetLastError());
+        return SFAIRSC_OK;
+    }
+
+    double* ident = nullptr;
+    const double* identity() {
+        if (!ident) {
+            ident = Q + (size_t)kLdMax * kLdMax - kMaxBlock * kMaxBlock;  // tail of Q, never used by rotations here
+            std::vector<double> I(b * b, 0.0);
+            for (int i = 0; i < b; ++i) I[i * b + i] = 1.0;
+            (void)hipMemcpyAsync(ident, I.data(), b * b * sizeof(double), hipMemcpyHostToDevice, s);
+            (void)hipStreamSynchronize(s);
+        }
+        return ident;
+    }
+
+    int apply(const double* X, int ldx, double* Y, int ldy, int bb) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            if (ev_used + 2 > evs.size()) {
+                for (int i = 0; i < 256; ++i) {
+                    hipEvent_t e;
+                    SF_HIP(hipEventCreate(&e));
+                    evs.push_back(e);
+                }
+            }
+            e0 = evs[ev_used++];
+            e1 = evs[ev_used++];
+        }
+        SF_TRY(op_apply(g, X, ldx, Y, ldy, bb, mixed, sigma, s, e0, e1, flag));
+        if (info) {
+            info->operator_applies += bb;
+            info->spmm_launches[mixed ? 1 : 0] += 1;
+        }
+        return SFAIRSC_OK;
+    }
+
+    // Sum the elapsed times of recorded SpMM event pairs (stream synced).
+    int harvest_timing() {
+        if (!timing || !info) return SFAIRSC_OK;
+        double tot = 0.0;
+        for (size_t i = 0; i + 1 < ev_used; i += 2) {
+            float ms = 0.f;
+            SF_HIP(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+            tot += ms;
+        }
+        info->spmm_ms[mixed ? 1 : 0] += tot;
+        ev_used = 0;
+        return SFAIRSC_OK;
+    }
+
+    ~Solver() {
+        for (auto e : evs) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+// Repair a rank-deficient residual block found at expansion cact (host
+// driven; rare).  Rotates Y onto the eigenvectors of its Gram matrix, keeps
+// the directions of significant norm, replaces the others by random vectors,
+// orthonormalises again and rebuilds the coupling R = Rnew diag(keep) U^T.
+static int repair_block(Solver& S, int cact, uint64_t seed, int attempt) {
+    const int b = S.b;
+    const int cv = cact + b;
+    std::vector<double> G(b * b), U(b * b), w(b);
+    SF_HIP(hipMemcpyAsync(G.data(), S.Gsave, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
+    SF_HIP(hipStreamSynchronize(S.s));
+    sym_eig(b, G.data(), w.data(), U.data());
+    // Y <- Y U, deficient columns -> random
+    SF_HIP(hipMemcpyAsync(S.Q, U.data(), b * b * sizeof(double), hipMemcpyHostToDevice, S.s));
+    int zero = 0;
+    SF_HIP(hipMemcpyAsync(S.flag, &zero, sizeof(int), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.ts(TS_MUL, 0, cv, S.Q));
+    std::vector<int> keep(b, 0);
+    for (int j = 0; j < b; ++j) {
+        keep[j] = w[j] > S.thresh * 1e4;
+        if (!keep[j]) k_random<<<grid_for(S.n, 256, 4096), 256, 0, S.s>>>(S.V, S.ld, S.n, cv + j, 1, seed,
+                                                                             1000003ull * (attempt + 1) + j);
+    }
+    SF_HIP(hipGetLastError());
+    // Orthogonalize again; the T column block of V_next already holds its
+    // projection coefficients, so do not touch T (cact = -1 path writes into
+    // scratch rows beyond the basis).
+    SF_TRY(S.orthonormalize(cv, -1));
+    int hflag[2];
+    SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
+    std::vector<double> Rn(b * b);
+    SF_HIP(hipMemcpyAsync(Rn.data(), S.Rc, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
+    SF_HIP(hipStreamSynchronize(S.s));
+    if (hflag[0]) return set_error(SFAIRSC_E_HIP, "could not repair a rank-deficient Krylov block");
+    // Y_old = Y_rot U^T,  Y_rot[:, j] = Qnew Rn[:, j] for kept j, 0 otherwise
+    std::vector<double> Rc(b * b, 0.0);
+    for (int i = 0; i < b; ++i)
+        for (int j = 0; j < b; ++j) {
+            double sacc = 0.0;
+            for (int t = 0; t < b; ++t)
+                if (keep[t]) sacc += Rn[i * b + t] * U[j * b + t];
+            Rc[i * b + j] = sacc;
+        }
+    SF_HIP(hipMemcpyAsync(S.Rc, Rc.data(), b * b * sizeof(double), hipMemcpyHostToDevice, S.s));
+    // symmetrise T's diagonal block of V_next (normally done by the second
+    // Cholesky pass of the expansion)
+    std::vector<double> Tb(b * S.ld);
+    SF_HIP(hipMemcpyAsync(Tb.data(), S.T + (size_t)cact * S.ld, b * S.ld * sizeof(double), hipMemcpyDeviceToHost,
+                          S.s));
+    SF_HIP(hipStreamSynchronize(S.s));
+    for (int i = 0; i < b; ++i)
+        for (int j = i + 1; j < b; ++j) {
+            double m = 0.5 * (Tb[i * S.ld + cact + j] + Tb[j * S.ld + cact + i]);
+            Tb[i * S.ld + cact + j] = m;
+            Tb[j * S.ld + cact + i] = m;
+        }
+    SF_HIP(hipMemcpyAsync(S.T + (size_t)cact * S.ld, Tb.data(), b * S.ld * sizeof(double), hipMemcpyHostToDevice,
+                          S.s));
+    if (S.info) S.info->breakdowns += 1;
+    return SFAIRSC_OK;
+}
+
+struct KsResult {
+    std::vector<double> theta;  // Ritz values of the last Rayleigh-Ritz
+    std::vector<double> res;    // residual estimates
+    std::vector<double> Z;      // c x c eigenvectors (row-major)
+    int c = 0;
+    bool converged = false;
+};
+
+// One Krylov-Schur run.  On return the basis V and KsResult describe the
+// final Rayleigh-Ritz: Ritz vectors = V[:, 0:c] Z[:, i].
+static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const double* x0, int b0, uint64_t seed,
+                  KsResult& out) {
+    const int b = S.b, ncv = S.ncv, k = S.k;
+    const int64_t n = S.n;
+    SF_TRY(S.setup());
+    // start block
+    int c = 0;
+    if (x0 && b0 > 0) k_copy_in<<<grid_for(n * b0, 256, 8192), 256, 0, S.s>>>(x0, b0, S.V, S.ld, n, 0);
+    if (b0 < b) k_random<<<grid_for(n * (b - b0), 256, 8192), 256, 0, S.s>>>(S.V, S.ld, n, b0, b - b0, seed, 0);
+    SF_HIP(hipGetLastError());
+    // A random start vector is not orthogonal to range(C) or to the trivial
+    // vector: harmless, the operator treats every direction exactly.
+    SF_TRY(S.orthonormalize(0, -1));
+    {
+        int hflag[2];
+        SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
+        SF_HIP(hipStreamSynchronize(S.s));
+        if (hflag[0]) return set_error(SFAIRSC_E_ARG, "start block is rank deficient");
+    }
+    int repairs = 0;
+    std::vector<double> hT, Z, w, Rc(b * b);
+    for (int restart = 0;; ++restart) {
+        // expansions
+        while (c + b <= ncv) {
+            SF_TRY(S.apply(S.V + c, S.ld, S.V + c + b, S.ld, b));
+            SF_TRY(S.orthonormalize(c + b, c));
+            if (S.info) S.info->block_steps += 1;
+            c += b;
+        }
+        int hflag[2];
+        SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
+        SF_HIP(hipStreamSynchronize(S.s));
+        SF_TRY(S.harvest_timing());
+        if (hflag[0]) {
+            // everything after the failed expansion at hflag[1] was skipped
+            const int cact = hflag[1];
+            if (++repairs > 64) return set_error(SFAIRSC_E_HIP, "too many Krylov breakdowns");
+            SF_TRY(repair_block(S, cact, seed, repairs));
+            c = cact + b;
+            if (S.info) S.info->block_steps += 1;
+            continue;
+        }
+        // Rayleigh-Ritz on T_c
+        hT.resize((size_t)c * c);
+        SF_HIP(hipMemcpy2DAsync(hT.data(), c * sizeof(double), S.T, S.ld * sizeof(double), c * sizeof(double), c,
+                                hipMemcpyDeviceToHost, S.s));
+        SF_HIP(hipMemcpyAsync(Rc.data(), S.Rc, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
+        SF_HIP(hipStreamSynchronize(S.s));
+        for (int i = 0; i < c; ++i)
+            for (int j = i + 1; j < c; ++j) {
+                double m = 0.5 * (hT[i * c + j] + hT[j * c + i]);
+                hT[i * c + j] = m;
+                hT[j * c + i] = m;
+            }
+        w.resize(c);
+        Z.resize((size_t)c * c);
+        sym_eig(c, hT.data(), w.data(), Z.data());
+        std::vector<double> res(c);
+        for (int i = 0; i < c; ++i) {
+            double ss = 0.0;
+            for (int r = 0; r < b; ++r) {
+                double acc = 0.0;
+                for (int q = r; q < b; ++q) acc += Rc[r * b + q] * Z[(size_t)(c - b + q) * c + i];
+                ss += acc * acc;
+            }
+            res[i] = std::sqrt(ss);
+        }
+        int nconv = 0;
+        for (int i = 0; i < k; ++i)
+            if (res[i] <= tol * S.sigma) ++nconv;
+        if (S.info) {
+            S.info->restarts = restart + 1;
+            S.info->converged = nconv;
+            S.info->gap_ratio = c > k ? (w[k] - w[k - 1]) / S.sigma : 0.0;
+        }
+        out.theta = w;
+        out.res = res;
+        out.Z = Z;
+        out.c = c;
+        out.converged = nconv == k;
+        if (out.converged || restart + 1 >= max_restarts) return SFAIRSC_OK;
+        // thick restart: keep p Ritz vectors
+        int p = keep_opt > 0 ? keep_opt : std::max(k + b, k + (c - k) / 2);
+        p = std::min(p, ncv - b);
+        p = std::max(p, std::min(k, ncv - b));
+        while (p < ncv - b && p < c && std::fabs(w[p] - w[p - 1]) <= 1e-10 * S.sigma) ++p;
+        std::vector<double> Qp((size_t)c * p);
+        for (int t = 0; t < c; ++t)
+            for (int q = 0; q < p; ++q) Qp[(size_t)t * p + q] = Z[(size_t)t * c + q];
+        SF_HIP(hipMemcpyAsync(S.Q, Qp.data(), Qp.size() * sizeof(double), hipMemcpyHostToDevice, S.s));
+        SF_HIP(hipMemcpyAsync(S.theta, w.data(), p * sizeof(double), hipMemcpyHostToDevice, S.s));
+        k_rotate<<<grid_for(n, kRotRows, 1024), 256, (size_t)kRotRows * (c + b) * sizeof(double), S.s>>>(
+            S.V, S.ld, n, c, p, b, S.Q, 0, nullptr, 0, nullptr);
+        k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.theta);
+        SF_HIP(hipGetLastError());
+        c = p;
+    }
+}
+
+// Ritz vectors X = V[:, 0:c] Z[:, 0:k] (row-major n x k in Xo, ld k).
+static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* scale) {
+    const int c = R.c, k = S.k;
+    std::vector<double> Qk((size_t)c * k);
+    for (int t = 0; t < c; ++t)
+        for (int q = 0; q < k; ++q) Qk[(size_t)t * k + q] = R.Z[(size_t)t * c + q];
+    SF_HIP(hipMemcpyAsync(S.Q, Qk.data(), Qk.size() * sizeof(double), hipMemcpyHostToDevice, S.s));
+    k_rotate<<<grid_for(S.n, kRotRows, 1024), 256, (size_t)kRotRows * (c + S.b) * sizeof(double), S.s>>>(
+        S.V, S.ld, S.n, c, k, S.b, S.Q, 1, Xo, k, scale);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+// FP64 residual norms ||L^sigma x_i - theta_i x_i|| of row-major X (n x k).
+static int certify(Solver& S, const double* X, double* Ybuf, const std::vector<double>& theta,
+                   std::vector<double>& res) {
+    const int k = S.k;
+    const bool was_mixed = S.mixed;
+    S.mixed = false;
+    int zero = 0;
+    SF_HIP(hipMemcpyAsync(S.flag, &zero, sizeof(int), hipMemcpyHostToDevice, S.s));
+    for (int j0 = 0; j0 < k; j0 += kMaxBlock) {
+        int bb = std::min(kMaxBlock, k - j0);
+        SF_TRY(op_apply(S.g, X + j0, k, Ybuf + j0, k, bb, 0, S.sigma, S.s, nullptr, nullptr, nullptr));
+    }
+    S.mixed = was_mixed;
+    SF_HIP(hipMemcpyAsync(S.theta, theta.data(), k * sizeof(double), hipMemcpyHostToDevice, S.s));
+    const int nb = grid_for(S.n, 256, kStatBlocks);
+    k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.theta, S.stats, S.imax);
+    SF_HIP(hipGetLastError());
+    std::vector<double> part((size_t)nb * 2 * k);
+    SF_HIP(hipMemcpyAsync(part.data(), S.stats, part.size() * sizeof(double), hipMemcpyDeviceToHost, S.s));
+    SF_HIP(hipStreamSynchronize(S.s));
+    res.assign(k, 0.0);
+    for (int blk = 0; blk < nb; ++blk)
+        for (int j = 0; j < k; ++j) res[j] += part[(size_t)blk * 2 * k + j];
+    for (int j = 0; j < k; ++j) res[j] = std::sqrt(res[j]);
+    return SFAIRSC_OK;
+}
+
+static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const sfairsc_eigs_opts& o,
+                     double* eigvals, double* H, sfairsc_eigs_info* info, hipStream_t s) {
+    const int64_t n = g->n;
+    const int dim = (int)std::min<int64_t>(n, INT32_MAX);
+    int b = o.block_width;
+    if (b == 0) b = k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+    if (b != 4 && b != 8 && b != 16 && b != 32) return set_error(SFAIRSC_E_ARG, "block width must be 4, 8, 16 or 32");
+    while (b > 4 && 3 * b + k > dim) b /= 2;
+    int ncv = o.max_basis;
+    if (ncv == 0) ncv = std::max(k + 4 * b, 3 * k + 2 * b);
+    ncv = ((ncv + b - 1) / b) * b;
+    ncv = std::min(ncv, kMaxBasis);
+    while (ncv + 2 * b > dim && ncv > b) ncv -= b;
+    if (ncv < k + b || ncv < 2 * b)
+        return set_error(SFAIRSC_E_ARG, "graph too small (n=%lld) for k=%d with block width %d", (long long)n, k, b);
+    if (o.b0 < 0 || o.b0 > b || (o.b0 > 0 && !o.x0)) return set_error(SFAIRSC_E_ARG, "bad warm start");
+
+    Solver S;
+    S.g = g;
+    S.s = s;
+    S.n = n;
+    S.b = b;
+    S.ncv = ncv;
+    S.k = k;
+    S.sigma = o.sigma > 0 ? o.sigma : g->sigma;
+    S.info = info;
+    S.timing = o.time_kernels != 0 && info != nullptr;
+    S.thresh = (1e-10 * S.sigma) * (1e-10 * S.sigma);
+    const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 2000;
+    if (info) info->sigma = S.sigma;
+
+    SF_TRY(g->eig.X.ensure((size_t)n * kMaxK * 2 * sizeof(double)));
+    double* Xr = g->eig.X.as<double>();     // row-major n x k Ritz vectors
+    double* Yr = Xr + (size_t)n * kMaxK;    // operator images for certification
+    const double* scale = g->normalized ? g->cs : nullptr;
+
+    KsResult R;
+    std::vector<double> res;
+    bool ok = false;
+    if (precision == SFAIRSC_PREC_MIXED) {
+        auto t0 = std::chrono::steady_clock::now();
+        S.mixed = true;
+        const double tol1 = std::max(tol, 5e-7);
+        SF_TRY(run_ks(S, tol1, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
+        SF_TRY(ritz_vectors(S, R, Xr, nullptr));
+        std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
+        SF_TRY(certify(S, Xr, Yr, th, res));
+        if (info) info->phase1_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ok = true;
+        for (int i = 0; i < k; ++i) ok = ok && res[i] <= tol * S.sigma;
+        if (!ok) {
+            // continue in FP64 from the float result: the k Ritz vectors seed
+            // the start block (block width at least k)
+            S.mixed = false;
+            const int b2 = std::max(b, k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32);
+            if (b2 != b) {
+                S.b = b2;
+                S.ncv = std::min(kMaxBasis, std::max(ncv, k + 4 * b2));
+                S.ncv = (S.ncv / b2) * b2;
+                while (S.ncv + 2 * b2 > dim && S.ncv > b2) S.ncv -= b2;
+            }
+            // Xr holds the k Ritz vectors, row-major n x k: the start block
+            SF_TRY(run_ks(S, tol, max_restarts, o.keep, Xr, k, o.seed + 1, R));
+            SF_TRY(ritz_vectors(S, R, Xr, nullptr));
+        }
+    } else {
+        S.mixed = false;
+        SF_TRY(run_ks(S, tol, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
+        SF_TRY(ritz_vectors(S, R, Xr, nullptr));
+    }
+    std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
+    if (o.certify || precision == SFAIRSC_PREC_MIXED) {
+        SF_TRY(certify(S, Xr, Yr, th, res));
+    } else {
+        res.assign(R.res.begin(), R.res.begin() + k);
+    }
+    double worst = 0.0;
+    int nconv = 0;
+    for (int i = 0; i < k; ++i) {
+        worst = std::max(worst, res[i] / S.sigma);
+        if (res[i] <= tol * S.sigma) ++nconv;
+    }
+    // sign convention and output H = D^{-1/2} X (normalized) or X
+    if (scale) SF_TRY(ritz_vectors(S, R, Xr, scale));
+    const int nb = grid_for(n, 256, kStatBlocks);
+    k_col_stats<<<nb, 256, 0, s>>>(Xr, nullptr, k, n, k, nullptr, S.stats, S.imax);
+    SF_HIP(hipGetLastError());
+    std::vector<double> part((size_t)nb * 2 * k);
+    std::vector<int64_t> pidx((size_t)nb * k);
+    SF_HIP(hipMemcpyAsync(part.data(), S.stats, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipMemcpyAsync(pidx.data(), S.imax, pidx.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipStreamSynchronize(s));
+    std::vector<double> sgn(k, 1.0);
+    std::vector<double> hx(k, 0.0);
+    std::vector<int64_t> at_row(k, -1);
+    for (int j = 0; j < k; ++j) {
+        double m = -1.0;
+        int64_t at = INT64_MAX;
+        for (int blk = 0; blk < nb; ++blk) {
+            double m2 = part[(size_t)blk * 2 * k + k + j];
+            int64_t i2 = pidx[(size_t)blk * k + j];
+            if (m2 > m || (m2 == m && i2 < at)) {
+                m = m2;
+                at = i2;
+            }
+        }
+        if (at >= 0 && at < n) {
+            at_row[j] = at;
+            SF_HIP(hipMemcpyAsync(&hx[j], Xr + at * k + j, sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+    }
+    SF_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < k; ++j) sgn[j] = (at_row[j] >= 0 && hx[j] < 0) ? -1.0 : 1.0;
+    SF_HIP(hipMemcpyAsync(S.theta, sgn.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, H);
+    SF_HIP(hipGetLastError());
+    SF_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) eigvals[i] = th[i];
+    if (info) {
+        info->max_rel_residual = worst;
+        info->converged = nconv;
+    }
+    if (nconv < k) return set_error(SFAIRSC_E_NOT_CONVERGED, "%d of %d pairs converged (worst rel. residual %.3e)",
+                                    nconv, k, worst);
+    return SFAIRSC_OK;
+}
+
+}  // namespace sfairsc
+
+using namespace sfairsc;
+
+extern "C" void sfairsc_eigs_opts_init(sfairsc_eigs_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->certify = 1;
+}
+
+extern "C" int sfairsc_eigs(sfairsc_graph_t g, int32_t k, double tol, int precision, const sfairsc_eigs_opts* opts,
+                            double* eigvals, double* H, sfairsc_eigs_info* info, hipStream_t stream) {
+    if (!g || !eigvals || !H) return set_error(SFAIRSC_E_ARG, "NULL argument");
+    if (k < 1 || k > kMaxK || k > g->n - g->h + 1) return set_error(SFAIRSC_E_ARG, "k=%d out of range", k);
+    if (!(tol > 0.0) || !(tol < 1.0)) return set_error(SFAIRSC_E_ARG, "tol must lie in (0, 1)");
+    if (precision != SFAIRSC_PREC_FP64 && precision != SFAIRSC_PREC_MIXED)
+        return set_error(SFAIRSC_E_ARG, "unknown precision %d", precision);
+    sfairsc_eigs_opts o;
+    if (opts)
+        o = *opts;
+    else
+        sfairsc_eigs_opts_init(&o);
+    if (info) std::memset(info, 0, sizeof *info);
+    return eigs_impl(g, k, tol, precision, o, eigvals, H, info, stream);
+}

@@ -1,0 +1,119 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sfairsc.h"
+#include "symeig.h"
+
+namespace sfairsc {
+
+// Limits of this build.
+constexpr int kMaxBlock = 32;     // widest block of vectors (columns)
+constexpr int kMaxGroups = 32;    // h
+constexpr int kMaxBasis = 192;    // Krylov basis columns before a restart
+constexpr int kMaxK = 64;         // wanted eigenpairs / k-means dimension
+constexpr int kLdMax = kMaxBasis + kMaxBlock;  // basis leading dimension
+
+int set_error(int code, const char* fmt, ...);
+
+#define SF_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return ::sfairsc::set_error(SFAIRSC_E_HIP, "%s failed: %s", #call, \
+                                        hipGetErrorString(e_));               \
+    } while (0)
+
+#define SF_TRY(expr)              \
+    do {                          \
+        int r_ = (expr);          \
+        if (r_ != SFAIRSC_OK)     \
+            return r_;            \
+    } while (0)
+
+// A device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need);
+    void release();
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Workspace of the operator L^sigma for blocks up to kMaxBlock columns.
+struct OpWork {
+    int nblk_spmm = 0;  // partial-sum slots of the SpMM epilogue
+    int nblk_proj = 0;  // partial-sum slots of the input projection
+    DevBuf part_in;     // [nblk_proj][h][32] double
+    DevBuf part_out;    // [nblk_spmm][h][32] double
+    DevBuf small;       // R_in, S, R_out tables: 3 x [h][32] double
+    DevBuf xp;          // projected input, n x BW (float or double)
+    DevBuf t;           // sparse product output, n x BW (float or double)
+    DevBuf xpad, ypad;  // padding copies for b not in {4, 8, 16, 32}
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+// Workspace of the Krylov-Schur solver.
+struct EigWork {
+    DevBuf V;       // n x ld basis (row-major), double
+    DevBuf T;       // ld x ld projected matrix, double
+    DevBuf part;    // tall-skinny partial sums
+    DevBuf small;   // H1, H2, Gram, R, Rinv, coupling, flags ...
+    DevBuf Q;       // ld x ld restart / rotation matrix
+    DevBuf X;       // n x kMaxK output staging
+    std::vector<double> hostT, hostQ;
+};
+
+struct KmWork {
+    DevBuf d2, cs, cent, lab, best, part, misc;
+};
+
+}  // namespace sfairsc
+
+struct sfairsc_graph {
+    int64_t n = 0, nnz = 0;
+    int h = 1, normalized = 0, value_dtype = SFAIRSC_F64;
+    int device = 0;
+    double sigma = 0.0, dmin = 0.0, dmax = 0.0;
+    int32_t* rowptr = nullptr;  // [n+1]
+    int32_t* col = nullptr;     // [nnz]
+    int32_t* grp = nullptr;     // [n]
+    void* wval = nullptr;       // [nnz] original weights (value dtype)
+    double* val64 = nullptr;    // [nnz] off-diagonal magnitudes: w or w-hat
+    float* val32 = nullptr;     // [nnz] the same rounded to float
+    double* diag64 = nullptr;   // [n] d (unnormalized) or 1 (normalized)
+    float* diag32 = nullptr;    // [n]
+    double* cs = nullptr;       // [n] d^{-1/2} (normalized); nullptr otherwise
+    double* deg = nullptr;      // [n] degrees
+    double* gpar = nullptr;     // device: p[h], Ginv[(h-1)^2]
+    std::vector<int64_t> count; // group sizes
+    std::vector<double> p;      // group fractions |V_s| / n
+    std::vector<double> ginv;   // (C^T C)^{-1}, (h-1) x (h-1)
+    sfairsc::OpWork op;
+    sfairsc::EigWork eig;
+    sfairsc::KmWork km;
+};
+
+namespace sfairsc {
+
+// Apply Y = L^sigma X for X, Y in row-major blocks with leading dimensions.
+// b <= 32.  mixed = float sparse product.  If timing events are given, the
+// SpMM launch is bracketed by them (ev_begin recorded before, ev_end after).
+int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy,
+             int b, int mixed, double sigma, hipStream_t s,
+             hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr,
+             const int* skip_flag = nullptr);
+
+// Raw sparse product T = L X (no projection), X/T compact row-major n x b.
+int op_spmm_raw(sfairsc_graph* g, const void* X, void* T, int b, int mixed,
+                hipStream_t s);
+
+
+}  // namespace sfairsc

@@ -1,0 +1,418 @@
+// k-means on the rows of H (Alg. 3 step 4: "apply k-means clustering to the
+// rows of H").  The paper does not specify the variant; this one is:
+//   * k-means++ seeding (Arthur and Vassilvitskii 2007): first centre row
+//     floor(u n); centre t >= 1 is the first row whose inclusive prefix sum
+//     of D^2 (squared distance to the nearest chosen centre) exceeds u * total
+//     (row floor(u n) when total = 0);
+//   * uniforms u from SplitMix64 (Steele, Lea and Flood 2014): restart r,
+//     draw t uses output number r * 2^32 + t + 1 of the stream seeded with
+//     `seed`, top 53 bits scaled to [0, 1);
+//   * Lloyd: nearest centroid by squared distance (ties: lowest index); stop
+//     when no label changes or after max_iter assignments, else move each
+//     centroid to its rows' mean; an empty cluster takes the row farthest
+//     from its own centroid (ties: lowest row), each row used once;
+//   * best inertia over restarts (ties: earliest), labels renumbered by
+//     first appearance.
+// H is read column-major (n x kdim) so consecutive threads read consecutive
+// rows.  Sums use fixed per-block partials combined in block order.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+
+namespace sfairsc {
+
+namespace {
+
+constexpr int kKmThreads = 256;
+constexpr int kKmMaxBlocks = 1024;
+constexpr int kChunk = 1024;  // rows per prefix-sum chunk in the seeding
+
+uint64_t sm_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double sm_uniform(uint64_t seed, uint64_t restart, uint64_t draw) {
+    const uint64_t idx = (restart << 32) + draw + 1;
+    const uint64_t z = sm_mix(seed + idx * 0x9E3779B97F4A7C15ull);
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+// cent[t] = H[idx]; d2 = (t == 0) ? dist : min(d2, dist) to that centre.
+__global__ __launch_bounds__(kKmThreads) void k_pp_update(const double* __restrict__ H, int64_t n, int kdim,
+                                                          const int64_t* __restrict__ idxp, int t,
+                                                          double* __restrict__ cent, double* __restrict__ d2) {
+    __shared__ double c[kMaxK];
+    const int64_t idx = *idxp;
+    if (threadIdx.x < kdim) c[threadIdx.x] = H[(int64_t)threadIdx.x * n + idx];
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x < kdim) cent[t * kdim + threadIdx.x] = c[threadIdx.x];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int l = 0; l < kdim; ++l) {
+            const double d = H[(int64_t)l * n + i] - c[l];
+            s += d * d;
+        }
+        d2[i] = (t == 0) ? s : fmin(d2[i], s);
+    }
+}
+
+// Chunk sums of d2 (chunk = kChunk rows, one block per chunk, fixed tree).
+__global__ __launch_bounds__(kKmThreads) void k_chunk_sums(const double* __restrict__ d2, int64_t n,
+                                                           double* __restrict__ csum) {
+    __shared__ double red[kKmThreads];
+    const int64_t base = (int64_t)blockIdx.x * kChunk;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < kChunk; q += kKmThreads) {
+        const int64_t i = base + q;
+        if (i < n) s += d2[i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kKmThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) csum[blockIdx.x] = red[0];
+}
+
+// D^2 sampling: index of the first row whose inclusive prefix sum exceeds
+// u * total (total = sum of chunk sums, accumulated in chunk order).
+__global__ void k_pp_pick(const double* __restrict__ d2, const double* __restrict__ csum, int nchunks, int64_t n,
+                          double u, int64_t* __restrict__ idxp) {
+    if (threadIdx.x != 0) return;
+    double total = 0.0;
+    for (int c = 0; c < nchunks; ++c) total += csum[c];
+    int64_t pick = (int64_t)(u * (double)n);
+    if (pick >= n) pick = n - 1;
+    if (total > 0.0) {
+        const double target = u * total;
+        double acc = 0.0;
+        int c = 0;
+        for (; c < nchunks; ++c) {
+            if (acc + csum[c] > target) break;
+            acc += csum[c];
+        }
+        if (c == nchunks) {
+            pick = n - 1;
+        } else {
+            const int64_t base = (int64_t)c * kChunk;
+            int64_t i = base;
+            const int64_t end = min(n, base + kChunk);
+            for (; i < end; ++i) {
+                acc += d2[i];
+                if (acc > target) break;
+            }
+            pick = i < end ? i : end - 1;
+        }
+    }
+    *idxp = pick;
+}
+
+// Assignment: label_i = argmin_j ||H_i - c_j||^2; per-block changed count.
+__global__ __launch_bounds__(kKmThreads) void k_assign(const double* __restrict__ H, int64_t n, int kdim, int K,
+                                                       const double* __restrict__ cent, int32_t* __restrict__ lab,
+                                                       double* __restrict__ mind, int* __restrict__ changed_part,
+                                                       const int* __restrict__ done) {
+    if (*done) return;
+    __shared__ double c[kMaxK * kMaxK];
+    __shared__ int cnt[kKmThreads];
+    for (int o = threadIdx.x; o < K * kdim; o += blockDim.x) c[o] = cent[o];
+    __syncthreads();
+    int changed = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double x[kMaxK];
+        for (int l = 0; l < kdim; ++l) x[l] = H[(int64_t)l * n + i];
+        double best = INFINITY;
+        int bj = 0;
+        for (int j = 0; j < K; ++j) {
+            double s = 0.0;
+            for (int l = 0; l < kdim; ++l) {
+                const double d = x[l] - c[j * kdim + l];
+                s += d * d;
+            }
+            if (s < best) {
+                best = s;
+                bj = j;
+            }
+        }
+        if (lab[i] != bj) ++changed;
+        lab[i] = bj;
+        mind[i] = best;
+    }
+    cnt[threadIdx.x] = changed;
+    __syncthreads();
+    for (int w = kKmThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) changed_part[blockIdx.x] = cnt[0];
+}
+
+// Per-block cluster sums: each wave walks its rows in order; lane l < kdim
+// owns dimension l.  part: [blk][K][kdim], cpart: [blk][K].
+__global__ __launch_bounds__(kKmThreads) void k_cluster_sums(const double* __restrict__ H, int64_t n, int kdim,
+                                                             int K, const int32_t* __restrict__ lab,
+                                                             double* __restrict__ part, int* __restrict__ cpart,
+                                                             const int* __restrict__ done) {
+    if (*done) return;
+    constexpr int kWaves = kKmThreads / 64;
+    extern __shared__ double sh[];  // [kWaves][K][kdim] sums, then [kWaves][K] counts (as double)
+    double* sums = sh;
+    double* cnts = sh + kWaves * K * kdim;
+    for (int o = threadIdx.x; o < kWaves * K * (kdim + 1); o += blockDim.x) sh[o] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t rows_per_block = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    const int64_t per_wave = (r1 - r0 + kWaves - 1) / kWaves;
+    const int64_t w0 = r0 + wave * per_wave, w1 = min(r1, w0 + per_wave);
+    double* ws = sums + wave * K * kdim;
+    for (int64_t i = w0; i < w1; ++i) {
+        const int j = lab[i];
+        if (lane < kdim) ws[j * kdim + lane] += H[(int64_t)lane * n + i];
+        if (lane == 0) cnts[wave * K + j] += 1.0;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < K * kdim; o += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += sums[w * K * kdim + o];
+        part[(size_t)blockIdx.x * K * kdim + o] = s;
+    }
+    for (int o = threadIdx.x; o < K; o += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += cnts[w * K + o];
+        cpart[(size_t)blockIdx.x * K + o] = (int)s;
+    }
+}
+
+// Combine: stop test, centroid means, empty-cluster refill.
+// state[0] = done, state[1] = assignments so far.
+__global__ __launch_bounds__(1024) void k_update(const double* __restrict__ H, int64_t n, int kdim, int K,
+                                                 const int* __restrict__ changed_part, int nb_assign,
+                                                 const double* __restrict__ part, const int* __restrict__ cpart,
+                                                 int nb_sum, const double* __restrict__ mind,
+                                                 double* __restrict__ cent, int* __restrict__ state, int max_iter) {
+    __shared__ int changed;
+    __shared__ int cnt[kMaxK];
+    __shared__ double bestv[1024];
+    __shared__ int64_t besti[1024];
+    __shared__ int64_t used[kMaxK];
+    if (state[0]) return;
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int b = 0; b < nb_assign; ++b) c += changed_part[b];
+        changed = c;
+        state[1] += 1;
+    }
+    __syncthreads();
+    if (changed == 0 || state[1] >= max_iter) {
+        if (threadIdx.x == 0) state[0] = 1;
+        return;
+    }
+    if (threadIdx.x < K) {
+        int c = 0;
+        for (int b = 0; b < nb_sum; ++b) c += cpart[(size_t)b * K + threadIdx.x];
+        cnt[threadIdx.x] = c;
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < K * kdim; o += blockDim.x) {
+        const int j = o / kdim;
+        if (cnt[j] > 0) {
+            double s = 0.0;
+            for (int b = 0; b < nb_sum; ++b) s += part[(size_t)b * K * kdim + o];
+            cent[o] = s / (double)cnt[j];
+        }
+    }
+    __syncthreads();
+    int nused = 0;
+    for (int j = 0; j < K; ++j) {
+        if (cnt[j] > 0) continue;
+        // farthest row from its own centroid among rows not yet used
+        double bv = -1.0;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            bool u = false;
+            for (int q = 0; q < nused; ++q) u = u || used[q] == i;
+            if (u) continue;
+            const double v = mind[i];
+            if (v > bv) {
+                bv = v;
+                bi = i;
+            }
+        }
+        bestv[threadIdx.x] = bv;
+        besti[threadIdx.x] = bi;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+                const double v2 = bestv[threadIdx.x + w];
+                const int64_t i2 = besti[threadIdx.x + w];
+                if (v2 > bestv[threadIdx.x] || (v2 == bestv[threadIdx.x] && i2 < besti[threadIdx.x])) {
+                    bestv[threadIdx.x] = v2;
+                    besti[threadIdx.x] = i2;
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t pick = besti[0];
+        if (threadIdx.x < kdim && pick < n) cent[j * kdim + threadIdx.x] = H[(int64_t)threadIdx.x * n + pick];
+        if (threadIdx.x == 0) used[nused] = pick;
+        ++nused;
+        __syncthreads();
+    }
+}
+
+// Per-block sums of mind (inertia), fixed tree.
+__global__ __launch_bounds__(kKmThreads) void k_sum(const double* __restrict__ v, int64_t n,
+                                                    double* __restrict__ part) {
+    __shared__ double red[kKmThreads];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += v[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kKmThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// first[j] = smallest row with label j (atomicMin: order independent).
+__global__ void k_first(const int32_t* __restrict__ lab, int64_t n, long long* __restrict__ first) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicMin(&first[lab[i]], (long long)i);
+}
+
+__global__ void k_relabel(const int32_t* __restrict__ lab, int64_t n, const int32_t* __restrict__ map,
+                          int32_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = map[lab[i]];
+}
+
+static int grid_n(int64_t n, int cap) {
+    int64_t g = (n + kKmThreads - 1) / kKmThreads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R, uint64_t seed, int max_iter,
+                       int32_t* labels, double* inertia_out, hipStream_t s) {
+    const int64_t n = g->n;
+    KmWork& w = g->km;
+    const int nchunks = (int)((n + kChunk - 1) / kChunk);
+    const int nb = grid_n(n, kKmMaxBlocks);
+    const int nbs = std::max(1, std::min<int>(nb, 256));
+    SF_TRY(w.d2.ensure((size_t)n * sizeof(double)));
+    SF_TRY(w.cs.ensure((size_t)std::max(nchunks, nb) * sizeof(double)));
+    SF_TRY(w.cent.ensure((size_t)K * kdim * sizeof(double)));
+    SF_TRY(w.lab.ensure((size_t)n * sizeof(int32_t)));
+    SF_TRY(w.best.ensure((size_t)n * sizeof(int32_t)));
+    SF_TRY(w.part.ensure((size_t)nbs * K * kdim * sizeof(double)));
+    SF_TRY(w.misc.ensure((size_t)(nb + nbs * K + 64) * sizeof(int) + 64 * sizeof(int64_t)));
+    double* d2 = w.d2.as<double>();  // D^2 during seeding, then min distances
+    double* csum = w.cs.as<double>();
+    double* cent = w.cent.as<double>();
+    int32_t* lab = w.lab.as<int32_t>();
+    int32_t* best = w.best.as<int32_t>();
+    double* part = w.part.as<double>();
+    int64_t* idxp = reinterpret_cast<int64_t*>(w.misc.p);
+    int* state = reinterpret_cast<int*>(idxp + 8);
+    int* changed_part = state + 8;
+    int* cpart = changed_part + nb;
+    const size_t sum_lds = (size_t)(kKmThreads / 64) * K * (kdim + 1) * sizeof(double);
+
+    double best_inertia = INFINITY;
+    std::vector<double> ipart(nb);
+    for (int r = 0; r < R; ++r) {
+        // k-means++ seeding
+        for (int t = 0; t < K; ++t) {
+            const double u = sm_uniform(seed, (uint64_t)r, (uint64_t)t);
+            if (t == 0) {
+                int64_t i0 = (int64_t)(u * (double)n);
+                if (i0 >= n) i0 = n - 1;
+                SF_HIP(hipMemcpyAsync(idxp, &i0, sizeof(int64_t), hipMemcpyHostToDevice, s));
+                SF_HIP(hipStreamSynchronize(s));
+            } else {
+                k_chunk_sums<<<nchunks, kKmThreads, 0, s>>>(d2, n, csum);
+                k_pp_pick<<<1, 64, 0, s>>>(d2, csum, nchunks, n, u, idxp);
+            }
+            k_pp_update<<<grid_n(n, 2048), kKmThreads, 0, s>>>(H, n, kdim, idxp, t, cent, d2);
+        }
+        SF_HIP(hipGetLastError());
+        // Lloyd
+        k_fill_i32<<<grid_n(n, 2048), kKmThreads, 0, s>>>(lab, n, -1);
+        SF_HIP(hipMemsetAsync(state, 0, 2 * sizeof(int), s));
+        int hstate[2] = {0, 0};
+        while (true) {
+            for (int it = 0; it < 8; ++it) {
+                k_assign<<<nb, kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+                k_cluster_sums<<<nbs, kKmThreads, sum_lds, s>>>(H, n, kdim, K, lab, part, cpart, state);
+                k_update<<<1, 1024, 0, s>>>(H, n, kdim, K, changed_part, nb, part, cpart, nbs, d2, cent, state,
+                                            max_iter);
+            }
+            SF_HIP(hipGetLastError());
+            SF_HIP(hipMemcpyAsync(hstate, state, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            SF_HIP(hipStreamSynchronize(s));
+            if (hstate[0]) break;
+        }
+        k_sum<<<nb, kKmThreads, 0, s>>>(d2, n, csum);
+        SF_HIP(hipGetLastError());
+        SF_HIP(hipMemcpyAsync(ipart.data(), csum, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        SF_HIP(hipStreamSynchronize(s));
+        double inertia = 0.0;
+        for (int b = 0; b < nb; ++b) inertia += ipart[b];
+        if (inertia < best_inertia) {
+            best_inertia = inertia;
+            SF_HIP(hipMemcpyAsync(best, lab, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        }
+    }
+    // renumber by first appearance
+    long long* first = reinterpret_cast<long long*>(part);
+    std::vector<long long> hfirst(K, (long long)INT64_MAX);
+    SF_HIP(hipMemcpyAsync(first, hfirst.data(), K * sizeof(long long), hipMemcpyHostToDevice, s));
+    k_first<<<grid_n(n, 2048), kKmThreads, 0, s>>>(best, n, first);
+    SF_HIP(hipMemcpyAsync(hfirst.data(), first, K * sizeof(long long), hipMemcpyDeviceToHost, s));
+    SF_HIP(hipStreamSynchronize(s));
+    std::vector<int> order(K);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hfirst[a] < hfirst[b]; });
+    std::vector<int32_t> map(K);
+    for (int q = 0; q < K; ++q) map[order[q]] = q;
+    int32_t* dmap = reinterpret_cast<int32_t*>(csum);
+    SF_HIP(hipMemcpyAsync(dmap, map.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    k_relabel<<<grid_n(n, 2048), kKmThreads, 0, s>>>(best, n, dmap, labels);
+    SF_HIP(hipGetLastError());
+    SF_HIP(hipStreamSynchronize(s));
+    if (inertia_out) *inertia_out = best_inertia;
+    return SFAIRSC_OK;
+}
+
+}  // namespace sfairsc
+
+using namespace sfairsc;
+
+extern "C" int sfairsc_labels(sfairsc_graph_t g, const double* H, int32_t kdim, int32_t n_clusters,
+                              int32_t n_restarts, uint64_t seed, int32_t max_iter, int32_t* labels, double* inertia,
+                              hipStream_t stream) {
+    if (!g || !H || !labels) return set_error(SFAIRSC_E_ARG, "NULL argument");
+    if (kdim < 1 || kdim > kMaxK) return set_error(SFAIRSC_E_ARG, "kdim=%d outside [1, %d]", kdim, kMaxK);
+    if (n_clusters < 2 || n_clusters > kMaxK || n_clusters > g->n)
+        return set_error(SFAIRSC_E_ARG, "n_clusters=%d out of range", n_clusters);
+    if (n_restarts < 1) return set_error(SFAIRSC_E_ARG, "n_restarts must be >= 1");
+    if ((size_t)(256 / 64) * n_clusters * (kdim + 1) * sizeof(double) > 65536)
+        return set_error(SFAIRSC_E_ARG, "n_clusters * (kdim + 1) must not exceed 2048");
+    if (max_iter <= 0) max_iter = 300;
+    return labels_impl(g, H, kdim, n_clusters, n_restarts, seed, max_iter, labels, inertia, stream);
+}

@@ -1,0 +1,405 @@
+// The deflated operator L^sigma = P (L_n - sigma I) P + sigma I (eq. asigma),
+// applied to a block of b <= 32 vectors as the matvec formula of Section 3.4:
+//   S  = C^T X                              (group-segmented reduction)
+//   X' = P X = X - C G^{-1} S               (eq. mv-Pw, G = C^T C)
+//   T  = L_n X'                             (CSR SpMM; epilogue sums C^T T)
+//   Y  = P T - sigma X' + sigma X = T - C G^{-1} (C^T T - sigma S)
+// C is never formed.  With F from Lemma 2.1 (first h-1 groups kept),
+//   (C^T Z)_s   = A_s - p_s sum_t A_t,  A_t = sum_{i in V_t} c_i Z_i,
+//   (C U)_i     = c_i R_{g_i},  R_s = U_s - q (s < h-1),  R_{h-1} = -q,
+//   q           = sum_{s<h-1} p_s U_s,
+// with c_i = d_i^{-1/2} (normalized) or 1, p_s = |V_s| / n.
+//
+// Every reduction has a fixed order (per-block partials combined in block
+// order), so results are bitwise reproducible run to run.
+#include <cmath>
+
+#include "internal.h"
+
+namespace sfairsc {
+
+constexpr int kSpmmThreads = 512;            // 8 waves
+constexpr int kSpmmWaves = kSpmmThreads / 64;
+constexpr int kSpmmMaxBlocks = 512;
+constexpr int kProjThreads = 256;
+constexpr int kProjMaxBlocks = 256;
+constexpr int kFinThreads = 1024;
+
+// 16-byte vector of 4 floats or 2 doubles.
+template <class VT>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    static constexpr int N = 4;
+    float v[4];
+    __device__ static Vec16 load(const float* p) {
+        float4 t = *reinterpret_cast<const float4*>(p);
+        return Vec16{{t.x, t.y, t.z, t.w}};
+    }
+    __device__ void store(float* p) const { *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]); }
+};
+template <>
+struct Vec16<double> {
+    static constexpr int N = 2;
+    double v[2];
+    __device__ static Vec16 load(const double* p) {
+        double2 t = *reinterpret_cast<const double2*>(p);
+        return Vec16{{t.x, t.y}};
+    }
+    __device__ void store(double* p) const { *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]); }
+};
+
+// ---------------------------------------------------------------------------
+// A_s partial sums of c_i X_i per group.  part: [gridDim.x][h][32].
+__global__ __launch_bounds__(kProjThreads) void k_proj_partial(const double* __restrict__ X, int ldx, int b,
+                                                                int64_t n, const int32_t* __restrict__ grp,
+                                                                const double* __restrict__ cs, int h,
+                                                                double* __restrict__ part, const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ double acc[];  // [kProjThreads / 32][h][32]
+    const int col = threadIdx.x & 31;
+    const int rsub = threadIdx.x >> 5;
+    constexpr int R = kProjThreads / 32;
+    for (int o = threadIdx.x; o < R * h * 32; o += kProjThreads) acc[o] = 0.0;
+    __syncthreads();
+    if (col < b) {
+        double* mine = acc + rsub * h * 32 + col;
+        for (int64_t i = (int64_t)blockIdx.x * R + rsub; i < n; i += (int64_t)gridDim.x * R) {
+            double c = cs ? cs[i] : 1.0;
+            mine[grp[i] * 32] += c * X[i * ldx + col];
+        }
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < h * 32; o += kProjThreads) {
+        double s = 0.0;
+        for (int r = 0; r < R; ++r) s += acc[r * h * 32 + o];
+        part[(size_t)blockIdx.x * h * 32 + o] = s;
+    }
+}
+
+// Combine per-block partial group sums and solve with G^{-1}.
+//   A = sum over blocks;  Z_s = A_s - p_s sum_t A_t  (s < h-1)
+//   if S_sub: Z -= sigma * S_sub   (output side: C^T T - sigma C^T X)
+//   U = Ginv Z; R table as in the file header.  Optionally store Z in S_out.
+__global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __restrict__ part, int nblk, int h,
+                                                                 int b, const double* __restrict__ gpar,
+                                                                 const double* __restrict__ S_sub, double sigma,
+                                                                 double* __restrict__ S_out,
+                                                                 double* __restrict__ Rtab, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[kFinThreads];
+    __shared__ double A[kMaxGroups * 32];
+    __shared__ double U[kMaxGroups * 32];
+    const int O = h * 32;             // <= kFinThreads since h <= 32
+    const int P = kFinThreads / O;    // threads per output
+    const int t = threadIdx.x;
+    {
+        const int o = t % O, sub = t / O;
+        double s = 0.0;
+        if (sub < P)
+            for (int blk = sub; blk < nblk; blk += P) s += part[(size_t)blk * O + o];
+        red[t] = s;
+    }
+    __syncthreads();
+    if (t < O) {
+        double tot = 0.0;
+        for (int q = 0; q < P; ++q) tot += red[q * O + t];
+        A[t] = tot;
+    }
+    __syncthreads();
+    const int m = h - 1;
+    const double* p = gpar;
+    const double* Ginv = gpar + h;
+    const int j = t;
+    if (j < b) {
+        double tot = 0.0;
+        for (int s = 0; s < h; ++s) tot += A[s * 32 + j];
+        // Z_s = (C^T Z)_s, reusing red[] as scratch: red[s * 32 + j]
+        for (int s = 0; s < m; ++s) {
+            double z = A[s * 32 + j] - p[s] * tot;
+            if (S_out) S_out[s * 32 + j] = z;
+            if (S_sub) z -= sigma * S_sub[s * 32 + j];
+            red[s * 32 + j] = z;
+        }
+        double q = 0.0;
+        for (int s = 0; s < m; ++s) {
+            double u = 0.0;
+            for (int r = 0; r < m; ++r) u += Ginv[s * m + r] * red[r * 32 + j];
+            U[s * 32 + j] = u;
+            q += p[s] * u;
+        }
+        for (int s = 0; s < m; ++s) Rtab[s * 32 + j] = U[s * 32 + j] - q;
+        Rtab[m * 32 + j] = -q;
+    } else if (j < 32) {
+        for (int s = 0; s < h; ++s) Rtab[s * 32 + j] = 0.0;
+        if (S_out)
+            for (int s = 0; s < m; ++s) S_out[s * 32 + j] = 0.0;
+    }
+}
+
+// X'_i = X_i - c_i R_{g_i}, written compact (stride BW) in type OT.
+template <class OT>
+__global__ __launch_bounds__(256) void k_proj_apply(const double* __restrict__ X, int ldx, int b, int BW, int64_t n,
+                                                     const int32_t* __restrict__ grp, const double* __restrict__ cs,
+                                                     const double* __restrict__ Rtab, OT* __restrict__ Xp,
+                                                     const int* skip) {
+    if (skip && *skip) return;
+    const int64_t total = n * BW;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / BW;
+        int j = (int)(idx - i * BW);
+        double v = 0.0;
+        if (j < b) {
+            double c = cs ? cs[i] : 1.0;
+            v = X[i * ldx + j] - c * Rtab[grp[i] * 32 + j];
+        }
+        Xp[idx] = (OT)v;
+    }
+}
+
+// T = diag * X' - W X' (CSR, one wavefront per row), epilogue: per-group sums
+// of c_i T_i into part[block][h][32].  X', T compact n x BW in type VT; the
+// products accumulate in VT (float in mixed precision).
+template <class VT, int BW>
+__global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const VT* __restrict__ val, const VT* __restrict__ diag,
+                                                        const VT* __restrict__ X, VT* __restrict__ T, int64_t n,
+                                                        const int32_t* __restrict__ grp,
+                                                        const double* __restrict__ cs, int h, int b,
+                                                        double* __restrict__ part, const int* skip) {
+    if (skip && *skip) return;
+    using V = Vec16<VT>;
+    constexpr int VEC = V::N;
+    constexpr int LPR = BW / VEC;  // lanes per row vector
+    constexpr int NS = 64 / LPR;   // nonzeros in flight per wave
+    extern __shared__ double gacc[];  // [kSpmmWaves][h][BW]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int slot = lane / LPR;
+    const int cl = lane % LPR;
+    const bool epi = part != nullptr;
+    if (epi) {
+        for (int o = threadIdx.x; o < kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
+        __syncthreads();
+    }
+    double* wacc = gacc + wave * h * BW;
+    for (int64_t row = (int64_t)blockIdx.x * kSpmmWaves + wave; row < n; row += (int64_t)gridDim.x * kSpmmWaves) {
+        const int32_t a = rowptr[row], e_end = rowptr[row + 1];
+        VT acc[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] = VT(0);
+        for (int32_t e = a + slot; e < e_end; e += NS) {
+            const int32_t j = col[e];
+            const VT w = val[e];
+            V x = V::load(X + (int64_t)j * BW + cl * VEC);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += w * x.v[v];
+        }
+#pragma unroll
+        for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off);
+        if (slot == 0) {
+            V xi = V::load(X + row * BW + cl * VEC);
+            const VT dg = diag[row];
+            V t;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) t.v[v] = dg * xi.v[v] - acc[v];
+            t.store(T + row * BW + cl * VEC);
+            if (epi) {
+                const double c = cs ? cs[row] : 1.0;
+                double* dst = wacc + grp[row] * BW + cl * VEC;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) dst[v] += c * (double)t.v[v];
+            }
+        }
+    }
+    if (epi) {
+        __syncthreads();
+        for (int o = threadIdx.x; o < h * 32; o += kSpmmThreads) {
+            const int s = o >> 5, jj = o & 31;
+            double tot = 0.0;
+            if (jj < BW && jj < b)
+                for (int w = 0; w < kSpmmWaves; ++w) tot += gacc[w * h * BW + s * BW + jj];
+            part[(size_t)blockIdx.x * h * 32 + o] = tot;
+        }
+    }
+}
+
+// Y_i = T_i - c_i R_{g_i} (T compact stride BW, type TT) into Y (double, ldy).
+template <class TT>
+__global__ __launch_bounds__(256) void k_defl_apply(const TT* __restrict__ T, int BW, int b, int64_t n,
+                                                     const int32_t* __restrict__ grp, const double* __restrict__ cs,
+                                                     const double* __restrict__ Rtab, double* __restrict__ Y, int ldy,
+                                                     const int* skip) {
+    if (skip && *skip) return;
+    const int64_t total = n * b;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / b;
+        int j = (int)(idx - i * b);
+        double c = cs ? cs[i] : 1.0;
+        Y[i * ldy + j] = (double)T[i * BW + j] - c * Rtab[grp[i] * 32 + j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+static int pad_width(int b) { return b <= 4 ? 4 : b <= 8 ? 8 : b <= 16 ? 16 : 32; }
+
+static int grid_rows(int64_t work, int per_block, int cap) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+static int ensure_op(sfairsc_graph* g) {
+    OpWork& w = g->op;
+    const int64_t n = g->n;
+    w.nblk_spmm = grid_rows(n, kSpmmWaves, kSpmmMaxBlocks);
+    w.nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
+    SF_TRY(w.part_in.ensure((size_t)w.nblk_proj * g->h * 32 * sizeof(double)));
+    SF_TRY(w.part_out.ensure((size_t)w.nblk_spmm * g->h * 32 * sizeof(double)));
+    SF_TRY(w.small.ensure((size_t)3 * kMaxGroups * 32 * sizeof(double)));
+    SF_TRY(w.xp.ensure((size_t)n * 32 * sizeof(double)));
+    SF_TRY(w.t.ensure((size_t)n * 32 * sizeof(double)));
+    return SFAIRSC_OK;
+}
+
+template <class VT>
+static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* val, const VT* diag, int b,
+                        double* part, int nblk, hipStream_t s, const int* skip) {
+    size_t lds = part ? (size_t)kSpmmWaves * g->h * BW * sizeof(double) : 0;
+#define SF_SPMM_CASE(W)                                                                                       \
+    case W:                                                                                                   \
+        k_spmm<VT, W><<<nblk, kSpmmThreads, lds, s>>>(g->rowptr, g->col, val, diag, X, T, g->n, g->grp, g->cs, \
+                                                      g->h, b, part, skip);                                   \
+        break;
+    switch (BW) {
+        SF_SPMM_CASE(4)
+        SF_SPMM_CASE(8)
+        SF_SPMM_CASE(16)
+        SF_SPMM_CASE(32)
+    }
+#undef SF_SPMM_CASE
+}
+
+int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
+             hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    SF_TRY(ensure_op(g));
+    OpWork& w = g->op;
+    const int BW = pad_width(b);
+    const int64_t n = g->n;
+    double* Rin = w.small.as<double>();
+    double* Sx = Rin + kMaxGroups * 32;
+    double* Rout = Sx + kMaxGroups * 32;
+    const int h = g->h;
+
+    // S = C^T X, R_in table
+    k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
+        X, ldx, b, n, g->grp, g->cs, h, w.part_in.as<double>(), skip);
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx,
+                                               Rin, skip);
+    const int ga = grid_rows(n * BW, 256, 8192);
+    if (mixed) {
+        float* xp = w.xp.as<float>();
+        float* t = w.t.as<float>();
+        k_proj_apply<float><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<float>(g, BW, xp, t, g->val32, g->diag32, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+        k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
+                                                   nullptr, Rout, skip);
+        k_defl_apply<float><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>(t, BW, b, n, g->grp, g->cs, Rout, Y, ldy,
+                                                                         skip);
+    } else {
+        double* xp = w.xp.as<double>();
+        double* t = w.t.as<double>();
+        k_proj_apply<double><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<double>(g, BW, xp, t, g->val64, g->diag64, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+        k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
+                                                   nullptr, Rout, skip);
+        k_defl_apply<double><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>(t, BW, b, n, g->grp, g->cs, Rout, Y, ldy,
+                                                                          skip);
+    }
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+// Pad / unpad copies between a user block of width b and the stride-BW layout.
+template <class T>
+__global__ void k_repack(const T* __restrict__ src, int lds_, T* __restrict__ dst, int ldd, int64_t n, int bcopy,
+                         int bfill) {
+    const int64_t total = n * bfill;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / bfill;
+        int j = (int)(idx - i * bfill);
+        dst[i * ldd + j] = j < bcopy ? src[i * lds_ + j] : T(0);
+    }
+}
+
+int op_spmm_raw(sfairsc_graph* g, const void* X, void* T, int b, int mixed, hipStream_t s) {
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    SF_TRY(ensure_op(g));
+    OpWork& w = g->op;
+    const int BW = pad_width(b);
+    const int64_t n = g->n;
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    const void* xin = X;
+    void* tout = T;
+    const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)T % 16 == 0);
+    if (BW != b || !aligned) {
+        SF_TRY(w.xpad.ensure((size_t)n * BW * es));
+        SF_TRY(w.ypad.ensure((size_t)n * BW * es));
+        int gr = grid_rows(n * BW, 256, 8192);
+        if (mixed)
+            k_repack<float><<<gr, 256, 0, s>>>((const float*)X, b, w.xpad.as<float>(), BW, n, b, BW);
+        else
+            k_repack<double><<<gr, 256, 0, s>>>((const double*)X, b, w.xpad.as<double>(), BW, n, b, BW);
+        xin = w.xpad.p;
+        tout = w.ypad.p;
+    }
+    if (mixed)
+        launch_spmm<float>(g, BW, (const float*)xin, (float*)tout, g->val32, g->diag32, b, nullptr, w.nblk_spmm, s,
+                           nullptr);
+    else
+        launch_spmm<double>(g, BW, (const double*)xin, (double*)tout, g->val64, g->diag64, b, nullptr, w.nblk_spmm,
+                            s, nullptr);
+    if (BW != b || !aligned) {
+        int gr = grid_rows(n * b, 256, 8192);
+        if (mixed)
+            k_repack<float><<<gr, 256, 0, s>>>(w.ypad.as<float>(), BW, (float*)T, b, n, b, b);
+        else
+            k_repack<double><<<gr, 256, 0, s>>>(w.ypad.as<double>(), BW, (double*)T, b, n, b, b);
+    }
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+}  // namespace sfairsc
+
+using namespace sfairsc;
+
+extern "C" int sfairsc_apply_operator(sfairsc_graph_t g, const double* X, double* Y, int32_t b, int precision,
+                                      double sigma, hipStream_t stream) {
+    if (!g || !X || !Y) return set_error(SFAIRSC_E_ARG, "NULL argument");
+    if (precision != SFAIRSC_PREC_FP64 && precision != SFAIRSC_PREC_MIXED)
+        return set_error(SFAIRSC_E_ARG, "unknown precision %d", precision);
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    if (sigma <= 0.0) sigma = g->sigma;
+    return op_apply(g, X, b, Y, b, b, precision == SFAIRSC_PREC_MIXED, sigma, stream);
+}
+
+extern "C" int sfairsc_spmm(sfairsc_graph_t g, const void* X, void* T, int32_t b, int precision,
+                            hipStream_t stream) {
+    if (!g || !X || !T) return set_error(SFAIRSC_E_ARG, "NULL argument");
+    if (precision != SFAIRSC_PREC_FP64 && precision != SFAIRSC_PREC_MIXED)
+        return set_error(SFAIRSC_E_ARG, "unknown precision %d", precision);
+    return op_spmm_raw(g, X, T, b, precision == SFAIRSC_PREC_MIXED, stream);
+}

@@ -1,0 +1,201 @@
+"""Parity of the fair eigensolver (sfairsc_eigs) against the FP64 oracle (GPU).
+
+Bars (Proposition 3.3 makes the GPU's eigenpairs of L^sigma the fair
+eigenpairs the oracle computes from an explicit nullspace):
+  * eigenvalues: relative 1e-8 in FP64, 1e-5 for the mixed solve; the
+    trivial eigenvalue 0 is compared against lambda_2;
+  * subspace: largest principal angle (D-weighted for the normalized
+    variant) <= 1e-6 (FP64) / 1e-4 (mixed), asserted only when the relative
+    gap (lambda_{k+1} - lambda_k) / sigma exceeds 100 tol (Davis-Kahan);
+  * constraints: F^T H = 0, H^T H = I (or H^T D H = I), and the oracle's own
+    residual of every returned pair below the requested tolerance.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+import oracle
+from conftest import read_golden
+from gpu_common import eig_parity, lib, log, to_np
+from sfairsc_inputs import msbm_from_blocks, random_sparse_graph, relabel, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def check_solution(g, lam, H, k, normalized, tol, sigma, lam_ref=None, H_ref=None, rtol=1e-8, atol_angle=1e-6,
+                   gap=None):
+    W = g.to_scipy()
+    d = oracle.degrees(W)
+    F = oracle.fairness_matrix(g.groups, g.h) if g.h > 1 else np.zeros((g.n, 0))
+    Hn = H
+    assert np.all(np.diff(lam) >= -1e-12 * sigma), "eigenvalues not ascending"
+    if F.shape[1]:
+        assert np.abs(F.T @ Hn).max() <= 1e-10 * np.sqrt(g.n) * np.abs(Hn).max()
+    M = Hn.T @ (d[:, None] * Hn) if normalized else Hn.T @ Hn
+    assert np.abs(M - np.eye(k)).max() <= 1e-9
+    res = oracle.residual_norms(W, g.groups, g.h, normalized, lam, Hn)
+    assert res.max() <= 4 * tol * sigma + 1e-12 * sigma, res.max() / sigma
+    if lam_ref is not None:
+        err = eig_parity(lam, lam_ref[:k], rtol)
+        log(f"  eigenvalue rel err {err:.2e}")
+        assert err <= rtol
+    if H_ref is not None and gap is not None and gap > 100 * tol:
+        ang = oracle.max_principal_angle(Hn, H_ref[:, :k], d if normalized else None)
+        log(f"  subspace angle {ang:.2e}")
+        assert ang <= atol_angle
+
+
+@pytest.mark.parametrize("normalized", [False, True])
+def test_msbm_2k_fp64(normalized):
+    sf = lib()
+    g = workload("msbm-2k-h2")
+    k, tol = 5, 1e-10
+    log(f"msbm-2k fp64 normalized={normalized}")
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, g.h, k + 1, normalized)
+    G = sf.Graph.from_msbm(g, normalized)
+    r = G.eigs(k, tol=tol, precision="fp64")
+    log(f"  info {r.info}")
+    sigma = G.sigma
+    gap = (lam_ref[k] - lam_ref[k - 1]) / sigma
+    check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
+    # planted recovery with the GPU k-means
+    lab, _ = G.labels(r.H, 5, n_restarts=10, seed=0)
+    assert oracle.error_rate(to_np(lab), g.clusters) == 0.0
+
+
+@pytest.mark.parametrize("normalized", [False, True])
+def test_msbm_2k_mixed(normalized):
+    sf = lib()
+    g = workload("msbm-2k-h2")
+    k, tol = 5, 1e-8
+    log(f"msbm-2k mixed normalized={normalized}")
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, g.h, k + 1, normalized)
+    G = sf.Graph.from_msbm(g, normalized)
+    r = G.eigs(k, tol=tol, precision="mixed")
+    log(f"  info {r.info}")
+    sigma = G.sigma
+    gap = (lam_ref[k] - lam_ref[k - 1]) / sigma
+    check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, sigma, lam_ref, H_ref, 1e-5, 1e-4, gap)
+    assert r.info["spmm_launches"][1] > 0
+
+
+def test_relabelled_graph():
+    sf = lib()
+    g = relabel(workload("msbm-2k-h2"), 17)
+    k, tol = 5, 1e-10
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, g.h, k + 1, False)
+    G = sf.Graph.from_msbm(g, False)
+    r = G.eigs(k, tol=tol)
+    gap = (lam_ref[k] - lam_ref[k - 1]) / G.sigma
+    check_solution(g, r.eigenvalues, to_np(r.H), k, False, tol, G.sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
+
+
+SMALL = [
+    (97, 8, 1, 2, False, 3),
+    (97, 8, 2, 2, True, 2),
+    (250, 12, 3, 3, False, 4),
+    (250, 12, 4, 3, True, 6),
+    (613, 6, 5, 1, False, 5),
+    (613, 6, 6, 2, True, 4),
+    (1201, 20, 7, 4, False, 8),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"n{c[0]}-h{c[3]}-{'norm' if c[4] else 'unnorm'}" for c in SMALL])
+def test_small_random_graphs(case):
+    sf = lib()
+    n, deg, seed, h, normalized, k = case
+    g = random_sparse_graph(n, deg, seed=seed, h=h, weights=("uniform", 0.5, 1.5))
+    log(f"small graph {case}")
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, h, k + 1, normalized)
+    G = sf.Graph.from_msbm(g, normalized)
+    tol = 1e-10
+    r = G.eigs(k, tol=tol)
+    gap = (lam_ref[k] - lam_ref[k - 1]) / G.sigma
+    check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, G.sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
+
+
+def test_complete_graph_breakdown_is_repaired():
+    # K_n has only the eigenvalues 0 and n (and sigma after deflation): the
+    # Krylov space becomes invariant after a few blocks and must be repaired
+    sf = lib()
+    n, h = 64, 4
+    rows = np.repeat(np.arange(n), n - 1)
+    cols = np.concatenate([np.delete(np.arange(n), i) for i in range(n)])
+    rowptr = np.arange(0, n * (n - 1) + 1, n - 1, dtype=np.int32)
+    G = sf.Graph(rowptr, cols.astype(np.int32), np.ones(n * (n - 1)), (np.arange(n) % h).astype(np.int32), h, False)
+    r = G.eigs(6, tol=1e-10)
+    log(f"  info {r.info}")
+    assert abs(r.eigenvalues[0]) < 1e-8 * n
+    assert np.allclose(r.eigenvalues[1:], n, rtol=1e-9)
+
+
+def test_disjoint_fair_cliques_zero_eigenspace():
+    # k disjoint fair cliques: eigenvalue 0 with multiplicity k, eigenspace
+    # spanned by the clique indicators (the eigenspace-mixing case)
+    sf = lib()
+    k, per = 4, 40
+    n = k * per
+    blocks = []
+    for c in range(k):
+        for i in range(per):
+            for j in range(per):
+                if i != j:
+                    blocks.append((c * per + i, c * per + j))
+    e = np.array(blocks)
+    W = sp.csr_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
+    W.sort_indices()
+    groups = (np.arange(n) % 2).astype(np.int32)
+    for normalized in (False, True):
+        G = sf.Graph(W.indptr.astype(np.int32), W.indices.astype(np.int32), W.data, groups, 2, normalized)
+        r = G.eigs(k, tol=1e-10)
+        assert np.all(np.abs(r.eigenvalues) < 1e-8 * G.sigma)
+        ind = np.kron(np.eye(k), np.ones((per, 1)))
+        d = np.asarray(W.sum(1)).ravel() if normalized else None
+        assert oracle.max_principal_angle(to_np(r.H), ind, d) < 1e-6
+
+
+def test_not_converged_returns_partial_result():
+    sf = lib()
+    g = workload("msbm-2k-h2")
+    G = sf.Graph.from_msbm(g, False)
+    r = G.eigs(5, tol=1e-15, max_restarts=1, raise_not_converged=False)
+    assert r.status == sf.E_NOT_CONVERGED
+    assert r.info["restarts"] == 1
+    assert np.all(np.isfinite(r.eigenvalues)) and torch.isfinite(r.H).all()
+
+
+def test_bitwise_repeatable_and_warm_start():
+    sf = lib()
+    g = workload("msbm-2k-h2")
+    G = sf.Graph.from_msbm(g, True)
+    a = G.eigs(5, tol=1e-10)
+    b = G.eigs(5, tol=1e-10)
+    assert np.array_equal(a.eigenvalues, b.eigenvalues)
+    assert torch.equal(a.H, b.H)
+    # warm start from the (back-transformed) solution: X = D^{1/2} H
+    d = torch.from_numpy(oracle.degrees(g.to_scipy())).to(a.H.device)
+    x0 = (a.H * d.sqrt()[:, None]).contiguous()
+    c = G.eigs(5, tol=1e-10, x0=x0, block_width=8)
+    assert c.info["restarts"] <= a.info["restarts"]
+    assert eig_parity(c.eigenvalues, a.eigenvalues, 1e-8) <= 1e-8
+
+
+def test_msbm_50k_normalized_fp64_and_mixed():
+    # the n = 50,000 normalized workload against stored oracle eigenvalues
+    # (tests/golden/make_golden.py) and the oracle's residuals
+    sf = lib()
+    gold = read_golden("msbm50k_normalized_eigs.txt")
+    lam_ref = np.array([float(x) for x in gold["eigenvalues"]])
+    g = workload("msbm-50k-h5-normalized")
+    G = sf.Graph.from_msbm(g, True)
+    k, tol = 10, 1e-8
+    for prec, rtol in (("fp64", 1e-8), ("mixed", 1e-5)):
+        log(f"msbm-50k {prec}")
+        r = G.eigs(k, tol=tol, precision=prec)
+        log(f"  info {r.info}")
+        check_solution(g, r.eigenvalues, to_np(r.H), k, True, tol, G.sigma, lam_ref, None, rtol)
