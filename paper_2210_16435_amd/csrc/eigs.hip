@@ -326,7 +326,8 @@ __global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double*
 // imax: [blk][k].
 __global__ __launch_bounds__(256) void k_col_stats(const double* __restrict__ X, const double* __restrict__ Y,
                                                     int ld, int64_t n, int k, const double* __restrict__ theta,
-                                                    double* __restrict__ part, int64_t* __restrict__ imax) {
+                                                    double* __restrict__ part, int64_t* __restrict__ imax,
+                                                    const double* __restrict__ scale) {
     __shared__ double ss[256];
     __shared__ double mx[256];
     __shared__ int64_t mi[256];
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256) void k_col_stats(const double* __restrict__ X,
                 const double r = Y[i * ld + j] - th * x;
                 s += r * r;
             }
-            const double a = fabs(x);
+            const double a = fabs(scale ? scale[i] * x : x);
             if (a > m) {
                 m = a;
                 at = i;
@@ -371,15 +372,15 @@ __global__ __launch_bounds__(256) void k_col_stats(const double* __restrict__ X,
     }
 }
 
-// Column-major output H[:, j] = sign_j * X[:, j] (row-major X, ld).
+// Column-major output H[:, j] = sign_j * scale_i * X[:, j] (row-major X, ld).
 __global__ void k_write_out(const double* __restrict__ X, int ld, int64_t n, int k, const double* __restrict__ sgn,
-                            double* __restrict__ H) {
+                            const double* __restrict__ scale, double* __restrict__ H) {
     const int64_t total = n * k;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         int j = (int)(idx / n);
         int64_t i = idx - (int64_t)j * n;
-        H[idx] = sgn[j] * X[i * ld + j];
+        H[idx] = sgn[j] * (scale ? scale[i] : 1.0) * X[i * ld + j];
     }
 }
 
@@ -769,7 +770,7 @@ static int certify(Solver& S, const double* X, double* Ybuf, const std::vector<d
     S.mixed = was_mixed;
     SF_HIP(hipMemcpyAsync(S.theta, theta.data(), k * sizeof(double), hipMemcpyHostToDevice, S.s));
     const int nb = grid_for(S.n, 256, kStatBlocks);
-    k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.theta, S.stats, S.imax);
+    k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.theta, S.stats, S.imax, nullptr);
     SF_HIP(hipGetLastError());
     std::vector<double> part((size_t)nb * 2 * k);
     SF_HIP(hipMemcpyAsync(part.data(), S.stats, part.size() * sizeof(double), hipMemcpyDeviceToHost, S.s));
@@ -790,7 +791,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     if (b != 4 && b != 8 && b != 16 && b != 32) return set_error(SFAIRSC_E_ARG, "block width must be 4, 8, 16 or 32");
     while (b > 4 && 3 * b + k > dim) b /= 2;
     int ncv = o.max_basis;
-    if (ncv == 0) ncv = std::max(k + 4 * b, 3 * k + 2 * b);
+    if (ncv == 0) ncv = std::max(k + 6 * b, 4 * k + 2 * b);
     ncv = ((ncv + b - 1) / b) * b;
     ncv = std::min(ncv, kMaxBasis);
     while (ncv + 2 * b > dim && ncv > b) ncv -= b;
@@ -851,6 +852,10 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
         SF_TRY(run_ks(S, tol, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
         SF_TRY(ritz_vectors(S, R, Xr, nullptr));
     }
+    // Exact eigenvectors of L^sigma below sigma lie in null(C^T) (Prop. 3.1);
+    // remove the O(residual / (sigma - theta)) range(C) part of the Ritz
+    // vectors so the returned H satisfies F^T H = 0 to rounding.
+    for (int j0 = 0; j0 < k; j0 += kMaxBlock) SF_TRY(op_project(g, Xr + j0, k, std::min(kMaxBlock, k - j0), s));
     std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
     if (o.certify || precision == SFAIRSC_PREC_MIXED) {
         SF_TRY(certify(S, Xr, Yr, th, res));
@@ -863,10 +868,10 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
         worst = std::max(worst, res[i] / S.sigma);
         if (res[i] <= tol * S.sigma) ++nconv;
     }
-    // sign convention and output H = D^{-1/2} X (normalized) or X
-    if (scale) SF_TRY(ritz_vectors(S, R, Xr, scale));
+    // sign convention on H = D^{-1/2} X (normalized) or X: the entry of
+    // largest magnitude of each column is made positive
     const int nb = grid_for(n, 256, kStatBlocks);
-    k_col_stats<<<nb, 256, 0, s>>>(Xr, nullptr, k, n, k, nullptr, S.stats, S.imax);
+    k_col_stats<<<nb, 256, 0, s>>>(Xr, nullptr, k, n, k, nullptr, S.stats, S.imax, scale);
     SF_HIP(hipGetLastError());
     std::vector<double> part((size_t)nb * 2 * k);
     std::vector<int64_t> pidx((size_t)nb * k);
@@ -895,7 +900,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     SF_HIP(hipStreamSynchronize(s));
     for (int j = 0; j < k; ++j) sgn[j] = (at_row[j] >= 0 && hx[j] < 0) ? -1.0 : 1.0;
     SF_HIP(hipMemcpyAsync(S.theta, sgn.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-    k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, H);
+    k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, scale, H);
     SF_HIP(hipGetLastError());
     SF_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < k; ++i) eigvals[i] = th[i];

@@ -111,6 +111,9 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy,
              hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr,
              const int* skip_flag = nullptr);
 
+// X <- P X = X - C (C^T C)^{-1} C^T X in place (X double, ldx, b <= 32).
+int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
+
 // Raw sparse product T = L X (no projection), X/T compact row-major n x b.
 int op_spmm_raw(sfairsc_graph* g, const void* X, void* T, int b, int mixed,
                 hipStream_t s);

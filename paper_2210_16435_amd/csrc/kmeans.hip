@@ -315,7 +315,7 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     const int nb = grid_n(n, kKmMaxBlocks);
     const int nbs = std::max(1, std::min<int>(nb, 256));
     SF_TRY(w.d2.ensure((size_t)n * sizeof(double)));
-    SF_TRY(w.cs.ensure((size_t)std::max(nchunks, nb) * sizeof(double)));
+    SF_TRY(w.cs.ensure((size_t)std::max(std::max(nchunks, nb), K) * sizeof(double)));
     SF_TRY(w.cent.ensure((size_t)K * kdim * sizeof(double)));
     SF_TRY(w.lab.ensure((size_t)n * sizeof(int32_t)));
     SF_TRY(w.best.ensure((size_t)n * sizeof(int32_t)));

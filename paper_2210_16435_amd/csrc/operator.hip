@@ -331,6 +331,36 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int
     return SFAIRSC_OK;
 }
 
+// X_i -= c_i R_{g_i} in place (X double, leading dimension ldx, b columns).
+__global__ __launch_bounds__(256) void k_proj_inplace(double* __restrict__ X, int ldx, int b, int64_t n,
+                                                       const int32_t* __restrict__ grp, const double* __restrict__ cs,
+                                                       const double* __restrict__ Rtab) {
+    const int64_t total = n * b;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx / b;
+        int j = (int)(idx - i * b);
+        double c = cs ? cs[i] : 1.0;
+        X[i * ldx + j] -= c * Rtab[grp[i] * 32 + j];
+    }
+}
+
+int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    SF_TRY(ensure_op(g));
+    OpWork& w = g->op;
+    double* Rin = w.small.as<double>();
+    double* Sx = Rin + kMaxGroups * 32;
+    const int h = g->h;
+    k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
+        X, ldx, b, g->n, g->grp, g->cs, h, w.part_in.as<double>(), nullptr);
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx,
+                                               Rin, nullptr);
+    k_proj_inplace<<<grid_rows(g->n * b, 256, 8192), 256, 0, s>>>(X, ldx, b, g->n, g->grp, g->cs, Rin);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
 // Pad / unpad copies between a user block of width b and the stride-BW layout.
 template <class T>
 __global__ void k_repack(const T* __restrict__ src, int lds_, T* __restrict__ dst, int ldd, int64_t n, int bcopy,
