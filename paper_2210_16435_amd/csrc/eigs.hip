@@ -313,6 +313,25 @@ __global__ void k_copy_in(const double* __restrict__ X, int b0, double* __restri
     }
 }
 
+// X[0:count] = 0 (a kernel rather than a memset: stream-ordered with the
+// solver's other kernels under every runtime mode, and graph-capturable).
+__global__ void k_zero(double* __restrict__ X, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        X[i] = 0.0;
+}
+
+__global__ void k_zero_i32(int* __restrict__ X, int count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) X[i] = 0;
+}
+
+// Tc (c x c, contiguous) = T[0:c, 0:c] (leading dimension ldt).
+__global__ void k_pack(const double* __restrict__ T, int ldt, int c, double* __restrict__ Tc) {
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < c * c; idx += gridDim.x * blockDim.x) {
+        int i = idx / c, j = idx - i * c;
+        Tc[idx] = T[(size_t)i * ldt + j];
+    }
+}
+
 // T[0:p, 0:p] = diag(theta).
 __global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta) {
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * p; idx += gridDim.x * blockDim.x) {
@@ -453,8 +472,11 @@ struct Solver {
         sp += 8;
         ident = nullptr;
         Q = w.Q.as<double>();
-        SF_HIP(hipMemsetAsync(flag, 0, 8 * sizeof(int), s));
-        SF_HIP(hipMemsetAsync(T, 0, (size_t)ld * ld * sizeof(double), s));
+        SF_TRY(w.opart.ensure(ortho_part_doubles(n) * sizeof(double)));
+        SF_TRY(w.osmall.ensure(ortho_small_doubles() * sizeof(double)));
+        k_zero_i32<<<1, 64, 0, s>>>(flag, 8);
+        k_zero<<<grid_for((int64_t)ld * ld, 256, 1024), 256, 0, s>>>(T, (int64_t)ld * ld);
+        SF_HIP(hipGetLastError());
         return SFAIRSC_OK;
     }
 
@@ -463,6 +485,60 @@ struct Solver {
         const int W = (useV ? cv : 0) + b;
         int msz = mode >= TS_MUL_SYRK ? b * b : 0;
         return (size_t)(kTsRows * W + msz + kTsRows * b) * sizeof(double);
+    }
+
+    // Stage `bytes` from host memory through the pinned buffer and enqueue
+    // the copy; regions are recycled after the stream is synchronised.
+    int upload(void* dst, const void* src, size_t bytes) {
+        EigWork& w = g->eig;
+        const size_t need = (bytes + 255) & ~(size_t)255;
+        if (!w.pin) {
+            w.pin_cap = std::max<size_t>((size_t)4 * kLdMax * kLdMax * sizeof(double), need);
+            SF_HIP(hipHostMalloc((void**)&w.pin, w.pin_cap, hipHostMallocDefault));
+            w.pin_off = 0;
+        }
+        if (need > w.pin_cap) return set_error(SFAIRSC_E_ARG, "upload of %zu bytes exceeds the staging buffer", bytes);
+        if (w.pin_off + need > w.pin_cap) SF_TRY(sync());
+        char* slot = reinterpret_cast<char*>(w.pin) + w.pin_off;
+        std::memcpy(slot, src, bytes);
+        w.pin_off += need;
+        SF_HIP(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, s));
+        return SFAIRSC_OK;
+    }
+
+    // Enqueue a device-to-host copy through the pinned buffer; the bytes
+    // reach `dst` at the next sync().
+    struct Pending {
+        void* dst;
+        const void* slot;
+        size_t bytes;
+    };
+    std::vector<Pending> pending;
+    int download(void* dst, const void* src, size_t bytes) {
+        EigWork& w = g->eig;
+        const size_t need = (bytes + 255) & ~(size_t)255;
+        if (!w.pin) {
+            w.pin_cap = std::max<size_t>((size_t)4 * kLdMax * kLdMax * sizeof(double), need);
+            SF_HIP(hipHostMalloc((void**)&w.pin, w.pin_cap, hipHostMallocDefault));
+            w.pin_off = 0;
+        }
+        if (need > w.pin_cap) return set_error(SFAIRSC_E_ARG, "download of %zu bytes exceeds the staging buffer", bytes);
+        if (w.pin_off + need > w.pin_cap) SF_TRY(sync());
+        char* slot = reinterpret_cast<char*>(w.pin) + w.pin_off;
+        w.pin_off += need;
+        SF_HIP(hipMemcpyAsync(slot, src, bytes, hipMemcpyDeviceToHost, s));
+        pending.push_back({dst, slot, bytes});
+        return SFAIRSC_OK;
+    }
+
+    // Synchronise the stream; staged uploads are complete and staged
+    // downloads are delivered afterwards.
+    int sync() {
+        SF_HIP(hipStreamSynchronize(s));
+        for (const Pending& p : pending) std::memcpy(p.dst, p.slot, p.bytes);
+        pending.clear();
+        g->eig.pin_off = 0;
+        return SFAIRSC_OK;
     }
 
     int ts(int mode, int cv, int yoff, const double* M) {
@@ -524,8 +600,7 @@ struct Solver {
             ident = Q + (size_t)kLdMax * kLdMax - kMaxBlock * kMaxBlock;  // tail of Q, never used by rotations here
             std::vector<double> I(b * b, 0.0);
             for (int i = 0; i < b; ++i) I[i * b + i] = 1.0;
-            (void)hipMemcpyAsync(ident, I.data(), b * b * sizeof(double), hipMemcpyHostToDevice, s);
-            (void)hipStreamSynchronize(s);
+            if (upload(ident, I.data(), b * b * sizeof(double)) != SFAIRSC_OK) return nullptr;
         }
         return ident;
     }
@@ -549,6 +624,51 @@ struct Solver {
             info->spmm_launches[mixed ? 1 : 0] += 1;
         }
         return SFAIRSC_OK;
+    }
+
+    // One Krylov expansion from V_next = V[:, c : c+b]: operator, then the
+    // matrix-core orthogonalisation passes into V[:, c+b : c+2b].
+    int expand(int c) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            if (ev_used + 2 > evs.size()) {
+                for (int i = 0; i < 256; ++i) {
+                    hipEvent_t e;
+                    SF_HIP(hipEventCreate(&e));
+                    evs.push_back(e);
+                }
+            }
+            e0 = evs[ev_used++];
+            e1 = evs[ev_used++];
+        }
+        OpOut o;
+        SF_TRY(op_apply_t(g, V + c, ld, b, mixed, sigma, s, e0, e1, flag, &o));
+        if (info) {
+            info->operator_applies += b;
+            info->spmm_launches[mixed ? 1 : 0] += 1;
+        }
+        OrthoArgs a;
+        a.V = V;
+        a.ld = ld;
+        a.n = n;
+        a.cv = c + b;
+        a.b = b;
+        a.t = o.t;
+        a.t_is_float = o.is_float;
+        a.BW = o.BW;
+        a.grp = g->grp;
+        a.cs = g->cs;
+        a.rtab = o.rtab;
+        a.T = T;
+        a.ldt = ld;
+        a.thresh = thresh;
+        a.part = g->eig.opart.as<double>();
+        a.small = g->eig.osmall.as<double>();
+        a.gsave = Gsave;
+        a.rc = Rc;
+        a.flag = flag;
+        a.stream = s;
+        return ortho_expand(a);
     }
 
     // Sum the elapsed times of recorded SpMM event pairs (stream synced).
@@ -576,17 +696,17 @@ struct Solver {
 // driven; rare).  Rotates Y onto the eigenvectors of its Gram matrix, keeps
 // the directions of significant norm, replaces the others by random vectors,
 // orthonormalises again and rebuilds the coupling R = Rnew diag(keep) U^T.
-static int repair_block(Solver& S, int cact, uint64_t seed, int attempt) {
+static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int stage) {
     const int b = S.b;
     const int cv = cact + b;
     std::vector<double> G(b * b), U(b * b), w(b);
-    SF_HIP(hipMemcpyAsync(G.data(), S.Gsave, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
-    SF_HIP(hipStreamSynchronize(S.s));
+    SF_TRY(S.download(G.data(), S.Gsave, b * b * sizeof(double)));
+    SF_TRY(S.sync());
     sym_eig(b, G.data(), w.data(), U.data());
     // Y <- Y U, deficient columns -> random
-    SF_HIP(hipMemcpyAsync(S.Q, U.data(), b * b * sizeof(double), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.upload(S.Q, U.data(), b * b * sizeof(double)));
     int zero = 0;
-    SF_HIP(hipMemcpyAsync(S.flag, &zero, sizeof(int), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.upload(S.flag, &zero, sizeof(int)));
     SF_TRY(S.ts(TS_MUL, 0, cv, S.Q));
     std::vector<int> keep(b, 0);
     for (int j = 0; j < b; ++j) {
@@ -599,11 +719,11 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt) {
     // projection coefficients, so do not touch T (cact = -1 path writes into
     // scratch rows beyond the basis).
     SF_TRY(S.orthonormalize(cv, -1));
-    int hflag[2];
-    SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
+    int hflag[3];
+    SF_TRY(S.download(hflag, S.flag, 3 * sizeof(int)));
     std::vector<double> Rn(b * b);
-    SF_HIP(hipMemcpyAsync(Rn.data(), S.Rc, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
-    SF_HIP(hipStreamSynchronize(S.s));
+    SF_TRY(S.download(Rn.data(), S.Rc, b * b * sizeof(double)));
+    SF_TRY(S.sync());
     if (hflag[0]) return set_error(SFAIRSC_E_HIP, "could not repair a rank-deficient Krylov block");
     // Y_old = Y_rot U^T,  Y_rot[:, j] = Qnew Rn[:, j] for kept j, 0 otherwise
     std::vector<double> Rc(b * b, 0.0);
@@ -614,21 +734,32 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt) {
                 if (keep[t]) sacc += Rn[i * b + t] * U[j * b + t];
             Rc[i * b + j] = sacc;
         }
-    SF_HIP(hipMemcpyAsync(S.Rc, Rc.data(), b * b * sizeof(double), hipMemcpyHostToDevice, S.s));
+    if (stage == 2) {
+        // the failed block was Y1 = W R1^{-1}: the residual is W = Y1 R1
+        std::vector<double> R1(b * b), Rm(b * b, 0.0);
+        SF_TRY(S.download(R1.data(), ortho_r1(S.g->eig.osmall.as<double>()), b * b * sizeof(double)));
+        SF_TRY(S.sync());
+        for (int i = 0; i < b; ++i)
+            for (int j = 0; j < b; ++j) {
+                double sacc = 0.0;
+                for (int t = 0; t < b; ++t) sacc += Rc[i * b + t] * R1[t * b + j];
+                Rm[i * b + j] = sacc;
+            }
+        Rc = Rm;
+    }
+    SF_TRY(S.upload(S.Rc, Rc.data(), b * b * sizeof(double)));
     // symmetrise T's diagonal block of V_next (normally done by the second
     // Cholesky pass of the expansion)
     std::vector<double> Tb(b * S.ld);
-    SF_HIP(hipMemcpyAsync(Tb.data(), S.T + (size_t)cact * S.ld, b * S.ld * sizeof(double), hipMemcpyDeviceToHost,
-                          S.s));
-    SF_HIP(hipStreamSynchronize(S.s));
+    SF_TRY(S.download(Tb.data(), S.T + (size_t)cact * S.ld, b * S.ld * sizeof(double)));
+    SF_TRY(S.sync());
     for (int i = 0; i < b; ++i)
         for (int j = i + 1; j < b; ++j) {
             double m = 0.5 * (Tb[i * S.ld + cact + j] + Tb[j * S.ld + cact + i]);
             Tb[i * S.ld + cact + j] = m;
             Tb[j * S.ld + cact + i] = m;
         }
-    SF_HIP(hipMemcpyAsync(S.T + (size_t)cact * S.ld, Tb.data(), b * S.ld * sizeof(double), hipMemcpyHostToDevice,
-                          S.s));
+    SF_TRY(S.upload(S.T + (size_t)cact * S.ld, Tb.data(), b * S.ld * sizeof(double)));
     if (S.info) S.info->breakdowns += 1;
     return SFAIRSC_OK;
 }
@@ -658,8 +789,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     SF_TRY(S.orthonormalize(0, -1));
     {
         int hflag[2];
-        SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
-        SF_HIP(hipStreamSynchronize(S.s));
+        SF_TRY(S.download(hflag, S.flag, 2 * sizeof(int)));
+        SF_TRY(S.sync());
         if (hflag[0]) return set_error(SFAIRSC_E_ARG, "start block is rank deficient");
     }
     int repairs = 0;
@@ -667,30 +798,30 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     for (int restart = 0;; ++restart) {
         // expansions
         while (c + b <= ncv) {
-            SF_TRY(S.apply(S.V + c, S.ld, S.V + c + b, S.ld, b));
-            SF_TRY(S.orthonormalize(c + b, c));
+            SF_TRY(S.expand(c));
             if (S.info) S.info->block_steps += 1;
             c += b;
         }
-        int hflag[2];
-        SF_HIP(hipMemcpyAsync(hflag, S.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, S.s));
-        SF_HIP(hipStreamSynchronize(S.s));
+        int hflag[3];
+        SF_TRY(S.download(hflag, S.flag, 3 * sizeof(int)));
+        SF_TRY(S.sync());
         SF_TRY(S.harvest_timing());
         if (hflag[0]) {
             // everything after the failed expansion at hflag[1] was skipped
             const int cact = hflag[1];
             if (++repairs > 64) return set_error(SFAIRSC_E_HIP, "too many Krylov breakdowns");
-            SF_TRY(repair_block(S, cact, seed, repairs));
+            SF_TRY(repair_block(S, cact, seed, repairs, hflag[2]));
             c = cact + b;
             if (S.info) S.info->block_steps += 1;
             continue;
         }
         // Rayleigh-Ritz on T_c
         hT.resize((size_t)c * c);
-        SF_HIP(hipMemcpy2DAsync(hT.data(), c * sizeof(double), S.T, S.ld * sizeof(double), c * sizeof(double), c,
-                                hipMemcpyDeviceToHost, S.s));
-        SF_HIP(hipMemcpyAsync(Rc.data(), S.Rc, b * b * sizeof(double), hipMemcpyDeviceToHost, S.s));
-        SF_HIP(hipStreamSynchronize(S.s));
+        k_pack<<<grid_for((int64_t)c * c, 256, 256), 256, 0, S.s>>>(S.T, S.ld, c, S.part);
+        SF_HIP(hipGetLastError());
+        SF_TRY(S.download(hT.data(), S.part, (size_t)c * c * sizeof(double)));
+        SF_TRY(S.download(Rc.data(), S.Rc, b * b * sizeof(double)));
+        SF_TRY(S.sync());
         for (int i = 0; i < c; ++i)
             for (int j = i + 1; j < c; ++j) {
                 double m = 0.5 * (hT[i * c + j] + hT[j * c + i]);
@@ -729,11 +860,12 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         p = std::min(p, ncv - b);
         p = std::max(p, std::min(k, ncv - b));
         while (p < ncv - b && p < c && std::fabs(w[p] - w[p - 1]) <= 1e-10 * S.sigma) ++p;
+        p = std::min((p + 3) & ~3, ncv - b);  // keeps every later column offset a multiple of 4
         std::vector<double> Qp((size_t)c * p);
         for (int t = 0; t < c; ++t)
             for (int q = 0; q < p; ++q) Qp[(size_t)t * p + q] = Z[(size_t)t * c + q];
-        SF_HIP(hipMemcpyAsync(S.Q, Qp.data(), Qp.size() * sizeof(double), hipMemcpyHostToDevice, S.s));
-        SF_HIP(hipMemcpyAsync(S.theta, w.data(), p * sizeof(double), hipMemcpyHostToDevice, S.s));
+        SF_TRY(S.upload(S.Q, Qp.data(), Qp.size() * sizeof(double)));
+        SF_TRY(S.upload(S.theta, w.data(), p * sizeof(double)));
         k_rotate<<<grid_for(n, kRotRows, 1024), 256, (size_t)kRotRows * (c + b) * sizeof(double), S.s>>>(
             S.V, S.ld, n, c, p, b, S.Q, 0, nullptr, 0, nullptr);
         k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.theta);
@@ -748,7 +880,7 @@ static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* 
     std::vector<double> Qk((size_t)c * k);
     for (int t = 0; t < c; ++t)
         for (int q = 0; q < k; ++q) Qk[(size_t)t * k + q] = R.Z[(size_t)t * c + q];
-    SF_HIP(hipMemcpyAsync(S.Q, Qk.data(), Qk.size() * sizeof(double), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.upload(S.Q, Qk.data(), Qk.size() * sizeof(double)));
     k_rotate<<<grid_for(S.n, kRotRows, 1024), 256, (size_t)kRotRows * (c + S.b) * sizeof(double), S.s>>>(
         S.V, S.ld, S.n, c, k, S.b, S.Q, 1, Xo, k, scale);
     SF_HIP(hipGetLastError());
@@ -762,19 +894,19 @@ static int certify(Solver& S, const double* X, double* Ybuf, const std::vector<d
     const bool was_mixed = S.mixed;
     S.mixed = false;
     int zero = 0;
-    SF_HIP(hipMemcpyAsync(S.flag, &zero, sizeof(int), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.upload(S.flag, &zero, sizeof(int)));
     for (int j0 = 0; j0 < k; j0 += kMaxBlock) {
         int bb = std::min(kMaxBlock, k - j0);
         SF_TRY(op_apply(S.g, X + j0, k, Ybuf + j0, k, bb, 0, S.sigma, S.s, nullptr, nullptr, nullptr));
     }
     S.mixed = was_mixed;
-    SF_HIP(hipMemcpyAsync(S.theta, theta.data(), k * sizeof(double), hipMemcpyHostToDevice, S.s));
+    SF_TRY(S.upload(S.theta, theta.data(), k * sizeof(double)));
     const int nb = grid_for(S.n, 256, kStatBlocks);
     k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.theta, S.stats, S.imax, nullptr);
     SF_HIP(hipGetLastError());
     std::vector<double> part((size_t)nb * 2 * k);
-    SF_HIP(hipMemcpyAsync(part.data(), S.stats, part.size() * sizeof(double), hipMemcpyDeviceToHost, S.s));
-    SF_HIP(hipStreamSynchronize(S.s));
+    SF_TRY(S.download(part.data(), S.stats, part.size() * sizeof(double)));
+    SF_TRY(S.sync());
     res.assign(k, 0.0);
     for (int blk = 0; blk < nb; ++blk)
         for (int j = 0; j < k; ++j) res[j] += part[(size_t)blk * 2 * k + j];
@@ -875,9 +1007,9 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     SF_HIP(hipGetLastError());
     std::vector<double> part((size_t)nb * 2 * k);
     std::vector<int64_t> pidx((size_t)nb * k);
-    SF_HIP(hipMemcpyAsync(part.data(), S.stats, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    SF_HIP(hipMemcpyAsync(pidx.data(), S.imax, pidx.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SF_HIP(hipStreamSynchronize(s));
+    SF_TRY(S.download(part.data(), S.stats, part.size() * sizeof(double)));
+    SF_TRY(S.download(pidx.data(), S.imax, pidx.size() * sizeof(int64_t)));
+    SF_TRY(S.sync());
     std::vector<double> sgn(k, 1.0);
     std::vector<double> hx(k, 0.0);
     std::vector<int64_t> at_row(k, -1);
@@ -894,15 +1026,15 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
         }
         if (at >= 0 && at < n) {
             at_row[j] = at;
-            SF_HIP(hipMemcpyAsync(&hx[j], Xr + at * k + j, sizeof(double), hipMemcpyDeviceToHost, s));
+            SF_TRY(S.download(&hx[j], Xr + at * k + j, sizeof(double)));
         }
     }
-    SF_HIP(hipStreamSynchronize(s));
+    SF_TRY(S.sync());
     for (int j = 0; j < k; ++j) sgn[j] = (at_row[j] >= 0 && hx[j] < 0) ? -1.0 : 1.0;
-    SF_HIP(hipMemcpyAsync(S.theta, sgn.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    SF_TRY(S.upload(S.theta, sgn.data(), k * sizeof(double)));
     k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, scale, H);
     SF_HIP(hipGetLastError());
-    SF_HIP(hipStreamSynchronize(s));
+    SF_TRY(S.sync());
     for (int i = 0; i < k; ++i) eigvals[i] = th[i];
     if (info) {
         info->max_rel_residual = worst;

@@ -239,6 +239,10 @@ static void free_graph(sfairsc_graph* g) {
     w.small.release();
     w.Q.release();
     w.X.release();
+    w.opart.release();
+    w.osmall.release();
+    if (w.pin) (void)hipHostFree(w.pin);
+    w.pin = nullptr;
     auto& k = g->km;
     k.d2.release();
     k.cs.release();

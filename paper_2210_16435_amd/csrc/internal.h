@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/sfairsc.h"
+#include "ortho.h"
 #include "symeig.h"
 
 namespace sfairsc {
@@ -68,7 +69,14 @@ struct EigWork {
     DevBuf small;   // H1, H2, Gram, R, Rinv, coupling, flags ...
     DevBuf Q;       // ld x ld restart / rotation matrix
     DevBuf X;       // n x kMaxK output staging
-    std::vector<double> hostT, hostQ;
+    DevBuf opart;   // partial sums of the matrix-core passes
+    DevBuf osmall;  // their reduced sums and coefficient matrices
+    // Pinned host staging for host-to-device uploads: a pageable source may
+    // be read by the DMA engine after hipMemcpyAsync returns, so every
+    // upload is first copied here and the region is only reused after the
+    // stream has been synchronised.
+    double* pin = nullptr;
+    size_t pin_cap = 0, pin_off = 0;
 };
 
 struct KmWork {
@@ -113,6 +121,18 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy,
 
 // X <- P X = X - C (C^T C)^{-1} C^T X in place (X double, ldx, b <= 32).
 int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
+
+// The operator up to (not including) the output deflation: projection, SpMM
+// with its C^T T epilogue and the deflation table.  Y = T - C R_out (row i:
+// T_i - c_i rtab[g_i]) is left to the caller (fused into its next pass).
+struct OpOut {
+    const void* t;       // n x BW compact, float if is_float else double
+    bool is_float;
+    int BW;
+    const double* rtab;  // [h][32]
+};
+int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
+               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out);
 
 // Raw sparse product T = L X (no projection), X/T compact row-major n x b.
 int op_spmm_raw(sfairsc_graph* g, const void* X, void* T, int b, int mixed,

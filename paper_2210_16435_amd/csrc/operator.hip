@@ -190,12 +190,28 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
         VT acc[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[v] = VT(0);
-        for (int32_t e = a + slot; e < e_end; e += NS) {
-            const int32_t j = col[e];
-            const VT w = val[e];
-            V x = V::load(X + (int64_t)j * BW + cl * VEC);
+        // 64 nonzeros per chunk: one coalesced load of their columns and
+        // values, then all gathers of the chunk issued back to back.
+        for (int32_t base = a; base < e_end; base += 64) {
+            const int cnt = min(64, e_end - base);
+            const int32_t my_col = lane < cnt ? col[base + lane] : 0;
+            const VT my_val = lane < cnt ? val[base + lane] : VT(0);
+            V x[64 / NS];
+            VT w[64 / NS];
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] += w * x.v[v];
+            for (int it = 0; it < 64 / NS; ++it) {
+                const int src = it * NS + slot;
+                const int32_t j = __shfl(my_col, src);
+                w[it] = __shfl(my_val, src);
+                if (src < cnt)
+                    x[it] = V::load(X + (int64_t)j * BW + cl * VEC);
+                else
+                    x[it] = V{};
+            }
+#pragma unroll
+            for (int it = 0; it < 64 / NS; ++it)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) acc[v] += w[it] * x[it].v[v];
         }
 #pragma unroll
         for (int off = LPR; off < 64; off <<= 1)
@@ -286,8 +302,8 @@ static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* 
 #undef SF_SPMM_CASE
 }
 
-int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
-             hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
+int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
+               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
     SF_TRY(ensure_op(g));
     OpWork& w = g->op;
@@ -311,10 +327,6 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<float>(g, BW, xp, t, g->val32, g->diag32, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
-        k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
-                                                   nullptr, Rout, skip);
-        k_defl_apply<float><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>(t, BW, b, n, g->grp, g->cs, Rout, Y, ldy,
-                                                                         skip);
     } else {
         double* xp = w.xp.as<double>();
         double* t = w.t.as<double>();
@@ -322,11 +334,29 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<double>(g, BW, xp, t, g->val64, g->diag64, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
-        k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
-                                                   nullptr, Rout, skip);
-        k_defl_apply<double><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>(t, BW, b, n, g->grp, g->cs, Rout, Y, ldy,
-                                                                          skip);
     }
+    // U = G^{-1} (C^T T - sigma S), R_out table
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
+                                               nullptr, Rout, skip);
+    SF_HIP(hipGetLastError());
+    out->t = w.t.p;
+    out->is_float = mixed != 0;
+    out->BW = BW;
+    out->rtab = Rout;
+    return SFAIRSC_OK;
+}
+
+int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
+             hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
+    OpOut o;
+    SF_TRY(op_apply_t(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, &o));
+    const int64_t n = g->n;
+    if (o.is_float)
+        k_defl_apply<float><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const float*)o.t, o.BW, b, n, g->grp, g->cs,
+                                                                         o.rtab, Y, ldy, skip);
+    else
+        k_defl_apply<double><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const double*)o.t, o.BW, b, n, g->grp,
+                                                                          g->cs, o.rtab, Y, ldy, skip);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }

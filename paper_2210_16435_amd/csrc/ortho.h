@@ -1,0 +1,43 @@
+// Block orthogonalisation of one Krylov expansion on the matrix cores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sfairsc {
+
+struct OrthoArgs {
+    double* V;          // basis, row-major n x ld
+    int ld;
+    int64_t n;
+    int cv;             // columns [0, cv) to orthogonalise against (incl. V_next)
+    int b;              // block width; the new block lands in V[:, cv : cv + b]
+    const void* t;      // sparse-product output (compact n x BW)
+    bool t_is_float;
+    int BW;
+    const int32_t* grp;
+    const double* cs;   // d^{-1/2} or nullptr
+    const double* rtab; // deflation table [h][32]
+    double* T;          // projected matrix (device, ldt x ldt)
+    int ldt;
+    double thresh;      // Cholesky pivot threshold (rank deficiency)
+    double* part;       // partial sums, ortho_part_doubles(n)
+    double* small;      // ortho_small_doubles()
+    double* gsave;      // b x b Gram of the failed block (repair path)
+    double* rc;         // coupling R (b x b) on success
+    int* flag;          // flag[0] = failure, flag[1] = its column,
+                        // flag[2] = 1 (first Cholesky) or 2 (second)
+    hipStream_t stream;
+};
+
+size_t ortho_part_doubles(int64_t n);
+size_t ortho_small_doubles();
+
+// R1 (b x b, the first Cholesky factor of the last expansion) inside `small`.
+double* ortho_r1(double* small);
+
+// Passes A-D of the expansion (see ortho.hip).  Asynchronous.
+int ortho_expand(const OrthoArgs& a);
+
+}  // namespace sfairsc

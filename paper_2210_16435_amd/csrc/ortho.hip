@@ -1,0 +1,525 @@
+// Tall-skinny block orthogonalisation on the FP64 matrix cores (gfx950
+// v_mfma_f64_16x16x4f64).  One Krylov expansion (block classical
+// Gram-Schmidt twice, then Cholesky-QR twice) runs as four row passes over
+// the row-major basis V (n x ld):
+//
+//   A  Y0 = T - C G^{-1}(C^T T - sigma S)  (deflation, Section 3.4), stored in
+//      the Y slot;  partial H1 = V[:, 0:cv]^T Y0
+//   B  Y' = [V | Y0] [-H1; I];  partial [H2; G] = [V | Y']^T Y'
+//   C  Y1 = [V | Y'] [-H2 R1^{-1}; R1^{-1}],  R1^T R1 = G;
+//      partial G2 = Y1^T Y1
+//   D  Y2 = Y1 R2^{-1},  R2^T R2 = G2            (the next block V_next)
+//
+// so that Y0 = V (H1 + H2) + Y2 (R2 R1): the projected matrix gets the
+// column block H1 + H2 and the coupling is R = R2 R1.
+//
+// MFMA operand layout (measured on gfx950): A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k, D[i][j] in lane j + 16 (i % 4), register i / 4.
+//  * Gram products (K = rows): lane (i, k) loads V[row0 + k][c0 + i], four
+//    rows of 16 consecutive columns per instruction (coalesced).
+//  * Updates (K = columns): lane (i, g) loads 4 consecutive columns
+//    V[row0 + i][c0 + 4g .. 4g + 3] as one 32-byte load and feeds four MFMAs;
+//    step s uses columns {c0 + 4g + s}, so the B operand reads the matching
+//    rows of the coefficient matrix.  The update's D register q holds rows
+//    4q..4q+3 in exactly the operand layout of a Gram step, so the new block
+//    feeds the following Gram/Syrk products straight from registers.
+//
+// Each block has 4 waves; a wave owns 16-row tiles (grid-stride) and keeps
+// its products in registers; the 4 waves add into LDS in a fixed order and
+// the block writes one partial (tile layout: [tile][lane][4]).  Partials are
+// summed in block order by k_tile_reduce: bitwise reproducible results.
+#include <algorithm>
+
+#include "internal.h"
+#include "ortho.h"
+
+namespace sfairsc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kOrThreads = 256;
+constexpr int kOrWaves = kOrThreads / 64;
+constexpr int kMaxRT = (kLdMax + 15) / 16;  // 14 row tiles of the Gram products
+
+// Sum the 4 waves' register tiles (ntile tiles of 64 x d4) in LDS in wave
+// order and write the block partial.
+template <int NT>
+__device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, double* lds, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < kOrWaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t < ntile) {
+                    double* p = lds + ((size_t)t * 64 + lane) * 4;
+                    if (w == 0) {
+                        p[0] = acc[t][0];
+                        p[1] = acc[t][1];
+                        p[2] = acc[t][2];
+                        p[3] = acc[t][3];
+                    } else {
+                        p[0] += acc[t][0];
+                        p[1] += acc[t][1];
+                        p[2] += acc[t][2];
+                        p[3] += acc[t][3];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
+}
+
+// Pass A.  Y0 from the sparse product T (compact stride BW, type TT) and the
+// deflation table Rtab; partial V[:, 0:cv]^T Y0 (nrt x BJ tiles).
+template <int BJ, class TT>
+__global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, int ld, int64_t n, int cv, int b,
+                                                        const TT* __restrict__ T, int BW,
+                                                        const int32_t* __restrict__ grp,
+                                                        const double* __restrict__ cs,
+                                                        const double* __restrict__ Rtab, double* __restrict__ part,
+                                                        const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nrt = (cv + 15) >> 4;
+    d4 acc[kMaxRT * BJ];
+#pragma unroll
+    for (int t = 0; t < kMaxRT * BJ; ++t) acc[t] = d4{0, 0, 0, 0};
+    const int64_t ntiles = (n + 15) >> 4;
+    const int64_t wstride = (int64_t)gridDim.x * kOrWaves;
+    for (int64_t tile = (int64_t)blockIdx.x * kOrWaves + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = tile * 16 + q * 4 + lk;
+            const bool rv = row < n;
+            double y[BJ];
+            const double c = (rv && cs) ? cs[row] : 1.0;
+            const int gi = rv ? grp[row] : 0;
+#pragma unroll
+            for (int jt = 0; jt < BJ; ++jt) {
+                const int col = jt * 16 + li;
+                double v = 0.0;
+                if (rv && col < b) {
+                    v = (double)T[row * BW + col] - c * Rtab[gi * 32 + col];
+                    V[row * ld + cv + col] = v;
+                }
+                y[jt] = v;
+            }
+#pragma unroll
+            for (int rt = 0; rt < kMaxRT; ++rt) {
+                if (rt < nrt) {
+                    const int col = rt * 16 + li;
+                    const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+#pragma unroll
+                    for (int jt = 0; jt < BJ; ++jt) acc[rt * BJ + jt] = mfma(a, y[jt], acc[rt * BJ + jt]);
+                }
+            }
+        }
+    }
+    block_store_tiles(acc, nrt * BJ, lds, part + (size_t)blockIdx.x * nrt * BJ * 256);
+}
+
+// Passes B, C, D.  Ynew = In M with In = V[:, coff : coff + kin] (kin a
+// multiple of 4) and M (kin x b, row-major) staged in LDS; Ynew replaces
+// V[:, yoff : yoff + b].
+//   GRAM: partial [V[:, 0:cv]^T Ynew (nrt x BJ tiles); Ynew^T Ynew (BJ x BJ)]
+//   SYRK: partial Ynew^T Ynew
+template <int BJ, bool GRAM, bool SYRK>
+__global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V, int ld, int64_t n, int coff,
+                                                          int kin, int yoff, int b, int cv,
+                                                          const double* __restrict__ M, double* __restrict__ part,
+                                                          const int* skip) {
+    if (skip && *skip) return;
+    extern __shared__ double lds[];
+    double* Ms = lds;                                   // [kin][BJ * 16]
+    const int mld = BJ * 16;
+    for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
+        const int r = e / mld, j = e - r * mld;
+        Ms[e] = j < b ? M[r * b + j] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nrt = GRAM ? (cv + 15) >> 4 : 0;
+    constexpr int NG = GRAM ? kMaxRT * BJ : 1;
+    d4 accg[NG];
+    d4 accs[BJ * BJ];
+#pragma unroll
+    for (int t = 0; t < NG; ++t) accg[t] = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < BJ * BJ; ++t) accs[t] = d4{0, 0, 0, 0};
+    const int64_t ntiles = (n + 15) >> 4;
+    const int64_t wstride = (int64_t)gridDim.x * kOrWaves;
+    for (int64_t tile = (int64_t)blockIdx.x * kOrWaves + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
+        const int64_t row0 = tile * 16;
+        // update: D[jt] (16 rows x 16 cols) = In(rows) M
+        d4 D[BJ];
+#pragma unroll
+        for (int jt = 0; jt < BJ; ++jt) D[jt] = d4{0, 0, 0, 0};
+        {
+            const int64_t row = row0 + li;
+            const bool rv = row < n;
+            const double* src = V + row * ld + coff + 4 * lk;
+#pragma unroll 2
+            for (int c0 = 0; c0 < kin; c0 += 16) {
+                double4 x = make_double4(0, 0, 0, 0);
+                if (rv && c0 + 4 * lk < kin) x = *reinterpret_cast<const double4*>(src + c0);
+                const double xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int kr = c0 + 4 * lk + s;
+                    const double* mrow = Ms + (size_t)(kr < kin ? kr : 0) * mld;
+#pragma unroll
+                    for (int jt = 0; jt < BJ; ++jt) {
+                        const double bm = kr < kin ? mrow[jt * 16 + li] : 0.0;
+                        D[jt] = mfma(xs[s], bm, D[jt]);
+                    }
+                }
+            }
+        }
+        // store Ynew: lane holds rows row0 + 4q + lk, column jt*16 + li
+        const int col_in_tile = li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = row0 + 4 * q + lk;
+            if (row < n) {
+#pragma unroll
+                for (int jt = 0; jt < BJ; ++jt) {
+                    const int col = jt * 16 + col_in_tile;
+                    if (col < b) V[row * ld + yoff + col] = D[jt][q];
+                }
+            }
+        }
+        // Gram and Syrk from registers (rows past n hold zeros)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (GRAM) {
+                const int64_t row = row0 + 4 * q + lk;
+                const bool rv = row < n;
+#pragma unroll
+                for (int rt = 0; rt < kMaxRT; ++rt) {
+                    if (rt < nrt) {
+                        const int col = rt * 16 + li;
+                        const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+#pragma unroll
+                        for (int jt = 0; jt < BJ; ++jt) accg[rt * BJ + jt] = mfma(a, D[jt][q], accg[rt * BJ + jt]);
+                    }
+                }
+            }
+            if (GRAM || SYRK) {
+#pragma unroll
+                for (int i1 = 0; i1 < BJ; ++i1)
+#pragma unroll
+                    for (int i2 = 0; i2 < BJ; ++i2) accs[i1 * BJ + i2] = mfma(D[i1][q], D[i2][q], accs[i1 * BJ + i2]);
+            }
+        }
+    }
+    if (GRAM || SYRK) {
+        __syncthreads();  // Ms no longer needed: reuse LDS for the block sums
+        const size_t gsz = (size_t)nrt * BJ * 256;
+        if (GRAM) block_store_tiles(accg, nrt * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256));
+        __syncthreads();
+        block_store_tiles(accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256) + gsz);
+    }
+}
+
+// Sum per-block partials (tile layout) in block order: out[e] = sum_b part[b][e].
+__global__ __launch_bounds__(1024) void k_tile_reduce(const double* __restrict__ part, int nblk, int O,
+                                                       double* __restrict__ out, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double red[1024];
+    const int el = threadIdx.x & 255, sub = threadIdx.x >> 8;  // 256 elements x 4 slices
+    const int e = blockIdx.x * 256 + el;
+    double s = 0.0;
+    if (e < O)
+        for (int blk = sub; blk < nblk; blk += 4) s += part[(size_t)blk * O + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (sub == 0 && e < O) out[e] = (red[el] + red[256 + el]) + (red[512 + el] + red[768 + el]);
+}
+
+// Element (i, j) of a tile-layout matrix with BJ column tiles.
+__device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
+    const int tile = (i >> 4) * BJ + (j >> 4);
+    const int ii = i & 15, jj = j & 15;
+    return t[((size_t)tile * 64 + jj + 16 * (ii & 3)) * 4 + (ii >> 2)];
+}
+
+// Block Cholesky helper on G (b x b, LDS): R upper with G = R^T R, returns
+// false if a pivot is <= thresh.  All threads participate.
+__device__ bool block_cholesky(double* G, double* R, int b, double thresh, int* bad) {
+    const int t = threadIdx.x;
+    if (t == 0) *bad = 0;
+    for (int e = t; e < b * b; e += blockDim.x) R[e] = 0.0;
+    __syncthreads();
+    for (int k = 0; k < b; ++k) {
+        if (t == 0) {
+            double piv = G[k * b + k];
+            if (!(piv > thresh)) {
+                *bad = 1;
+                piv = 1.0;
+            }
+            R[k * b + k] = sqrt(piv);
+        }
+        __syncthreads();
+        if (t > k && t < b) R[k * b + t] = G[k * b + t] / R[k * b + k];
+        __syncthreads();
+        for (int e = t; e < b * b; e += blockDim.x) {
+            const int i = e / b, j = e - i * b;
+            if (i > k && j >= i) G[i * b + j] -= R[k * b + i] * R[k * b + j];
+        }
+        __syncthreads();
+    }
+    return *bad == 0;
+}
+
+// Upper-triangular inverse (columns by back substitution), into Ri (LDS).
+__device__ void block_triinv(const double* R, double* Ri, int b) {
+    const int j = threadIdx.x;
+    if (j < b) {
+        for (int i = b - 1; i >= 0; --i) {
+            double s = (i == j) ? 1.0 : 0.0;
+            if (i <= j) {
+                for (int q = i + 1; q <= j; ++q) s -= R[i * b + q] * Ri[q * b + j];
+                Ri[i * b + j] = s / R[i * b + i];
+            } else {
+                Ri[i * b + j] = 0.0;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// After pass A: H1 (cv x b) from the summed tiles -> M1 = [-H1; I]
+// ((cv + b) x b) and T[0:cv, cact:cact+b] = H1 (and the mirror for q < cact).
+__global__ __launch_bounds__(1024) void k_fin_a(const double* __restrict__ sumA, int BJ, int cv, int b,
+                                                 double* __restrict__ H1, double* __restrict__ M1,
+                                                 double* __restrict__ T, int ldt, int cact, const int* skip) {
+    if (skip && *skip) return;
+    for (int e = threadIdx.x; e < (cv + b) * b; e += blockDim.x) {
+        const int q = e / b, j = e - q * b;
+        if (q < cv) {
+            const double h = tile_at(sumA, BJ, q, j);
+            H1[e] = h;
+            M1[e] = -h;
+            T[(size_t)q * ldt + cact + j] = h;
+            if (q < cact) T[(size_t)(cact + j) * ldt + q] = h;
+        } else {
+            M1[e] = (q - cv == j) ? 1.0 : 0.0;
+        }
+    }
+}
+
+// After pass B: H2 and G = Y'^T Y' from the summed tiles.  T column block
+// += H2 (and mirror), diagonal block symmetrised; R1 = chol(G) (pivot test
+// against thresh: flag[0] = 1, flag[1] = cact on failure; G saved for the
+// repair path); M2 = [-H2 R1^{-1}; R1^{-1}].  (H2 is O(eps) relative to the
+// first projection, so G - H2^T H2 and G differ at rounding level; the second
+// Cholesky-QR pass absorbs the difference.)
+__global__ __launch_bounds__(1024) void k_fin_b(const double* __restrict__ sumB, int BJ, int cv, int b,
+                                                 double thresh, double* __restrict__ M2, double* __restrict__ R1g,
+                                                 double* __restrict__ Gsave, double* __restrict__ T, int ldt,
+                                                 int cact, int* flag, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double G[kMaxBlock * kMaxBlock];
+    __shared__ double R[kMaxBlock * kMaxBlock];
+    __shared__ double Ri[kMaxBlock * kMaxBlock];
+    __shared__ int bad;
+    const int nrt = (cv + 15) >> 4;
+    const double* gt = sumB + (size_t)nrt * BJ * 256;
+    for (int e = threadIdx.x; e < cv * b; e += blockDim.x) {
+        const int q = e / b, j = e - q * b;
+        const double h = tile_at(sumB, BJ, q, j);
+        T[(size_t)q * ldt + cact + j] += h;
+        if (q < cact) T[(size_t)(cact + j) * ldt + q] += h;
+    }
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e - i * b;
+        const double g = tile_at(gt, BJ, i, j);
+        G[e] = g;
+        Gsave[e] = g;
+    }
+    __syncthreads();  // T updates (global, this workgroup) and G visible
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e - i * b;
+        if (j > i) {
+            double* a = T + (size_t)(cact + i) * ldt + cact + j;
+            double* c = T + (size_t)(cact + j) * ldt + cact + i;
+            const double m = 0.5 * (*a + *c);
+            *a = m;
+            *c = m;
+        }
+    }
+    if (!block_cholesky(G, R, b, thresh, &bad)) {
+        if (threadIdx.x == 0) {
+            flag[0] = 1;
+            flag[1] = cact;
+            flag[2] = 1;
+        }
+        return;
+    }
+    block_triinv(R, Ri, b);
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) R1g[e] = R[e];
+    for (int e = threadIdx.x; e < (cv + b) * b; e += blockDim.x) {
+        const int q = e / b, j = e - q * b;
+        double s;
+        if (q < cv) {
+            s = 0.0;
+            for (int t = 0; t <= j; ++t) s -= tile_at(sumB, BJ, q, t) * Ri[t * b + j];
+        } else {
+            s = Ri[(q - cv) * b + j];
+        }
+        M2[e] = s;
+    }
+}
+
+// After pass C: R2 = chol(G2) (sum of partials, direct), M3 = R2^{-1},
+// coupling Rc = R2 R1.
+__global__ __launch_bounds__(1024) void k_fin_c(const double* __restrict__ part, int nblk, int BJ, int b,
+                                                 const double* __restrict__ R1g, double* __restrict__ M3,
+                                                 double* __restrict__ Rc, double* __restrict__ Gsave, int cact,
+                                                 int* flag, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double G[kMaxBlock * kMaxBlock];
+    __shared__ double R[kMaxBlock * kMaxBlock];
+    __shared__ double Ri[kMaxBlock * kMaxBlock];
+    __shared__ double red[1024];
+    __shared__ int bad;
+    const int O = BJ * BJ * 256;  // <= 1024
+    const int P = 1024 / O;
+    {
+        const int e = threadIdx.x % O, sub = threadIdx.x / O;
+        double s = 0.0;
+        if (sub < P)
+            for (int blk = sub; blk < nblk; blk += P) s += part[(size_t)blk * O + e];
+        red[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < O) {
+        double s = 0.0;
+        for (int q = 0; q < P; ++q) s += red[q * O + threadIdx.x];
+        red[threadIdx.x] = s;  // own slot: slices q >= 1 live at higher indices
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e - i * b;
+        G[e] = tile_at(red, BJ, i, j);
+        Gsave[e] = G[e];
+    }
+    __syncthreads();
+    if (!block_cholesky(G, R, b, 0.25, &bad)) {
+        if (threadIdx.x == 0) {
+            flag[0] = 1;
+            flag[1] = cact;
+            flag[2] = 2;
+        }
+        return;
+    }
+    block_triinv(R, Ri, b);
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e - i * b;
+        M3[e] = Ri[e];
+        double s = 0.0;
+        for (int q = i; q <= j; ++q) s += R[i * b + q] * R1g[q * b + j];
+        Rc[e] = j >= i ? s : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static int nblk_for(int64_t n) {
+    const int64_t ntiles = (n + 15) / 16;
+    int64_t g = (ntiles + kOrWaves * 3 - 1) / (kOrWaves * 3);  // about 3 tiles per wave
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 240));
+}
+
+size_t ortho_part_doubles(int64_t n) {
+    return (size_t)nblk_for(n) * ((size_t)kMaxRT * 2 * 256 + 4 * 256);
+}
+
+double* ortho_r1(double* small) {
+    return small + (size_t)(kMaxRT * 2 + 4) * 256 * 2 + (size_t)kLdMax * kMaxBlock * 3;
+}
+
+size_t ortho_small_doubles() {
+    // sumA, sumB tiles; H1; M1, M2 ((ld) x 32); R1; M3; Gsave
+    return (size_t)(kMaxRT * 2 + 4) * 256 * 2 + (size_t)kLdMax * kMaxBlock * 3 + 4 * kMaxBlock * kMaxBlock;
+}
+
+template <class TT>
+static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int cv, int b,
+                     const TT* T, int BW, const int32_t* grp, const double* cs, const double* Rtab, double* part,
+                     const int* skip) {
+    if (BJ == 1)
+        k_pass_a<1, TT><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, part, skip);
+    else
+        k_pass_a<2, TT><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, part, skip);
+}
+
+template <bool GRAM, bool SYRK>
+static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
+                       int yoff, int b, int cv, const double* M, double* part, const int* skip) {
+    if (BJ == 1)
+        k_pass_upd<1, GRAM, SYRK><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip);
+    else
+        k_pass_upd<2, GRAM, SYRK><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip);
+}
+
+int ortho_expand(const OrthoArgs& a) {
+    const int b = a.b, cv = a.cv, BJ = b > 16 ? 2 : 1;
+    const int64_t n = a.n;
+    if (cv % 4 != 0 || a.ld % 4 != 0 || cv + 2 * b > a.ld + b || cv > kLdMax)
+        return set_error(SFAIRSC_E_ARG, "internal: bad orthogonalisation shape cv=%d ld=%d b=%d", cv, a.ld, b);
+    const int nblk = nblk_for(n);
+    const int nrt = (cv + 15) / 16;
+    hipStream_t s = a.stream;
+    double* sumA = a.small;
+    double* sumB = sumA + (size_t)(kMaxRT * 2 + 4) * 256;
+    double* H1 = sumB + (size_t)(kMaxRT * 2 + 4) * 256;
+    double* M1 = H1 + (size_t)kLdMax * kMaxBlock;
+    double* M2 = M1 + (size_t)kLdMax * kMaxBlock;
+    double* R1 = M2 + (size_t)kLdMax * kMaxBlock;
+    double* M3 = R1 + kMaxBlock * kMaxBlock;
+    const int cact = cv - b;
+
+    // pass A
+    const int OA = nrt * BJ * 256;
+    size_t ldsA = (size_t)OA * sizeof(double);
+    if (a.t_is_float)
+        launch_a<float>(BJ, nblk, ldsA, s, a.V, a.ld, n, cv, b, (const float*)a.t, a.BW, a.grp, a.cs, a.rtab, a.part,
+                        a.flag);
+    else
+        launch_a<double>(BJ, nblk, ldsA, s, a.V, a.ld, n, cv, b, (const double*)a.t, a.BW, a.grp, a.cs, a.rtab,
+                         a.part, a.flag);
+    k_tile_reduce<<<(OA + 255) / 256, 1024, 0, s>>>(a.part, nblk, OA, sumA, a.flag);
+    k_fin_a<<<1, 1024, 0, s>>>(sumA, BJ, cv, b, H1, M1, a.T, a.ldt, cact, a.flag);
+
+    // pass B: Y' = [V | Y0] M1, Gram + Syrk
+    const int kin = cv + b;
+    const int OB = (nrt * BJ + BJ * BJ) * 256;
+    size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)nrt * BJ * 256) * sizeof(double);
+    launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, M1, a.part, a.flag);
+    k_tile_reduce<<<(OB + 255) / 256, 1024, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
+    k_fin_b<<<1, 1024, 0, s>>>(sumB, BJ, cv, b, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag);
+
+    // pass C: Y1 = [V | Y'] M2, Syrk
+    size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
+    launch_upd<false, true>(BJ, nblk, ldsC, s, a.V, a.ld, n, 0, kin, cv, b, cv, M2, a.part, a.flag);
+    k_fin_c<<<1, 1024, 0, s>>>(a.part, nblk, BJ, b, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag);
+
+    // pass D: Y2 = Y1 R2^{-1}
+    size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
+    launch_upd<false, false>(BJ, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, b, cv, M3, nullptr, a.flag);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+}  // namespace sfairsc
