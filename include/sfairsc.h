@@ -168,6 +168,8 @@ typedef struct sfairsc_eigs_info {
     double gap_ratio;          /* (theta_{k+1} - theta_k) / sigma, last RR */
     double phase1_ms;          /* mixed precision: host wall time of the
                                   FP32-SpMM phase; 0 otherwise             */
+    double rr_ms;              /* host time spent in Rayleigh-Ritz (small
+                                  dense eigensolves), all phases           */
 } sfairsc_eigs_info;
 
 /* Fill *opts with the defaults (all automatic, seed 0, certify 1). */

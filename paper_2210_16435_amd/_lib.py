@@ -88,6 +88,7 @@ class EigsInfo(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("gap_ratio", ctypes.c_double),
         ("phase1_ms", ctypes.c_double),
+        ("rr_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -103,6 +104,7 @@ class EigsInfo(ctypes.Structure):
             "sigma": self.sigma,
             "gap_ratio": self.gap_ratio,
             "phase1_ms": self.phase1_ms,
+            "rr_ms": self.rr_ms,
         }
 
 

@@ -421,6 +421,7 @@ struct Solver {
     bool mixed;
     double sigma;
     double* V;
+    double* V2;
     double* T;
     double* part;
     int nblk;
@@ -439,6 +440,8 @@ struct Solver {
         EigWork& w = g->eig;
         ld = ncv + b;
         SF_TRY(w.V.ensure((size_t)n * ld * sizeof(double)));
+        SF_TRY(w.V2.ensure((size_t)n * ld * sizeof(double)));
+        V2 = w.V2.as<double>();
         SF_TRY(w.T.ensure((size_t)ld * ld * sizeof(double)));
         nblk = grid_for(n, kTsRows, kTsMaxBlocks);
         SF_TRY(w.part.ensure((size_t)nblk * (size_t)ld * kMaxBlock * sizeof(double)));
@@ -767,8 +770,8 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int sta
 struct KsResult {
     std::vector<double> theta;  // Ritz values of the last Rayleigh-Ritz
     std::vector<double> res;    // residual estimates
-    std::vector<double> Z;      // c x c eigenvectors (row-major)
-    int c = 0;
+    std::vector<double> Z;      // c x m Ritz vectors (row-major), m >= k
+    int c = 0, m = 0;
     bool converged = false;
 };
 
@@ -795,6 +798,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     }
     int repairs = 0;
     std::vector<double> hT, Z, w, Rc(b * b);
+    SymEigSel sel;
     for (int restart = 0;; ++restart) {
         // expansions
         while (c + b <= ncv) {
@@ -828,15 +832,31 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
                 hT[i * c + j] = m;
                 hT[j * c + i] = m;
             }
-        w.resize(c);
-        Z.resize((size_t)c * c);
-        sym_eig(c, hT.data(), w.data(), Z.data());
-        std::vector<double> res(c);
-        for (int i = 0; i < c; ++i) {
+        // Rayleigh-Ritz: all Ritz values, then Ritz vectors only for the
+        // wanted pairs and those kept at a restart
+        int p = 0, m = k;
+        {
+            auto t0 = std::chrono::steady_clock::now();
+            sel.reduce(c, hT.data());
+            w = sel.w;
+            p = keep_opt > 0 ? keep_opt : std::max(k + b, k + (c - k) / 2);
+            p = std::min(p, ncv - b);
+            p = std::max(p, std::min(k, ncv - b));
+            while (p < ncv - b && p < c && std::fabs(w[p] - w[p - 1]) <= 1e-10 * S.sigma) ++p;
+            p = std::min((p + 3) & ~3, ncv - b);  // keeps every later column offset a multiple of 4
+            m = std::min(c, std::max(p, k));
+            Z.resize((size_t)c * m);
+            sel.vectors(m, Z.data());
+            if (S.info)
+                S.info->rr_ms +=
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        std::vector<double> res(m);
+        for (int i = 0; i < m; ++i) {
             double ss = 0.0;
             for (int r = 0; r < b; ++r) {
                 double acc = 0.0;
-                for (int q = r; q < b; ++q) acc += Rc[r * b + q] * Z[(size_t)(c - b + q) * c + i];
+                for (int q = r; q < b; ++q) acc += Rc[r * b + q] * Z[(size_t)(c - b + q) * m + i];
                 ss += acc * acc;
             }
             res[i] = std::sqrt(ss);
@@ -853,21 +873,23 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         out.res = res;
         out.Z = Z;
         out.c = c;
+        out.m = m;
         out.converged = nconv == k;
         if (out.converged || restart + 1 >= max_restarts) return SFAIRSC_OK;
-        // thick restart: keep p Ritz vectors
-        int p = keep_opt > 0 ? keep_opt : std::max(k + b, k + (c - k) / 2);
-        p = std::min(p, ncv - b);
-        p = std::max(p, std::min(k, ncv - b));
-        while (p < ncv - b && p < c && std::fabs(w[p] - w[p - 1]) <= 1e-10 * S.sigma) ++p;
-        p = std::min((p + 3) & ~3, ncv - b);  // keeps every later column offset a multiple of 4
-        std::vector<double> Qp((size_t)c * p);
-        for (int t = 0; t < c; ++t)
-            for (int q = 0; q < p; ++q) Qp[(size_t)t * p + q] = Z[(size_t)t * c + q];
+        // Q[:, 0:p] in 32-column slices, then the b x b identity (V_next copy)
+        std::vector<double> Qp((size_t)c * p + (size_t)b * b, 0.0);
+        size_t off = 0;
+        for (int j0 = 0; j0 < p; j0 += 32) {
+            const int wt = std::min(32, p - j0);
+            for (int t = 0; t < c; ++t)
+                for (int q = 0; q < wt; ++q) Qp[off + (size_t)t * wt + q] = Z[(size_t)t * m + j0 + q];
+            off += (size_t)c * wt;
+        }
+        for (int i = 0; i < b; ++i) Qp[off + (size_t)i * b + i] = 1.0;
         SF_TRY(S.upload(S.Q, Qp.data(), Qp.size() * sizeof(double)));
         SF_TRY(S.upload(S.theta, w.data(), p * sizeof(double)));
-        k_rotate<<<grid_for(n, kRotRows, 1024), 256, (size_t)kRotRows * (c + b) * sizeof(double), S.s>>>(
-            S.V, S.ld, n, c, p, b, S.Q, 0, nullptr, 0, nullptr);
+        SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
+        std::swap(S.V, S.V2);
         k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.theta);
         SF_HIP(hipGetLastError());
         c = p;
@@ -879,7 +901,7 @@ static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* 
     const int c = R.c, k = S.k;
     std::vector<double> Qk((size_t)c * k);
     for (int t = 0; t < c; ++t)
-        for (int q = 0; q < k; ++q) Qk[(size_t)t * k + q] = R.Z[(size_t)t * c + q];
+        for (int q = 0; q < k; ++q) Qk[(size_t)t * k + q] = R.Z[(size_t)t * R.m + q];
     SF_TRY(S.upload(S.Q, Qk.data(), Qk.size() * sizeof(double)));
     k_rotate<<<grid_for(S.n, kRotRows, 1024), 256, (size_t)kRotRows * (c + S.b) * sizeof(double), S.s>>>(
         S.V, S.ld, S.n, c, k, S.b, S.Q, 1, Xo, k, scale);
@@ -969,12 +991,12 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
             // the start block (block width at least k)
             S.mixed = false;
             const int b2 = std::max(b, k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32);
-            if (b2 != b) {
-                S.b = b2;
-                S.ncv = std::min(kMaxBasis, std::max(ncv, k + 4 * b2));
-                S.ncv = (S.ncv / b2) * b2;
-                while (S.ncv + 2 * b2 > dim && S.ncv > b2) S.ncv -= b2;
-            }
+            // The start block already holds the k Ritz vectors to about the
+            // float floor, so a short basis suffices before the first
+            // Rayleigh-Ritz check.
+            S.b = b2;
+            S.ncv = std::min(kMaxBasis, 3 * b2);
+            while (S.ncv + 2 * b2 > dim && S.ncv > b2) S.ncv -= b2;
             // Xr holds the k Ritz vectors, row-major n x k: the start block
             SF_TRY(run_ks(S, tol, max_restarts, o.keep, Xr, k, o.seed + 1, R));
             SF_TRY(ritz_vectors(S, R, Xr, nullptr));

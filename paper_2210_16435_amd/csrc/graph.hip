@@ -234,6 +234,7 @@ static void free_graph(sfairsc_graph* g) {
     if (o.ev1) (void)hipEventDestroy(o.ev1);
     auto& w = g->eig;
     w.V.release();
+    w.V2.release();
     w.T.release();
     w.part.release();
     w.small.release();

@@ -64,6 +64,7 @@ struct OpWork {
 // Workspace of the Krylov-Schur solver.
 struct EigWork {
     DevBuf V;       // n x ld basis (row-major), double
+    DevBuf V2;      // second basis buffer (restart rotation target)
     DevBuf T;       // ld x ld projected matrix, double
     DevBuf part;    // tall-skinny partial sums
     DevBuf small;   // H1, H2, Gram, R, Rinv, coupling, flags ...

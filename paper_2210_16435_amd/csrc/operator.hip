@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "reduce.h"
 
 namespace sfairsc {
 
@@ -94,11 +95,20 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     const int P = kFinThreads / O;    // threads per output
     const int t = threadIdx.x;
     {
+        // four independent accumulators keep several partial loads in flight
         const int o = t % O, sub = t / O;
-        double s = 0.0;
-        if (sub < P)
-            for (int blk = sub; blk < nblk; blk += P) s += part[(size_t)blk * O + o];
-        red[t] = s;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (sub < P) {
+            int blk = sub;
+            for (; blk + 3 * P < nblk; blk += 4 * P) {
+                s0 += part[(size_t)blk * O + o];
+                s1 += part[(size_t)(blk + P) * O + o];
+                s2 += part[(size_t)(blk + 2 * P) * O + o];
+                s3 += part[(size_t)(blk + 3 * P) * O + o];
+            }
+            for (; blk < nblk; blk += P) s0 += part[(size_t)blk * O + o];
+        }
+        red[t] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     if (t < O) {
@@ -278,7 +288,7 @@ static int ensure_op(sfairsc_graph* g) {
     w.nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
     SF_TRY(w.part_in.ensure((size_t)w.nblk_proj * g->h * 32 * sizeof(double)));
     SF_TRY(w.part_out.ensure((size_t)w.nblk_spmm * g->h * 32 * sizeof(double)));
-    SF_TRY(w.small.ensure((size_t)3 * kMaxGroups * 32 * sizeof(double)));
+    SF_TRY(w.small.ensure((size_t)5 * kMaxGroups * 32 * sizeof(double)));
     SF_TRY(w.xp.ensure((size_t)n * 32 * sizeof(double)));
     SF_TRY(w.t.ensure((size_t)n * 32 * sizeof(double)));
     return SFAIRSC_OK;
@@ -384,8 +394,10 @@ int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
     const int h = g->h;
     k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
         X, ldx, b, g->n, g->grp, g->cs, h, w.part_in.as<double>(), nullptr);
-    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx,
-                                               Rin, nullptr);
+    double* sums = Rin + 4 * kMaxGroups * 32;
+    k_reduce_partials<<<reduce_grid(h * 32), kRedElems * kRedSlices, 0, s>>>(w.part_in.as<double>(), w.nblk_proj,
+                                                                             h * 32, sums, nullptr);
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(sums, 1, h, b, g->gpar, nullptr, 0.0, Sx, Rin, nullptr);
     k_proj_inplace<<<grid_rows(g->n * b, 256, 8192), 256, 0, s>>>(X, ldx, b, g->n, g->grp, g->cs, Rin);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;

@@ -40,4 +40,8 @@ double* ortho_r1(double* small);
 // Passes A-D of the expansion (see ortho.hip).  Asynchronous.
 int ortho_expand(const OrthoArgs& a);
 
+// Thick-restart rotation into a second basis buffer (see ortho.hip).
+int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
+                 hipStream_t s);
+
 }  // namespace sfairsc

@@ -27,11 +27,12 @@
 // Each block has 4 waves; a wave owns 16-row tiles (grid-stride) and keeps
 // its products in registers; the 4 waves add into LDS in a fixed order and
 // the block writes one partial (tile layout: [tile][lane][4]).  Partials are
-// summed in block order by k_tile_reduce: bitwise reproducible results.
+// summed in a fixed order by k_reduce_partials: bitwise reproducible results.
 #include <algorithm>
 
 #include "internal.h"
 #include "ortho.h"
+#include "reduce.h"
 
 namespace sfairsc {
 
@@ -126,16 +127,18 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
     block_store_tiles(acc, nrt * BJ, lds, part + (size_t)blockIdx.x * nrt * BJ * 256);
 }
 
-// Passes B, C, D.  Ynew = In M with In = V[:, coff : coff + kin] (kin a
-// multiple of 4) and M (kin x b, row-major) staged in LDS; Ynew replaces
-// V[:, yoff : yoff + b].
+// Passes B, C, D (and the restart rotation).  Ynew = In M with
+// In = V[:, coff : coff + kin] (kin a multiple of 4) and M (kin x b,
+// row-major) staged in LDS; Ynew replaces Vout[:, yoff : yoff + b] (Vout may
+// be V itself: every row is read completely before it is written, by the
+// same wavefront).
 //   GRAM: partial [V[:, 0:cv]^T Ynew (nrt x BJ tiles); Ynew^T Ynew (BJ x BJ)]
 //   SYRK: partial Ynew^T Ynew
 template <int BJ, bool GRAM, bool SYRK>
-__global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V, int ld, int64_t n, int coff,
-                                                          int kin, int yoff, int b, int cv,
-                                                          const double* __restrict__ M, double* __restrict__ part,
-                                                          const int* skip) {
+__global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
+                                                          int b, int cv, const double* __restrict__ M,
+                                                          double* __restrict__ part, const int* skip, double* Vout,
+                                                          int ldo) {
     if (skip && *skip) return;
     extern __shared__ double lds[];
     double* Ms = lds;                                   // [kin][BJ * 16]
@@ -167,10 +170,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V,
             const int64_t row = row0 + li;
             const bool rv = row < n;
             const double* src = V + row * ld + coff + 4 * lk;
-#pragma unroll 2
-            for (int c0 = 0; c0 < kin; c0 += 16) {
-                double4 x = make_double4(0, 0, 0, 0);
-                if (rv && c0 + 4 * lk < kin) x = *reinterpret_cast<const double4*>(src + c0);
+            auto step = [&](const double4 x, int c0) {
                 const double xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
@@ -182,6 +182,14 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V,
                         D[jt] = mfma(xs[s], bm, D[jt]);
                     }
                 }
+            };
+            // two 16-column chunks per iteration: both loads in flight first
+            for (int c0 = 0; c0 < kin; c0 += 32) {
+                double4 x0 = make_double4(0, 0, 0, 0), x1 = make_double4(0, 0, 0, 0);
+                if (rv && c0 + 4 * lk < kin) x0 = *reinterpret_cast<const double4*>(src + c0);
+                if (rv && c0 + 16 + 4 * lk < kin) x1 = *reinterpret_cast<const double4*>(src + c0 + 16);
+                step(x0, c0);
+                step(x1, c0 + 16);
             }
         }
         // store Ynew: lane holds rows row0 + 4q + lk, column jt*16 + li
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V,
 #pragma unroll
                 for (int jt = 0; jt < BJ; ++jt) {
                     const int col = jt * 16 + col_in_tile;
-                    if (col < b) V[row * ld + yoff + col] = D[jt][q];
+                    if (col < b) Vout[row * ldo + yoff + col] = D[jt][q];
                 }
             }
         }
@@ -230,21 +238,6 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* __restrict__ V,
     }
 }
 
-// Sum per-block partials (tile layout) in block order: out[e] = sum_b part[b][e].
-__global__ __launch_bounds__(1024) void k_tile_reduce(const double* __restrict__ part, int nblk, int O,
-                                                       double* __restrict__ out, const int* skip) {
-    if (skip && *skip) return;
-    __shared__ double red[1024];
-    const int el = threadIdx.x & 255, sub = threadIdx.x >> 8;  // 256 elements x 4 slices
-    const int e = blockIdx.x * 256 + el;
-    double s = 0.0;
-    if (e < O)
-        for (int blk = sub; blk < nblk; blk += 4) s += part[(size_t)blk * O + e];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (sub == 0 && e < O) out[e] = (red[el] + red[256 + el]) + (red[512 + el] + red[768 + el]);
-}
-
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
 __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
     const int tile = (i >> 4) * BJ + (j >> 4);
@@ -252,49 +245,36 @@ __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, 
     return t[((size_t)tile * 64 + jj + 16 * (ii & 3)) * 4 + (ii >> 2)];
 }
 
-// Block Cholesky helper on G (b x b, LDS): R upper with G = R^T R, returns
-// false if a pivot is <= thresh.  All threads participate.
-__device__ bool block_cholesky(double* G, double* R, int b, double thresh, int* bad) {
-    const int t = threadIdx.x;
-    if (t == 0) *bad = 0;
-    for (int e = t; e < b * b; e += blockDim.x) R[e] = 0.0;
-    __syncthreads();
-    for (int k = 0; k < b; ++k) {
-        if (t == 0) {
-            double piv = G[k * b + k];
-            if (!(piv > thresh)) {
-                *bad = 1;
-                piv = 1.0;
-            }
-            R[k * b + k] = sqrt(piv);
+// One wavefront factors a B x B SPD matrix in registers.  Lane j (< B)
+// holds column j of G in g[0..B); on return g holds column j of R
+// (G = R^T R, R upper triangular) and ri column j of R^{-1}.  Returns false
+// (uniformly across the wavefront) if a pivot is <= thresh.
+template <int B>
+__device__ bool wave_chol_inv(double (&g)[B], double (&ri)[B], double thresh) {
+    const int j = threadIdx.x & 63;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        double piv = __shfl(g[k], k);
+        if (!(piv > thresh)) {
+            ok = false;
+            piv = 1.0;
         }
-        __syncthreads();
-        if (t > k && t < b) R[k * b + t] = G[k * b + t] / R[k * b + k];
-        __syncthreads();
-        for (int e = t; e < b * b; e += blockDim.x) {
-            const int i = e / b, j = e - i * b;
-            if (i > k && j >= i) G[i * b + j] -= R[k * b + i] * R[k * b + j];
-        }
-        __syncthreads();
+        const double rkk = sqrt(piv);
+        const double rkj = (j > k) ? g[k] / rkk : (j == k ? rkk : 0.0);
+        g[k] = rkj;
+#pragma unroll
+        for (int i = k + 1; i < B; ++i) g[i] -= __shfl(rkj, i) * rkj;
     }
-    return *bad == 0;
-}
-
-// Upper-triangular inverse (columns by back substitution), into Ri (LDS).
-__device__ void block_triinv(const double* R, double* Ri, int b) {
-    const int j = threadIdx.x;
-    if (j < b) {
-        for (int i = b - 1; i >= 0; --i) {
-            double s = (i == j) ? 1.0 : 0.0;
-            if (i <= j) {
-                for (int q = i + 1; q <= j; ++q) s -= R[i * b + q] * Ri[q * b + j];
-                Ri[i * b + j] = s / R[i * b + i];
-            } else {
-                Ri[i * b + j] = 0.0;
-            }
-        }
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = i + 1; t < B; ++t) acc -= __shfl(g[i], t) * ri[t];
+        const double rii = __shfl(g[i], i);
+        ri[i] = (i <= j) ? acc / rii : 0.0;
     }
-    __syncthreads();
+    return ok;
 }
 
 // After pass A: H1 (cv x b) from the summed tiles -> M1 = [-H1; I]
@@ -323,14 +303,14 @@ __global__ __launch_bounds__(1024) void k_fin_a(const double* __restrict__ sumA,
 // repair path); M2 = [-H2 R1^{-1}; R1^{-1}].  (H2 is O(eps) relative to the
 // first projection, so G - H2^T H2 and G differ at rounding level; the second
 // Cholesky-QR pass absorbs the difference.)
-__global__ __launch_bounds__(1024) void k_fin_b(const double* __restrict__ sumB, int BJ, int cv, int b,
-                                                 double thresh, double* __restrict__ M2, double* __restrict__ R1g,
-                                                 double* __restrict__ Gsave, double* __restrict__ T, int ldt,
-                                                 int cact, int* flag, const int* skip) {
+template <int B>
+__global__ __launch_bounds__(256) void k_fin_b(const double* __restrict__ sumB, int BJ, int cv, double thresh,
+                                                double* __restrict__ M2, double* __restrict__ R1g,
+                                                double* __restrict__ Gsave, double* __restrict__ T, int ldt,
+                                                int cact, int* flag, const int* skip) {
     if (skip && *skip) return;
-    __shared__ double G[kMaxBlock * kMaxBlock];
-    __shared__ double R[kMaxBlock * kMaxBlock];
-    __shared__ double Ri[kMaxBlock * kMaxBlock];
+    constexpr int b = B;
+    __shared__ double Ri[B * B];
     __shared__ int bad;
     const int nrt = (cv + 15) >> 4;
     const double* gt = sumB + (size_t)nrt * BJ * 256;
@@ -340,13 +320,7 @@ __global__ __launch_bounds__(1024) void k_fin_b(const double* __restrict__ sumB,
         T[(size_t)q * ldt + cact + j] += h;
         if (q < cact) T[(size_t)(cact + j) * ldt + q] += h;
     }
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e - i * b;
-        const double g = tile_at(gt, BJ, i, j);
-        G[e] = g;
-        Gsave[e] = g;
-    }
-    __syncthreads();  // T updates (global, this workgroup) and G visible
+    __syncthreads();  // T updates (global, this workgroup) visible
     for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
         const int i = e / b, j = e - i * b;
         if (j > i) {
@@ -357,78 +331,86 @@ __global__ __launch_bounds__(1024) void k_fin_b(const double* __restrict__ sumB,
             *c = m;
         }
     }
-    if (!block_cholesky(G, R, b, thresh, &bad)) {
-        if (threadIdx.x == 0) {
-            flag[0] = 1;
-            flag[1] = cact;
-            flag[2] = 1;
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
+        double g[B], ri[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            g[i] = j < B ? tile_at(gt, BJ, i, j) : 0.0;
+            ri[i] = 0.0;
+            if (j < B) Gsave[i * b + j] = g[i];
         }
-        return;
+        const bool ok = wave_chol_inv<B>(g, ri, thresh);
+        if (j < B) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                R1g[i * b + j] = g[i];
+                Ri[i * b + j] = ri[i];
+            }
+        }
+        if (j == 0) {
+            bad = ok ? 0 : 1;
+            if (!ok) {
+                flag[0] = 1;
+                flag[1] = cact;
+                flag[2] = 1;
+            }
+        }
     }
-    block_triinv(R, Ri, b);
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) R1g[e] = R[e];
+    __syncthreads();
+    if (bad) return;
     for (int e = threadIdx.x; e < (cv + b) * b; e += blockDim.x) {
         const int q = e / b, j = e - q * b;
-        double s;
+        double acc;
         if (q < cv) {
-            s = 0.0;
-            for (int t = 0; t <= j; ++t) s -= tile_at(sumB, BJ, q, t) * Ri[t * b + j];
+            acc = 0.0;
+            for (int t = 0; t <= j; ++t) acc -= tile_at(sumB, BJ, q, t) * Ri[t * b + j];
         } else {
-            s = Ri[(q - cv) * b + j];
+            acc = Ri[(q - cv) * b + j];
         }
-        M2[e] = s;
+        M2[e] = acc;
     }
 }
 
-// After pass C: R2 = chol(G2) (sum of partials, direct), M3 = R2^{-1},
+// After pass C: R2 = chol(G2) from the summed tiles, M3 = R2^{-1},
 // coupling Rc = R2 R1.
-__global__ __launch_bounds__(1024) void k_fin_c(const double* __restrict__ part, int nblk, int BJ, int b,
-                                                 const double* __restrict__ R1g, double* __restrict__ M3,
-                                                 double* __restrict__ Rc, double* __restrict__ Gsave, int cact,
-                                                 int* flag, const int* skip) {
+template <int B>
+__global__ __launch_bounds__(64) void k_fin_c(const double* __restrict__ sumC, int BJ,
+                                               const double* __restrict__ R1g, double* __restrict__ M3,
+                                               double* __restrict__ Rc, double* __restrict__ Gsave, int cact,
+                                               int* flag, const int* skip) {
     if (skip && *skip) return;
-    __shared__ double G[kMaxBlock * kMaxBlock];
-    __shared__ double R[kMaxBlock * kMaxBlock];
-    __shared__ double Ri[kMaxBlock * kMaxBlock];
-    __shared__ double red[1024];
-    __shared__ int bad;
-    const int O = BJ * BJ * 256;  // <= 1024
-    const int P = 1024 / O;
-    {
-        const int e = threadIdx.x % O, sub = threadIdx.x / O;
-        double s = 0.0;
-        if (sub < P)
-            for (int blk = sub; blk < nblk; blk += P) s += part[(size_t)blk * O + e];
-        red[threadIdx.x] = s;
+    constexpr int b = B;
+    const int j = threadIdx.x;
+    double g[B], ri[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        g[i] = j < B ? tile_at(sumC, BJ, i, j) : 0.0;
+        ri[i] = 0.0;
+        if (j < B) Gsave[i * b + j] = g[i];
     }
-    __syncthreads();
-    if (threadIdx.x < O) {
-        double s = 0.0;
-        for (int q = 0; q < P; ++q) s += red[q * O + threadIdx.x];
-        red[threadIdx.x] = s;  // own slot: slices q >= 1 live at higher indices
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e - i * b;
-        G[e] = tile_at(red, BJ, i, j);
-        Gsave[e] = G[e];
-    }
-    __syncthreads();
-    if (!block_cholesky(G, R, b, 0.25, &bad)) {
-        if (threadIdx.x == 0) {
+    const bool ok = wave_chol_inv<B>(g, ri, 0.25);
+    if (!ok) {
+        if (j == 0) {
             flag[0] = 1;
             flag[1] = cact;
             flag[2] = 2;
         }
         return;
     }
-    block_triinv(R, Ri, b);
-    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
-        const int i = e / b, j = e - i * b;
-        M3[e] = Ri[e];
-        double s = 0.0;
-        for (int q = i; q <= j; ++q) s += R[i * b + q] * R1g[q * b + j];
-        Rc[e] = j >= i ? s : 0.0;
+    // column j of R1 (global), column j of R2 in g (row i of R2 via shuffles)
+    double r1[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) r1[q] = j < B ? R1g[q * b + j] : 0.0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) acc += __shfl(g[i], q) * r1[q];  // R2[i][q] * R1[q][j]
+        if (j < B) {
+            M3[i * b + j] = ri[i];
+            Rc[i * b + j] = acc;
+        }
     }
 }
 
@@ -466,11 +448,18 @@ static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int l
 
 template <bool GRAM, bool SYRK>
 static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
-                       int yoff, int b, int cv, const double* M, double* part, const int* skip) {
+                       int yoff, int b, int cv, const double* M, double* part, const int* skip,
+                       double* Vout = nullptr, int ldo = 0) {
+    if (!Vout) {
+        Vout = V;
+        ldo = ld;
+    }
     if (BJ == 1)
-        k_pass_upd<1, GRAM, SYRK><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip);
+        k_pass_upd<1, GRAM, SYRK>
+            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo);
     else
-        k_pass_upd<2, GRAM, SYRK><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip);
+        k_pass_upd<2, GRAM, SYRK>
+            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo);
 }
 
 int ortho_expand(const OrthoArgs& a) {
@@ -499,7 +488,7 @@ int ortho_expand(const OrthoArgs& a) {
     else
         launch_a<double>(BJ, nblk, ldsA, s, a.V, a.ld, n, cv, b, (const double*)a.t, a.BW, a.grp, a.cs, a.rtab,
                          a.part, a.flag);
-    k_tile_reduce<<<(OA + 255) / 256, 1024, 0, s>>>(a.part, nblk, OA, sumA, a.flag);
+    k_reduce_partials<<<reduce_grid(OA), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OA, sumA, a.flag);
     k_fin_a<<<1, 1024, 0, s>>>(sumA, BJ, cv, b, H1, M1, a.T, a.ldt, cact, a.flag);
 
     // pass B: Y' = [V | Y0] M1, Gram + Syrk
@@ -507,17 +496,53 @@ int ortho_expand(const OrthoArgs& a) {
     const int OB = (nrt * BJ + BJ * BJ) * 256;
     size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)nrt * BJ * 256) * sizeof(double);
     launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, M1, a.part, a.flag);
-    k_tile_reduce<<<(OB + 255) / 256, 1024, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
-    k_fin_b<<<1, 1024, 0, s>>>(sumB, BJ, cv, b, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag);
+    k_reduce_partials<<<reduce_grid(OB), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
+    switch (b) {
+        case 4: k_fin_b<4><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
+        case 8: k_fin_b<8><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
+        case 16: k_fin_b<16><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
+        default: k_fin_b<32><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
+    }
 
     // pass C: Y1 = [V | Y'] M2, Syrk
     size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
     launch_upd<false, true>(BJ, nblk, ldsC, s, a.V, a.ld, n, 0, kin, cv, b, cv, M2, a.part, a.flag);
-    k_fin_c<<<1, 1024, 0, s>>>(a.part, nblk, BJ, b, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag);
+    const int OC = BJ * BJ * 256;
+    k_reduce_partials<<<reduce_grid(OC), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OC, sumA, a.flag);
+    switch (b) {
+        case 4: k_fin_c<4><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
+        case 8: k_fin_c<8><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
+        case 16: k_fin_c<16><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
+        default: k_fin_c<32><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
+    }
 
     // pass D: Y2 = Y1 R2^{-1}
     size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
     launch_upd<false, false>(BJ, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, b, cv, M3, nullptr, a.flag);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+// Thick restart: Vout[:, 0:p] = V[:, 0:c] Q (Q: c x p row-major, device)
+// and Vout[:, p:p+b] = V[:, c:c+b].  Qchunks holds Q split into 32-column
+// slices (slice t: c x wt row-major, wt = min(32, p - 32 t)) followed by the
+// b x b identity.
+int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
+                 hipStream_t s) {
+    if (c % 4 != 0 || ld % 4 != 0 || c > kLdMax || p + b > ld)
+        return set_error(SFAIRSC_E_ARG, "internal: bad rotation shape c=%d p=%d", c, p);
+    const int nblk = nblk_for(n);
+    const double* q = Qchunks;
+    for (int j0 = 0; j0 < p; j0 += 32) {
+        const int wt = std::min(32, p - j0);
+        const int BJ = wt > 16 ? 2 : 1;
+        const size_t lds = (size_t)c * BJ * 16 * sizeof(double);
+        launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, c, j0, wt, c, q, nullptr, nullptr, Vout, ld);
+        q += (size_t)c * wt;
+    }
+    const int BJ = b > 16 ? 2 : 1;
+    launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, c, b, p, b, c, q, nullptr,
+                             nullptr, Vout, ld);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }

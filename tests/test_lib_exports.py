@@ -57,7 +57,7 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {
         "sfairsc_eigs_opts": (L.EigsOpts, ["seed", "sigma", "x0", "b0"]),
         "sfairsc_graph_stats": (L.GraphStats, ["sigma", "max_degree"]),
-        "sfairsc_eigs_info": (L.EigsInfo, ["operator_applies", "spmm_ms", "max_rel_residual", "phase1_ms"]),
+        "sfairsc_eigs_info": (L.EigsInfo, ["operator_applies", "spmm_ms", "max_rel_residual", "phase1_ms", "rr_ms"]),
     }
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sfairsc.h"', "int main(void){"]
     for st, (_, fl) in fields.items():
