@@ -43,7 +43,22 @@ def main():
     ap.add_argument("--workload", default="msbm-50k-h5-normalized")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument(
+        "--copy-calibration",
+        action="store_true",
+        help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
+    )
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print(
             "bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +131,8 @@ def main():
     achieved = by / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
     peak = 8000.0
 
+    traffic = spmm_traffic(head, b)
+
     # accuracy against the oracle's stored eigenvalues when available
     acc = None
     gold = os.path.join(ROOT, "tests", "golden", "msbm50k_normalized_eigs.txt")
@@ -173,13 +190,41 @@ def main():
             "peak": peak,
             "unit": "GB/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_launch": by,
             "launch_ms": per_launch_ms,
         },
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def _source_hash():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_2210_16435_amd", "csrc", "operator.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def spmm_traffic(prec, b):
+    """Measured HBM bytes per SpMM launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None if
+    absent or taken on a different version of the kernel source."""
+    name = f"spmm_{'f32' if prec == 'mixed' else 'f64'}_b{b}_msbm50k_counters.md"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k_, v = line.split(":", 1)
+            vals[k_.strip().strip("-").strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(g, k, normalized):
