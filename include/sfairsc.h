@@ -201,6 +201,111 @@ int sfairsc_eigs(sfairsc_graph_t g, int32_t k, double tol, int precision,
                  const sfairsc_eigs_opts* opts, double* eigvals, double* H,
                  sfairsc_eigs_info* info, hipStream_t stream);
 
+/* ---- batched solves (many independent graphs) -------------------------- */
+
+/*
+ * Per-graph outcome of sfairsc_eigs_batched.
+ */
+typedef struct sfairsc_batch_info {
+    int32_t status;        /* SFAIRSC_OK or SFAIRSC_E_NOT_CONVERGED          */
+    int32_t path;          /* 0: solved in the batched launch;
+                              1: solved by sfairsc_eigs (the launch could
+                              not take the graph or did not finish it)      */
+    int32_t batch_status;  /* the launch's outcome: 0 converged, 1 not
+                              converged, 2 rank-deficient block, 3 FP64
+                              certification above tol, 4 shape not
+                              supported; -1 not attempted                   */
+    int32_t block_width;   /* configuration used in the launch             */
+    int32_t max_basis;
+    int32_t spmm_rows;     /* CSR rows a wavefront handles together        */
+    int32_t from_table;    /* 1: configuration from the tuning table       */
+    int32_t double_spmm;   /* 1: double sparse products in the launch      */
+    int32_t restarts, block_steps, converged, reserved;
+    double max_rel_residual;  /* max_i ||L^s x_i - theta_i x_i|| / sigma   */
+    double sigma;
+    double gap_ratio;      /* (theta_{k+1} - theta_k) / sigma              */
+    double graph_ms;       /* wall time of this graph's workgroup          */
+    double batch_ms;       /* wall time of the whole launch                */
+    double phase_ms[8];    /* graph_ms by phase: operator, Gram-Schmidt
+                              passes A, B, C, D, Rayleigh-Ritz, restart
+                              rotation, start block and output            */
+} sfairsc_batch_info;
+
+/*
+ * The k[i] smallest fair eigenpairs of each of `count` independent graphs
+ * (the problem of sfairsc_eigs for every graph), solved in ONE persistent
+ * kernel launch: each workgroup takes graphs from a device work queue,
+ * largest first, and runs the whole block Krylov-Schur iteration of its
+ * graph (deflated operator of eq. asigma with the group-sum projection of
+ * eq. mv-Pw, block Gram-Schmidt and Cholesky-QR on the FP64 matrix cores,
+ * Rayleigh-Ritz by Jacobi rotations in LDS, Proposition 3.3's output).
+ *
+ * graphs     host array of `count` handles, all on the current device.
+ * k          host int32[count], 1 <= k[i] <= min(64, n_i - h_i + 1).
+ * tol        as for sfairsc_eigs (||r_i|| <= tol * sigma).
+ * precision  SFAIRSC_PREC_MIXED: float sparse products with float
+ *            accumulation (double below tol = 5e-7); SFAIRSC_PREC_FP64.
+ * opts       may be NULL.  block_width (0, 4, 8 or 16) and max_basis (0 or
+ *            a multiple of the block width <= 80) force one configuration
+ *            for every graph; both 0 = per graph from the tuning table
+ *            (sfairsc_autotune), else a built-in rule.  seed, sigma,
+ *            certify and max_restarts (0 = 500) as for sfairsc_eigs; x0 must
+ *            be NULL.
+ * eigvals    host array of `count` host pointers to double[k[i]], ascending.
+ * H          host array of `count` device pointers to column-major
+ *            n_i x k[i] doubles (the layout and sign rule of sfairsc_eigs).
+ * infos      host array of `count` records, or NULL.
+ *
+ * Graphs the launch cannot take (k[i] > 48, n_i below twice the basis
+ * leading dimension) and graphs whose launch result misses tol are solved by
+ * sfairsc_eigs on the same stream.  The library keeps a per-device
+ * workspace between calls: calls on one device must not overlap.
+ * Synchronises `stream`.  Returns SFAIRSC_OK, SFAIRSC_E_NOT_CONVERGED (some
+ * graph's status), E_ARG, E_NOMEM or E_HIP.
+ */
+int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count,
+                         const int32_t* k, double tol, int precision,
+                         const sfairsc_eigs_opts* opts,
+                         double* const* eigvals, double* const* H,
+                         sfairsc_batch_info* infos, hipStream_t stream);
+
+/*
+ * Autotuner of the batched solve.  Graphs are grouped into buckets by
+ * (floor(log2 n), average degree class <16 / <32 / <64 / >=64, k class
+ * <=4 / <=8 / <=16 / >16, sparse-product precision, normalized); for up to
+ * per_bucket (1..16) graphs of each bucket, candidate configurations run as
+ * timed batched launches (each graph timed by its workgroup's wall clock):
+ * first block width x basis size, then the CSR rows per wavefront.  The
+ * fastest configuration whose solves all converge is stored in the
+ * process-wide tuning table (replacing that bucket's entry).  Synchronises
+ * `stream`.  Errors: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count,
+                     const int32_t* k, double tol, int precision,
+                     int32_t per_bucket, hipStream_t stream);
+
+/* Write the tuning table to `path` (JSON: an "entries" array of flat
+ * objects n_log2, degree_bucket, k_bucket, double_spmm, normalized,
+ * block_width, max_basis, spmm_rows, ms). */
+int sfairsc_tuning_save(const char* path);
+
+/* Replace the tuning table by the file's entries.  The environment variable
+ * SFAIRSC_TUNING_FILE, if set, is loaded at the first table use instead. */
+int sfairsc_tuning_load(const char* path);
+
+/* Empty the tuning table. */
+int sfairsc_tuning_clear(void);
+
+/* Number of entries in the tuning table. */
+int sfairsc_tuning_size(void);
+
+/* The configuration a batched solve would use for a graph of this shape:
+ * returns 1 if it comes from the table, 0 for the built-in rule, or a
+ * negative status. */
+int sfairsc_tuning_lookup(int64_t n, int64_t nnz, int32_t k, int precision,
+                          int normalized, double tol, int32_t* block_width,
+                          int32_t* max_basis, int32_t* spmm_rows);
+
 /* ---- clustering (Alg. 3 step 4) -------------------------------------- */
 
 /*

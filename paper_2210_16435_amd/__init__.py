@@ -37,6 +37,13 @@ from ._lib import (  # noqa: F401
 
 __all__ = [
     "Graph",
+    "eigs_batched",
+    "autotune",
+    "tuning_save",
+    "tuning_load",
+    "tuning_clear",
+    "tuning_size",
+    "tuning_lookup",
     "EigsResult",
     "FairEigSum",
     "SfairscError",
@@ -243,6 +250,108 @@ class Graph:
         grad = torch.empty(self.nnz, dtype=self.value_dtype, device=self.device)
         _lib.check(_lib.lib().sfairsc_eigsum_backward(self._h, _ptr(Hc), Hc.shape[0], _ptr(grad), _stream(stream)))
         return grad
+
+
+# -- batched solves ---------------------------------------------------------
+def _handles(graphs):
+    arr = (ctypes.c_void_p * len(graphs))()
+    for i, g in enumerate(graphs):
+        arr[i] = g._h
+    return arr
+
+
+def eigs_batched(
+    graphs,
+    k,
+    tol: float = 1e-6,
+    precision="mixed",
+    block_width: int = 0,
+    max_basis: int = 0,
+    max_restarts: int = 0,
+    seed: int = 0,
+    sigma: float = 0.0,
+    certify: bool = True,
+    H_out=None,
+    raise_not_converged: bool = True,
+    stream=None,
+):
+    """The k[i] smallest fair eigenpairs of every graph in one persistent
+    launch -> list of EigsResult (info: the per-graph batch record)."""
+    graphs = list(graphs)
+    cnt = len(graphs)
+    if isinstance(k, int):
+        k = [k] * cnt
+    k = [int(x) for x in k]
+    if len(k) != cnt:
+        raise ValueError("k must have one entry per graph")
+    opts = _lib.EigsOpts()
+    _lib.lib().sfairsc_eigs_opts_init(ctypes.byref(opts))
+    opts.block_width = block_width
+    opts.max_basis = max_basis
+    opts.max_restarts = max_restarts
+    opts.seed = seed
+    opts.sigma = sigma
+    opts.certify = int(certify)
+    karr = (ctypes.c_int32 * cnt)(*k)
+    evs = [(ctypes.c_double * kk)() for kk in k]
+    evp = (ctypes.c_void_p * cnt)(*[ctypes.cast(e, ctypes.c_void_p) for e in evs])
+    if H_out is None:
+        H_out = [torch.empty((kk, g.n), dtype=torch.float64, device=g.device) for g, kk in zip(graphs, k)]
+    Hp = (ctypes.c_void_p * cnt)(*[h.data_ptr() for h in H_out])
+    infos = (_lib.BatchInfo * cnt)()
+    code = _lib.lib().sfairsc_eigs_batched(
+        _handles(graphs), cnt, karr, float(tol), _prec(precision), ctypes.byref(opts), evp, Hp, infos,
+        _stream(stream)
+    )
+    allow = () if raise_not_converged else (E_NOT_CONVERGED,)
+    _lib.check(code, allow=allow)
+    return [
+        EigsResult(np.array(evs[i][:]), H_out[i].t(), infos[i].as_dict(), infos[i].status) for i in range(cnt)
+    ]
+
+
+def autotune(graphs, k, tol: float = 1e-6, precision="mixed", per_bucket: int = 2, stream=None) -> int:
+    """Time candidate batched configurations per graph bucket and fill the
+    tuning table; returns the number of table entries."""
+    graphs = list(graphs)
+    cnt = len(graphs)
+    if isinstance(k, int):
+        k = [k] * cnt
+    karr = (ctypes.c_int32 * cnt)(*[int(x) for x in k])
+    _lib.check(
+        _lib.lib().sfairsc_autotune(
+            _handles(graphs), cnt, karr, float(tol), _prec(precision), int(per_bucket), _stream(stream)
+        )
+    )
+    return tuning_size()
+
+
+def tuning_save(path: str) -> None:
+    _lib.check(_lib.lib().sfairsc_tuning_save(str(path).encode()))
+
+
+def tuning_load(path: str) -> None:
+    _lib.check(_lib.lib().sfairsc_tuning_load(str(path).encode()))
+
+
+def tuning_clear() -> None:
+    _lib.check(_lib.lib().sfairsc_tuning_clear())
+
+
+def tuning_size() -> int:
+    return int(_lib.lib().sfairsc_tuning_size())
+
+
+def tuning_lookup(n: int, nnz: int, k: int, precision="mixed", normalized: bool = False, tol: float = 1e-6):
+    """(block_width, max_basis, spmm_rows, from_table) a batched solve would use."""
+    b, m, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    code = _lib.lib().sfairsc_tuning_lookup(
+        int(n), int(nnz), int(k), _prec(precision), int(normalized), float(tol), ctypes.byref(b), ctypes.byref(m),
+        ctypes.byref(r)
+    )
+    if code < 0:
+        _lib.check(code)
+    return b.value, m.value, r.value, bool(code)
 
 
 class FairEigSum(torch.autograd.Function):

@@ -108,6 +108,34 @@ class EigsInfo(ctypes.Structure):
         }
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("path", ctypes.c_int32),
+        ("batch_status", ctypes.c_int32),
+        ("block_width", ctypes.c_int32),
+        ("max_basis", ctypes.c_int32),
+        ("spmm_rows", ctypes.c_int32),
+        ("from_table", ctypes.c_int32),
+        ("double_spmm", ctypes.c_int32),
+        ("restarts", ctypes.c_int32),
+        ("block_steps", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("max_rel_residual", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("gap_ratio", ctypes.c_double),
+        ("graph_ms", ctypes.c_double),
+        ("batch_ms", ctypes.c_double),
+        ("phase_ms", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in ("reserved", "phase_ms")}
+        d["phase_ms"] = [self.phase_ms[i] for i in range(8)]
+        return d
+
+
 # name -> (restype, argtypes); must match include/sfairsc.h
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -124,6 +152,19 @@ PROTOTYPES = {
     "sfairsc_eigs": (
         _int,
         [_vp, _i32, _dbl, _int, ctypes.POINTER(EigsOpts), ctypes.POINTER(_dbl), _vp, ctypes.POINTER(EigsInfo), _vp],
+    ),
+    "sfairsc_eigs_batched": (
+        _int,
+        [_vp, _i32, _vp, _dbl, _int, ctypes.POINTER(EigsOpts), _vp, _vp, ctypes.POINTER(BatchInfo), _vp],
+    ),
+    "sfairsc_autotune": (_int, [_vp, _i32, _vp, _dbl, _int, _i32, _vp]),
+    "sfairsc_tuning_save": (_int, [ctypes.c_char_p]),
+    "sfairsc_tuning_load": (_int, [ctypes.c_char_p]),
+    "sfairsc_tuning_clear": (_int, []),
+    "sfairsc_tuning_size": (_int, []),
+    "sfairsc_tuning_lookup": (
+        _int,
+        [_i64, _i64, _i32, _int, _int, _dbl, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     ),
     "sfairsc_labels": (_int, [_vp, _vp, _i32, _i32, _i32, ctypes.c_uint64, _i32, _vp, ctypes.POINTER(_dbl), _vp]),
     "sfairsc_eigsum_backward": (_int, [_vp, _vp, _i32, _vp, _vp]),

@@ -33,6 +33,7 @@
 #include "internal.h"
 #include "ortho.h"
 #include "reduce.h"
+#include "wave_chol.h"
 
 namespace sfairsc {
 
@@ -243,38 +244,6 @@ __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, 
     const int tile = (i >> 4) * BJ + (j >> 4);
     const int ii = i & 15, jj = j & 15;
     return t[((size_t)tile * 64 + jj + 16 * (ii & 3)) * 4 + (ii >> 2)];
-}
-
-// One wavefront factors a B x B SPD matrix in registers.  Lane j (< B)
-// holds column j of G in g[0..B); on return g holds column j of R
-// (G = R^T R, R upper triangular) and ri column j of R^{-1}.  Returns false
-// (uniformly across the wavefront) if a pivot is <= thresh.
-template <int B>
-__device__ bool wave_chol_inv(double (&g)[B], double (&ri)[B], double thresh) {
-    const int j = threadIdx.x & 63;
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-        double piv = __shfl(g[k], k);
-        if (!(piv > thresh)) {
-            ok = false;
-            piv = 1.0;
-        }
-        const double rkk = sqrt(piv);
-        const double rkj = (j > k) ? g[k] / rkk : (j == k ? rkk : 0.0);
-        g[k] = rkj;
-#pragma unroll
-        for (int i = k + 1; i < B; ++i) g[i] -= __shfl(rkj, i) * rkj;
-    }
-#pragma unroll
-    for (int i = B - 1; i >= 0; --i) {
-        double acc = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int t = i + 1; t < B; ++t) acc -= __shfl(g[i], t) * ri[t];
-        const double rii = __shfl(g[i], i);
-        ri[i] = (i <= j) ? acc / rii : 0.0;
-    }
-    return ok;
 }
 
 // After pass A: H1 (cv x b) from the summed tiles -> M1 = [-H1; I]
