@@ -696,27 +696,65 @@ struct Solver {
 }  // namespace
 
 // Repair a rank-deficient residual block found at expansion cact (host
-// driven; rare).  Rotates Y onto the eigenvectors of its Gram matrix, keeps
-// the directions of significant norm, replaces the others by random vectors,
-// orthonormalises again and rebuilds the coupling R = Rnew diag(keep) U^T.
+// driven; rare).  Works on the residual block W itself (at the second
+// Cholesky stage the failed block is W R1^{-1}, so it is first multiplied
+// back by R1): rotates W onto the eigenvectors U of its Gram matrix and
+// measures every rotated column's norm from its own entries (the Gram
+// eigenvalues only resolve norms down to about sqrt(eps) times the largest,
+// while a nearly converged direction can be far smaller and still matter at
+// the tolerance).  Columns at the rounding level are replaced by random
+// vectors, the others scaled to unit norm; the block is orthonormalised
+// again and the coupling rebuilt as R = Rnew diag(norm, kept) U^T.
 static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int stage) {
     const int b = S.b;
     const int cv = cact + b;
-    std::vector<double> G(b * b), U(b * b), w(b);
-    SF_TRY(S.download(G.data(), S.Gsave, b * b * sizeof(double)));
-    SF_TRY(S.sync());
-    sym_eig(b, G.data(), w.data(), U.data());
-    // Y <- Y U, deficient columns -> random
-    SF_TRY(S.upload(S.Q, U.data(), b * b * sizeof(double)));
     int zero = 0;
     SF_TRY(S.upload(S.flag, &zero, sizeof(int)));
-    SF_TRY(S.ts(TS_MUL, 0, cv, S.Q));
-    std::vector<int> keep(b, 0);
-    for (int j = 0; j < b; ++j) {
-        keep[j] = w[j] > S.thresh * 1e4;
-        if (!keep[j]) k_random<<<grid_for(S.n, 256, 4096), 256, 0, S.s>>>(S.V, S.ld, S.n, cv + j, 1, seed,
-                                                                             1000003ull * (attempt + 1) + j);
+    auto gram = [&](const double* M, std::vector<double>& G) -> int {
+        // Y <- Y M and G = Y^T Y (row-major b x b)
+        SF_TRY(S.ts(TS_MUL_SYRK, 0, cv, M));
+        k_gram_reduce<<<grid_for(b * b, 256, 64), 256, 0, S.s>>>(S.part, S.nblk, b, b, S.H1, nullptr, 0, 0, 0,
+                                                                 nullptr);
+        SF_HIP(hipGetLastError());
+        G.resize(b * b);
+        SF_TRY(S.download(G.data(), S.H1, b * b * sizeof(double)));
+        return S.sync();
+    };
+    std::vector<double> G, G2, U(b * b), w(b);
+    if (stage == 2) {
+        std::vector<double> R1(b * b);
+        SF_TRY(S.download(R1.data(), ortho_r1(S.g->eig.osmall.as<double>()), b * b * sizeof(double)));
+        SF_TRY(S.sync());
+        SF_TRY(S.upload(S.Q, R1.data(), b * b * sizeof(double)));
+        SF_TRY(gram(S.Q, G));
+    } else {
+        SF_TRY(gram(S.identity(), G));
     }
+    sym_eig(b, G.data(), w.data(), U.data());
+    // W <- W U; the diagonal of the rotated block's Gram: column norms^2
+    SF_TRY(S.upload(S.Q, U.data(), b * b * sizeof(double)));
+    SF_TRY(gram(S.Q, G2));
+    std::vector<double> nrm(b, 0.0);
+    double big = 0.0;
+    for (int j = 0; j < b; ++j) {
+        nrm[j] = std::sqrt(std::max(0.0, G2[j * b + j]));
+        big = std::max(big, nrm[j]);
+    }
+    // rounding level: relative to the block's largest column and to the
+    // operator scale sigma (an invariant subspace leaves only noise)
+    const double floor_norm = 1024.0 * 2.220446049250313e-16 * std::max(big, S.sigma);
+    std::vector<int> keep(b, 0);
+    std::vector<double> Dg(b * b, 0.0);
+    for (int j = 0; j < b; ++j) {
+        keep[j] = nrm[j] > floor_norm;
+        Dg[j * b + j] = keep[j] ? 1.0 / nrm[j] : 1.0;
+    }
+    SF_TRY(S.upload(S.Q, Dg.data(), b * b * sizeof(double)));
+    SF_TRY(S.ts(TS_MUL, 0, cv, S.Q));
+    for (int j = 0; j < b; ++j)
+        if (!keep[j])
+            k_random<<<grid_for(S.n, 256, 4096), 256, 0, S.s>>>(S.V, S.ld, S.n, cv + j, 1, seed,
+                                                                 1000003ull * (attempt + 1) + j);
     SF_HIP(hipGetLastError());
     // Orthogonalize again; the T column block of V_next already holds its
     // projection coefficients, so do not touch T (cact = -1 path writes into
@@ -728,28 +766,15 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int sta
     SF_TRY(S.download(Rn.data(), S.Rc, b * b * sizeof(double)));
     SF_TRY(S.sync());
     if (hflag[0]) return set_error(SFAIRSC_E_HIP, "could not repair a rank-deficient Krylov block");
-    // Y_old = Y_rot U^T,  Y_rot[:, j] = Qnew Rn[:, j] for kept j, 0 otherwise
+    // W = W_rot U^T,  W_rot[:, t] = nrm_t Qnew Rn[:, t] for kept t, 0 otherwise
     std::vector<double> Rc(b * b, 0.0);
     for (int i = 0; i < b; ++i)
         for (int j = 0; j < b; ++j) {
             double sacc = 0.0;
             for (int t = 0; t < b; ++t)
-                if (keep[t]) sacc += Rn[i * b + t] * U[j * b + t];
+                if (keep[t]) sacc += Rn[i * b + t] * nrm[t] * U[j * b + t];
             Rc[i * b + j] = sacc;
         }
-    if (stage == 2) {
-        // the failed block was Y1 = W R1^{-1}: the residual is W = Y1 R1
-        std::vector<double> R1(b * b), Rm(b * b, 0.0);
-        SF_TRY(S.download(R1.data(), ortho_r1(S.g->eig.osmall.as<double>()), b * b * sizeof(double)));
-        SF_TRY(S.sync());
-        for (int i = 0; i < b; ++i)
-            for (int j = 0; j < b; ++j) {
-                double sacc = 0.0;
-                for (int t = 0; t < b; ++t) sacc += Rc[i * b + t] * R1[t * b + j];
-                Rm[i * b + j] = sacc;
-            }
-        Rc = Rm;
-    }
     SF_TRY(S.upload(S.Rc, Rc.data(), b * b * sizeof(double)));
     // symmetrise T's diagonal block of V_next (normally done by the second
     // Cholesky pass of the expansion)

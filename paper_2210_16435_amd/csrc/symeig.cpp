@@ -247,7 +247,7 @@ void sym_eig(int n, const double* A, double* w, double* Z) {
         std::fill(col.begin(), col.end(), 0.0);
         col[j] = 1.0;
         apply_q(t, col.data());
-        for (int i = 0; i < n; ++i) Zt[(size_t)i * n + j] = col[i];
+        for (int i = 0; i < n; ++i) Zt[(size_t)j * n + i] = col[i];
     }
     std::vector<double> d = t.d, e = t.e;
     tridiag_ql(n, d, e, Zt.data());
