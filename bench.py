@@ -42,6 +42,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="msbm-50k-h5-normalized")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument(
+        "--no-extra",
+        action="store_true",
+        help="skip the other workloads (batched 256 graphs, 200k backward, 2M mixed solve)",
+    )
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument(
         "--copy-calibration",
@@ -148,6 +153,16 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, k, normalized)
 
+    extra = None
+    if not args.no_extra and args.only == "both":
+        del G
+        torch.cuda.empty_cache()
+        extra = {
+            "batched_256": bench_batched(sf, torch),
+            "backward_200k": bench_backward(sf, torch),
+            "mixed_2m": bench_2m(sf, torch),
+        }
+
     out = {
         "metric": "fair eigensolve time-to-tol & SpMM HBM GB/s; FP32-mixed vs FP64 speedup",
         "value": round(ms_head, 4),
@@ -184,7 +199,7 @@ def main():
         "kmeans_ms": round(kmeans_ms, 3),
         "spmm_gbps": round(achieved, 1),
         "roofline": {
-            "kernel": "k_spmm<float,16>" if head == "mixed" else "k_spmm<double,16>",
+            "kernel": f"k_spmm<float,{b}>" if head == "mixed" else f"k_spmm<double,{b}>",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": peak,
@@ -195,8 +210,171 @@ def main():
             "launch_ms": per_launch_ms,
         },
         "cpu_baseline": cpu,
+        "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_batched(sf, torch):
+    """256 uneven modified-SBM graphs (n log-uniform in [1e3, 5e4], k in 2..10,
+    h in 2..6, degree 10..80), all solved in one persistent launch with the
+    autotuned per-bucket configuration, float sparse products, tol 1e-6."""
+    from sfairsc_inputs.msbm import batched_graph, batched_specs
+
+    t0 = time.perf_counter()
+    specs = batched_specs()
+    graphs = [batched_graph(s) for s in specs]
+    ks = [s["k"] for s in specs]
+    gen_s = time.perf_counter() - t0
+    Gs = [sf.Graph.from_msbm(g, False) for g in graphs]
+    H = [torch.empty((k, g.n), dtype=torch.float64, device="cuda") for g, k in zip(graphs, ks)]
+    torch.cuda.synchronize()
+    sf.tuning_clear()
+    t0 = time.perf_counter()
+    entries = sf.autotune(Gs, ks, tol=1e-6, precision="mixed", per_bucket=2)
+    tune_s = time.perf_counter() - t0
+
+    def run():
+        return sf.eigs_batched(Gs, ks, tol=1e-6, precision="mixed", H_out=H, raise_not_converged=False)
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rs = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    graph_ms = np.array([r.info["graph_ms"] for r in rs])
+    phases = np.array([r.info["phase_ms"] for r in rs]).sum(0)
+    # the same graphs one after another through the single-graph solver
+    t0 = time.perf_counter()
+    for G, k, h in zip(Gs, ks, H):
+        G.eigs(k, tol=1e-6, precision="mixed", H_out=h)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    out = {
+        "workload": "batched-256 (n log-uniform 1e3..5e4, k 2..10, h 2..6, degree 10..80, tol 1e-6, mixed)",
+        "graphs": len(graphs),
+        "sum_n": int(sum(g.n for g in graphs)),
+        "sum_nnz": int(sum(g.nnz for g in graphs)),
+        "ms_per_batch": round(ms, 2),
+        "graphs_per_s": round(len(graphs) / (ms * 1e-3), 1),
+        "launch_ms": round(rs[0].info["batch_ms"], 2),
+        "max_graph_ms": round(float(graph_ms.max()), 2),
+        "sum_graph_ms": round(float(graph_ms.sum()), 1),
+        "phase_ms_sum": {
+            name: round(float(v), 1)
+            for name, v in zip(
+                ["operator", "pass_a", "pass_b", "pass_c", "pass_d", "rayleigh_ritz", "restart", "start_output"],
+                phases,
+            )
+        },
+        "solved_in_launch": int(sum(1 for r in rs if r.info["path"] == 0)),
+        "all_converged": bool(all(r.status == 0 for r in rs)),
+        "max_rel_residual": float(max(r.info["max_rel_residual"] for r in rs)),
+        "sequential_single_graph_ms": round(seq_ms, 1),
+        "speedup_vs_sequential": round(seq_ms / ms, 2),
+        "autotune_s": round(tune_s, 2),
+        "tuning_entries": entries,
+        "generation_s": round(gen_s, 1),
+    }
+    _log(f"batched: {out}")
+    del Gs, H
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_backward(sf, torch):
+    """Gradient of the sum of the 10 smallest fair eigenvalues w.r.t. every
+    stored weight (n = 200,000, degree 40, weights U(0.5, 1.5) float)."""
+    from sfairsc_inputs import workload
+
+    g = workload("msbm-200k-h4-grad")
+    G = sf.Graph.from_msbm(g, False)
+    k = 10
+    t0 = time.perf_counter()
+    r = G.eigs(k, tol=1e-10, precision="fp64")
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3
+    Hc = r.H.t().contiguous()  # column-major storage for the kernel
+    grad = torch.empty(g.nnz, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    lib = sf._lib.lib()
+    import ctypes
+
+    def once():
+        sf._lib.check(lib.sfairsc_eigsum_backward(G._h, ctypes.c_void_p(Hc.data_ptr()), k,
+                                                  ctypes.c_void_p(grad.data_ptr()),
+                                                  ctypes.c_void_p(stream.cuda_stream)))
+
+    once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        once()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # algorithmic bytes: rowptr, col, grad written once, H rows read once
+    by = 4 * (g.n + 1) + 4 * g.nnz + 4 * g.nnz + 8 * g.n * k
+    out = {
+        "workload": "msbm-200k-h4-grad (n=200000, k=10, degree 40)",
+        "n": g.n,
+        "nnz": g.nnz,
+        "forward_fp64_ms": round(fwd_ms, 2),
+        "backward_ms": round(ms, 4),
+        "backward_bytes": by,
+        "backward_gbps": round(by / (ms * 1e-3) / 1e9, 1),
+        "backward_frac_of_hbm": round(by / (ms * 1e-3) / 8e12, 4),
+    }
+    _log(f"backward: {out}")
+    del G
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_2m(sf, torch):
+    """n = 2,000,000 unnormalized modified SBM, k = 20, h = 8, degree 30,
+    weights U(0.5, 1.5), float sparse products, block width 32, tol 1e-6."""
+    from sfairsc_inputs import workload
+
+    g = workload("msbm-2m-h8")
+    G = sf.Graph.from_msbm(g, False)
+    k, b = 20, 32
+    H = torch.empty((k, g.n), dtype=torch.float64, device="cuda")
+    G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    rt = G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H, time_kernels=True)
+    launches = rt.info["spmm_launches"][1]
+    spmm_ms = rt.info["spmm_ms"][1] / max(launches, 1)
+    by = spmm_bytes(g.n, g.nnz, b, 4, 4)
+    out = {
+        "workload": "msbm-2m-h8 (n=2e6, k=20, h=8, degree 30, tol 1e-6, mixed, b=32)",
+        "n": g.n,
+        "nnz": g.nnz,
+        "ms_per_solve": round(ms, 2),
+        "block_steps": r.info["block_steps"],
+        "restarts": r.info["restarts"],
+        "max_rel_residual": r.info["max_rel_residual"],
+        "spmm_launch_ms": round(spmm_ms, 4),
+        "spmm_bytes": by,
+        "spmm_gbps": round(by / (spmm_ms * 1e-3) / 1e9, 1) if spmm_ms > 0 else None,
+        "rr_ms": round(r.info["rr_ms"], 1),
+    }
+    _log(f"2m: {out}")
+    del G, H
+    torch.cuda.empty_cache()
+    return out
 
 
 def _source_hash():

@@ -151,7 +151,8 @@ typedef struct sfairsc_eigs_opts {
     int32_t time_kernels;  /* 1: time every SpMM launch with HIP events
                               (reported in sfairsc_eigs_info)             */
     const double* x0;      /* optional device row-major n x b0 warm start */
-    int32_t b0;            /* columns of x0 (0 = none), <= block width    */
+    int32_t b0;            /* columns of x0 (0 = none), <= block width;
+                              an automatic block width is widened to it   */
     int32_t reserved;
 } sfairsc_eigs_opts;
 

@@ -814,7 +814,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     SF_HIP(hipGetLastError());
     // A random start vector is not orthogonal to range(C) or to the trivial
     // vector: harmless, the operator treats every direction exactly.
-    SF_TRY(S.orthonormalize(0, -1));
+    SF_TRY(ortho_start(S.V, S.ld, n, b, S.identity(), S.thresh, S.g->eig.opart.as<double>(),
+                       S.g->eig.osmall.as<double>(), S.Gsave, S.Rc, S.flag, S.s));
     {
         int hflag[2];
         SF_TRY(S.download(hflag, S.flag, 2 * sizeof(int)));
@@ -966,7 +967,10 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     const int64_t n = g->n;
     const int dim = (int)std::min<int64_t>(n, INT32_MAX);
     int b = o.block_width;
-    if (b == 0) b = k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32;
+    if (b == 0) {
+        b = k <= 4 ? 4 : k <= 16 ? 8 : 16;
+        while (b < o.b0 && b < kMaxBlock) b *= 2;  // room for the whole warm start
+    }
     if (b != 4 && b != 8 && b != 16 && b != 32) return set_error(SFAIRSC_E_ARG, "block width must be 4, 8, 16 or 32");
     while (b > 4 && 3 * b + k > dim) b /= 2;
     int ncv = o.max_basis;

@@ -252,6 +252,7 @@ static void free_graph(sfairsc_graph* g) {
     k.best.release();
     k.part.release();
     k.misc.release();
+    g->gw.hrow.release();
     delete g;
 }
 

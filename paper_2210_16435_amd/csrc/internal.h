@@ -84,6 +84,10 @@ struct KmWork {
     DevBuf d2, cs, cent, lab, best, part, misc;
 };
 
+struct GradWork {
+    DevBuf hrow;  // H staged row-major for the backward kernel
+};
+
 }  // namespace sfairsc
 
 struct sfairsc_graph {
@@ -108,6 +112,7 @@ struct sfairsc_graph {
     sfairsc::OpWork op;
     sfairsc::EigWork eig;
     sfairsc::KmWork km;
+    sfairsc::GradWork gw;
 };
 
 namespace sfairsc {

@@ -21,7 +21,10 @@ namespace sfairsc {
 
 constexpr int kSpmmThreads = 512;            // 8 waves
 constexpr int kSpmmWaves = kSpmmThreads / 64;
-constexpr int kSpmmMaxBlocks = 512;
+#ifndef SF_SPMM_MAX_BLOCKS
+#define SF_SPMM_MAX_BLOCKS 512
+#endif
+constexpr int kSpmmMaxBlocks = SF_SPMM_MAX_BLOCKS;
 constexpr int kProjThreads = 256;
 constexpr int kProjMaxBlocks = 256;
 constexpr int kFinThreads = 1024;

@@ -40,6 +40,10 @@ double* ortho_r1(double* small);
 // Passes A-D of the expansion (see ortho.hip).  Asynchronous.
 int ortho_expand(const OrthoArgs& a);
 
+// Cholesky-QR twice of the start block V[:, 0:b] on the matrix cores.
+int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double thresh, double* part, double* small,
+                double* gsave, double* rc, int* flag, hipStream_t s);
+
 // Thick-restart rotation into a second basis buffer (see ortho.hip).
 int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
                  hipStream_t s);

@@ -77,6 +77,13 @@ __device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, doub
     for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
 }
 
+// Element (i, j) of a tile-layout matrix with BJ column tiles.
+__device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
+    const int tile = (i >> 4) * BJ + (j >> 4);
+    const int ii = i & 15, jj = j & 15;
+    return t[((size_t)tile * 64 + jj + 16 * (ii & 3)) * 4 + (ii >> 2)];
+}
+
 // Pass A.  Y0 from the sparse product T (compact stride BW, type TT) and the
 // deflation table Rtab; partial V[:, 0:cv]^T Y0 (nrt x BJ tiles).
 template <int BJ, class TT>
@@ -139,14 +146,24 @@ template <int BJ, bool GRAM, bool SYRK>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
-                                                          int ldo) {
+                                                          int ldo, const double* __restrict__ Htiles) {
     if (skip && *skip) return;
     extern __shared__ double lds[];
     double* Ms = lds;                                   // [kin][BJ * 16]
     const int mld = BJ * 16;
-    for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
-        const int r = e / mld, j = e - r * mld;
-        Ms[e] = j < b ? M[r * b + j] : 0.0;
+    if (Htiles) {
+        // M = [-H1; I] straight from pass A's reduced tiles (rows < cv)
+        for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
+            const int r = e / mld, j = e - r * mld;
+            double v = 0.0;
+            if (j < b) v = r < cv ? -tile_at(Htiles, BJ, r, j) : (r - cv == j ? 1.0 : 0.0);
+            Ms[e] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
+            const int r = e / mld, j = e - r * mld;
+            Ms[e] = j < b ? M[r * b + j] : 0.0;
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -239,55 +256,40 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
     }
 }
 
-// Element (i, j) of a tile-layout matrix with BJ column tiles.
-__device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
-    const int tile = (i >> 4) * BJ + (j >> 4);
-    const int ii = i & 15, jj = j & 15;
-    return t[((size_t)tile * 64 + jj + 16 * (ii & 3)) * 4 + (ii >> 2)];
-}
-
-// After pass A: H1 (cv x b) from the summed tiles -> M1 = [-H1; I]
-// ((cv + b) x b) and T[0:cv, cact:cact+b] = H1 (and the mirror for q < cact).
-__global__ __launch_bounds__(1024) void k_fin_a(const double* __restrict__ sumA, int BJ, int cv, int b,
-                                                 double* __restrict__ H1, double* __restrict__ M1,
-                                                 double* __restrict__ T, int ldt, int cact, const int* skip) {
-    if (skip && *skip) return;
-    for (int e = threadIdx.x; e < (cv + b) * b; e += blockDim.x) {
-        const int q = e / b, j = e - q * b;
-        if (q < cv) {
-            const double h = tile_at(sumA, BJ, q, j);
-            H1[e] = h;
-            M1[e] = -h;
-            T[(size_t)q * ldt + cact + j] = h;
-            if (q < cact) T[(size_t)(cact + j) * ldt + q] = h;
-        } else {
-            M1[e] = (q - cv == j) ? 1.0 : 0.0;
-        }
-    }
-}
-
 // After pass B: H2 and G = Y'^T Y' from the summed tiles.  T column block
-// += H2 (and mirror), diagonal block symmetrised; R1 = chol(G) (pivot test
-// against thresh: flag[0] = 1, flag[1] = cact on failure; G saved for the
-// repair path); M2 = [-H2 R1^{-1}; R1^{-1}].  (H2 is O(eps) relative to the
-// first projection, so G - H2^T H2 and G differ at rounding level; the second
-// Cholesky-QR pass absorbs the difference.)
+// = H1 + H2 (pass A's and pass B's tiles; and the mirror), diagonal block
+// symmetrised; R1 = chol(G) (pivot test against thresh: flag[0] = 1,
+// flag[1] = cact on failure; G saved for the repair path);
+// M2 = [-H2 R1^{-1}; R1^{-1}].  (H2 is O(eps) relative to the first
+// projection, so G - H2^T H2 and G differ at rounding level; the second
+// Cholesky-QR pass absorbs the difference.)  For B <= 16 the H2 tiles are
+// first staged in LDS.
 template <int B>
-__global__ __launch_bounds__(256) void k_fin_b(const double* __restrict__ sumB, int BJ, int cv, double thresh,
-                                                double* __restrict__ M2, double* __restrict__ R1g,
-                                                double* __restrict__ Gsave, double* __restrict__ T, int ldt,
-                                                int cact, int* flag, const int* skip) {
+__global__ __launch_bounds__(256) void k_fin_b(const double* __restrict__ sumA, const double* __restrict__ sumB,
+                                                int BJ, int cv, double thresh, double* __restrict__ M2,
+                                                double* __restrict__ R1g, double* __restrict__ Gsave,
+                                                double* __restrict__ T, int ldt, int cact, int* flag,
+                                                const int* skip) {
     if (skip && *skip) return;
     constexpr int b = B;
+    constexpr bool kStage = B <= 16;
     __shared__ double Ri[B * B];
+    __shared__ double Hs[kStage ? (kMaxRT + 1) * 256 : 1];
     __shared__ int bad;
     const int nrt = (cv + 15) >> 4;
     const double* gt = sumB + (size_t)nrt * BJ * 256;
+    const double* H2 = sumB;
+    if (kStage) {
+        for (int e = threadIdx.x; e < (nrt + 1) * 256; e += blockDim.x) Hs[e] = sumB[e];
+        __syncthreads();
+        H2 = Hs;
+        gt = Hs + (size_t)nrt * 256;
+    }
     for (int e = threadIdx.x; e < cv * b; e += blockDim.x) {
         const int q = e / b, j = e - q * b;
-        const double h = tile_at(sumB, BJ, q, j);
-        T[(size_t)q * ldt + cact + j] += h;
-        if (q < cact) T[(size_t)(cact + j) * ldt + q] += h;
+        const double h = tile_at(sumA, BJ, q, j) + tile_at(H2, BJ, q, j);
+        T[(size_t)q * ldt + cact + j] = h;
+        if (q < cact) T[(size_t)(cact + j) * ldt + q] = h;
     }
     __syncthreads();  // T updates (global, this workgroup) visible
     for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(256) void k_fin_b(const double* __restrict__ sumB, 
         double acc;
         if (q < cv) {
             acc = 0.0;
-            for (int t = 0; t <= j; ++t) acc -= tile_at(sumB, BJ, q, t) * Ri[t * b + j];
+            for (int t = 0; t <= j; ++t) acc -= tile_at(H2, BJ, q, t) * Ri[t * b + j];
         } else {
             acc = Ri[(q - cv) * b + j];
         }
@@ -342,44 +344,52 @@ __global__ __launch_bounds__(256) void k_fin_b(const double* __restrict__ sumB, 
 }
 
 // After pass C: R2 = chol(G2) from the summed tiles, M3 = R2^{-1},
-// coupling Rc = R2 R1.
+// coupling Rc = R2 R1.  Wavefront 0 factors while the others stage R1;
+// the product Rc runs over the whole block from LDS.
 template <int B>
-__global__ __launch_bounds__(64) void k_fin_c(const double* __restrict__ sumC, int BJ,
-                                               const double* __restrict__ R1g, double* __restrict__ M3,
-                                               double* __restrict__ Rc, double* __restrict__ Gsave, int cact,
-                                               int* flag, const int* skip) {
+__global__ __launch_bounds__(256) void k_fin_c(const double* __restrict__ sumC, int BJ,
+                                                const double* __restrict__ R1g, double* __restrict__ M3,
+                                                double* __restrict__ Rc, double* __restrict__ Gsave, int cact,
+                                                int* flag, const int* skip, double thresh) {
     if (skip && *skip) return;
     constexpr int b = B;
-    const int j = threadIdx.x;
-    double g[B], ri[B];
+    __shared__ double R1s[B * B], R2s[B * B];
+    __shared__ int bad;
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
+        double g[B], ri[B];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-        g[i] = j < B ? tile_at(sumC, BJ, i, j) : 0.0;
-        ri[i] = 0.0;
-        if (j < B) Gsave[i * b + j] = g[i];
-    }
-    const bool ok = wave_chol_inv<B>(g, ri, 0.25);
-    if (!ok) {
-        if (j == 0) {
-            flag[0] = 1;
-            flag[1] = cact;
-            flag[2] = 2;
+        for (int i = 0; i < B; ++i) {
+            g[i] = j < B ? tile_at(sumC, BJ, i, j) : 0.0;
+            ri[i] = 0.0;
+            if (j < B) Gsave[i * b + j] = g[i];
         }
-        return;
-    }
-    // column j of R1 (global), column j of R2 in g (row i of R2 via shuffles)
-    double r1[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) r1[q] = j < B ? R1g[q * b + j] : 0.0;
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < B; ++q) acc += __shfl(g[i], q) * r1[q];  // R2[i][q] * R1[q][j]
+        const bool ok = wave_chol_inv<B>(g, ri, thresh);
         if (j < B) {
-            M3[i * b + j] = ri[i];
-            Rc[i * b + j] = acc;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                R2s[i * b + j] = g[i];
+                M3[i * b + j] = ri[i];
+            }
         }
+        if (j == 0) {
+            bad = ok ? 0 : 1;
+            if (!ok) {
+                flag[0] = 1;
+                flag[1] = cact;
+                flag[2] = 2;
+            }
+        }
+    } else {
+        for (int e = threadIdx.x - 64; e < b * b; e += blockDim.x - 64) R1s[e] = R1g[e];
+    }
+    __syncthreads();
+    if (bad) return;
+    for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+        const int i = e / b, j = e - i * b;
+        double acc = 0.0;
+        for (int q = i; q <= j; ++q) acc += R2s[i * b + q] * R1s[q * b + j];
+        Rc[e] = acc;
     }
 }
 
@@ -418,17 +428,17 @@ static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int l
 template <bool GRAM, bool SYRK>
 static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
                        int yoff, int b, int cv, const double* M, double* part, const int* skip,
-                       double* Vout = nullptr, int ldo = 0) {
+                       double* Vout = nullptr, int ldo = 0, const double* Htiles = nullptr) {
     if (!Vout) {
         Vout = V;
         ldo = ld;
     }
     if (BJ == 1)
         k_pass_upd<1, GRAM, SYRK>
-            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo);
+            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles);
     else
         k_pass_upd<2, GRAM, SYRK>
-            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo);
+            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles);
 }
 
 int ortho_expand(const OrthoArgs& a) {
@@ -458,20 +468,23 @@ int ortho_expand(const OrthoArgs& a) {
         launch_a<double>(BJ, nblk, ldsA, s, a.V, a.ld, n, cv, b, (const double*)a.t, a.BW, a.grp, a.cs, a.rtab,
                          a.part, a.flag);
     k_reduce_partials<<<reduce_grid(OA), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OA, sumA, a.flag);
-    k_fin_a<<<1, 1024, 0, s>>>(sumA, BJ, cv, b, H1, M1, a.T, a.ldt, cact, a.flag);
 
-    // pass B: Y' = [V | Y0] M1, Gram + Syrk
+    // pass B: Y' = [V | Y0] [-H1; I] (built from pass A's tiles), Gram + Syrk
     const int kin = cv + b;
     const int OB = (nrt * BJ + BJ * BJ) * 256;
     size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)nrt * BJ * 256) * sizeof(double);
-    launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, M1, a.part, a.flag);
+    launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, nullptr, a.part, a.flag, nullptr, 0,
+                           sumA);
     k_reduce_partials<<<reduce_grid(OB), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
+#define SF_FINB(BB) \
+    k_fin_b<BB><<<1, 256, 0, s>>>(sumA, sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag)
     switch (b) {
-        case 4: k_fin_b<4><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
-        case 8: k_fin_b<8><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
-        case 16: k_fin_b<16><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
-        default: k_fin_b<32><<<1, 256, 0, s>>>(sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag); break;
+        case 4: SF_FINB(4); break;
+        case 8: SF_FINB(8); break;
+        case 16: SF_FINB(16); break;
+        default: SF_FINB(32); break;
     }
+#undef SF_FINB
 
     // pass C: Y1 = [V | Y'] M2, Syrk
     size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
@@ -479,15 +492,56 @@ int ortho_expand(const OrthoArgs& a) {
     const int OC = BJ * BJ * 256;
     k_reduce_partials<<<reduce_grid(OC), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OC, sumA, a.flag);
     switch (b) {
-        case 4: k_fin_c<4><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
-        case 8: k_fin_c<8><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
-        case 16: k_fin_c<16><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
-        default: k_fin_c<32><<<1, 64, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag); break;
+        case 4: k_fin_c<4><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
+        case 8: k_fin_c<8><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
+        case 16: k_fin_c<16><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
+        default: k_fin_c<32><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
     }
 
     // pass D: Y2 = Y1 R2^{-1}
     size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
     launch_upd<false, false>(BJ, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, b, cv, M3, nullptr, a.flag);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+// Start block: Cholesky-QR twice of V[:, 0:b] in place on the matrix
+// cores (Syrk pass, Cholesky, update + Syrk, Cholesky, update).  ident is
+// the b x b identity, R1 receives the first factor (its pivot test uses
+// thresh), flag[0] = 1 if either factorisation fails.
+int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double thresh, double* part, double* small,
+                double* gsave, double* rc, int* flag, hipStream_t s) {
+    const int BJ = b > 16 ? 2 : 1;
+    const int nblk = nblk_for(n);
+    double* sumA = small;
+    double* R1 = ortho_r1(small);
+    double* M3 = R1 + kMaxBlock * kMaxBlock;
+    double* M = sumA + (size_t)(kMaxRT * 2 + 4) * 256 * 2;  // the H1 slot: b x b
+    const int OS = BJ * BJ * 256;
+    const size_t lds = std::max((size_t)b * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
+#define SF_FINC(BB, R1IN, MOUT, TH)                                                                            \
+    k_fin_c<BB><<<1, 256, 0, s>>>(sumA, BJ, R1IN, MOUT, rc, gsave, 0, flag, flag, TH)
+#define SF_FINC_B(R1IN, MOUT, TH)                \
+    switch (b) {                                 \
+        case 4: SF_FINC(4, R1IN, MOUT, TH); break;   \
+        case 8: SF_FINC(8, R1IN, MOUT, TH); break;   \
+        case 16: SF_FINC(16, R1IN, MOUT, TH); break; \
+        default: SF_FINC(32, R1IN, MOUT, TH); break; \
+    }
+    // G = Y^T Y (Y unchanged: multiplied by the identity)
+    launch_upd<false, true>(BJ, nblk, lds, s, V, ld, n, 0, b, 0, b, 0, ident, part, flag);
+    k_reduce_partials<<<reduce_grid(OS), kRedElems * kRedSlices, 0, s>>>(part, nblk, OS, sumA, flag);
+    // R = chol(G) (coupling against the identity), M = R^{-1}
+    SF_FINC_B(ident, M, thresh);
+    // Y <- Y M with the Gram of the result, then the second factor
+    launch_upd<false, true>(BJ, nblk, lds, s, V, ld, n, 0, b, 0, b, 0, M, part, flag);
+    k_reduce_partials<<<reduce_grid(OS), kRedElems * kRedSlices, 0, s>>>(part, nblk, OS, sumA, flag);
+    SF_FINC_B(ident, M3, 0.25);
+    launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, 0, b, 0, b, 0, M3,
+                             nullptr, flag);
+#undef SF_FINC_B
+#undef SF_FINC
+    (void)R1;
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }

@@ -414,9 +414,9 @@ def _w_500(seed=55):
 # name -> (builder, solve parameters)
 WORKLOADS = {
     "msbm-2k-h2": (_w_2k, dict(k=5, normalized=False, tol=1e-10, block=8)),
-    "msbm-50k-h5-normalized": (_w_50k, dict(k=10, normalized=True, tol=1e-8, block=16)),
+    "msbm-50k-h5-normalized": (_w_50k, dict(k=10, normalized=True, tol=1e-8, block=8)),
     "msbm-2m-h8": (_w_2m, dict(k=20, normalized=False, tol=1e-6, block=32)),
-    "msbm-200k-h4-grad": (_w_200k, dict(k=10, normalized=False, tol=1e-10, block=16)),
+    "msbm-200k-h4-grad": (_w_200k, dict(k=10, normalized=False, tol=1e-10, block=8)),
     "msbm-500-h4-grad": (_w_500, dict(k=10, normalized=False, tol=1e-12, block=8)),
 }
 
