@@ -52,8 +52,8 @@ struct DevBuf {
 struct OpWork {
     int nblk_spmm = 0;  // partial-sum slots of the SpMM epilogue
     int nblk_proj = 0;  // partial-sum slots of the input projection
-    DevBuf part_in;     // [nblk_proj][h][32] double
-    DevBuf part_out;    // [nblk_spmm][h][32] double
+    DevBuf part_in;     // [nblk_proj][h][b] double (b <= 32)
+    DevBuf part_out;    // [nblk_spmm][h][b] double (b <= 32)
     DevBuf small;       // R_in, S, R_out tables: 3 x [h][32] double
     DevBuf xp;          // projected input, n x BW (float or double)
     DevBuf t;           // sparse product output, n x BW (float or double)

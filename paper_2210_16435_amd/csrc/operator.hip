@@ -54,7 +54,7 @@ struct Vec16<double> {
 };
 
 // ---------------------------------------------------------------------------
-// A_s partial sums of c_i X_i per group.  part: [gridDim.x][h][32].
+// A_s partial sums of c_i X_i per group.  part: [gridDim.x][h][b].
 __global__ __launch_bounds__(kProjThreads) void k_proj_partial(const double* __restrict__ X, int ldx, int b,
                                                                 int64_t n, const int32_t* __restrict__ grp,
                                                                 const double* __restrict__ cs, int h,
@@ -74,10 +74,11 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_partial(const double* __r
         }
     }
     __syncthreads();
-    for (int o = threadIdx.x; o < h * 32; o += kProjThreads) {
+    for (int o = threadIdx.x; o < h * b; o += kProjThreads) {
+        const int g = o / b, j = o - g * b;
         double s = 0.0;
-        for (int r = 0; r < R; ++r) s += acc[r * h * 32 + o];
-        part[(size_t)blockIdx.x * h * 32 + o] = s;
+        for (int r = 0; r < R; ++r) s += acc[r * h * 32 + g * 32 + j];
+        part[(size_t)blockIdx.x * h * b + o] = s;
     }
 }
 
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     __shared__ double red[kFinThreads];
     __shared__ double A[kMaxGroups * 32];
     __shared__ double U[kMaxGroups * 32];
-    const int O = h * 32;             // <= kFinThreads since h <= 32
+    const int O = h * b;              // <= kFinThreads since h, b <= 32
     const int P = kFinThreads / O;    // threads per output
     const int t = threadIdx.x;
     {
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     if (t < O) {
         double tot = 0.0;
         for (int q = 0; q < P; ++q) tot += red[q * O + t];
-        A[t] = tot;
+        A[(t / b) * 32 + t % b] = tot;
     }
     __syncthreads();
     const int m = h - 1;
@@ -171,10 +172,19 @@ __global__ __launch_bounds__(256) void k_proj_apply(const double* __restrict__ X
     }
 }
 
-// T = diag * X' - W X' (CSR, one wavefront per row), epilogue: per-group sums
-// of c_i T_i into part[block][h][32].  X', T compact n x BW in type VT; the
-// products accumulate in VT (float in mixed precision).
-template <class VT, int BW>
+// T = diag * X' - W X' (CSR), epilogue: per-group sums of c_i T_i into
+// part[block][h][b].  X', T compact n x BW in type VT; the products
+// accumulate in VT (float in mixed precision).
+//
+// A wavefront takes RPW rows at once, G = 64 / RPW lanes each.  A row's
+// nonzeros go in chunks of G: one coalesced load of their columns and
+// values, then every gather of the chunk issued back to back (G / NS per
+// lane, NS = G / LPR nonzeros per instruction, LPR lanes per 16-byte row
+// vector).  Every row of the wavefront runs the wavefront's largest chunk
+// count, so the cross-lane shuffles stay uniform.  Several rows per
+// wavefront shorten the chain of dependent loads each wavefront walks
+// through when rows are short.
+template <class VT, int BW, int RPW>
 __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
                                                         const VT* __restrict__ val, const VT* __restrict__ diag,
@@ -185,74 +195,91 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
     if (skip && *skip) return;
     using V = Vec16<VT>;
     constexpr int VEC = V::N;
-    constexpr int LPR = BW / VEC;  // lanes per row vector
-    constexpr int NS = 64 / LPR;   // nonzeros in flight per wave
+    constexpr int LPR = BW / VEC;   // lanes per row vector
+    constexpr int G = 64 / RPW;     // lanes per row
+    constexpr int NS = G / LPR;     // nonzeros per gather instruction
+    constexpr int IT = G / NS;      // gathers per lane per chunk (= LPR)
+    static_assert(NS >= 1, "row group narrower than a row vector");
     extern __shared__ double gacc[];  // [kSpmmWaves][h][BW]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int slot = lane / LPR;
-    const int cl = lane % LPR;
+    const int sub = lane / G, sl = lane - sub * G;
+    const int slot = sl / LPR;
+    const int cl = sl - slot * LPR;
     const bool epi = part != nullptr;
     if (epi) {
         for (int o = threadIdx.x; o < kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
         __syncthreads();
     }
     double* wacc = gacc + wave * h * BW;
-    for (int64_t row = (int64_t)blockIdx.x * kSpmmWaves + wave; row < n; row += (int64_t)gridDim.x * kSpmmWaves) {
-        const int32_t a = rowptr[row], e_end = rowptr[row + 1];
+    const int64_t rstride = (int64_t)gridDim.x * kSpmmWaves * RPW;
+    for (int64_t row0 = ((int64_t)blockIdx.x * kSpmmWaves + wave) * RPW; row0 < n; row0 += rstride) {
+        const int64_t row = row0 + sub;
+        const bool rv = row < n;
+        const int32_t a = rv ? rowptr[row] : 0;
+        const int32_t e_end = rv ? rowptr[row + 1] : 0;
+        // the wavefront's largest chunk count
+        int nch = (e_end - a + G - 1) / G;
+#pragma unroll
+        for (int off = G; off < 64; off <<= 1) nch = max(nch, __shfl_xor(nch, off));
         VT acc[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[v] = VT(0);
-        // 64 nonzeros per chunk: one coalesced load of their columns and
-        // values, then all gathers of the chunk issued back to back.
-        for (int32_t base = a; base < e_end; base += 64) {
-            const int cnt = min(64, e_end - base);
-            const int32_t my_col = lane < cnt ? col[base + lane] : 0;
-            const VT my_val = lane < cnt ? val[base + lane] : VT(0);
-            V x[64 / NS];
-            VT w[64 / NS];
+        int32_t base = a;
+        for (int ch = 0; ch < nch; ++ch, base += G) {
+            const int cnt = max(0, min(G, e_end - base));
+            const int32_t my_col = sl < cnt ? col[base + sl] : 0;
+            const VT my_val = sl < cnt ? val[base + sl] : VT(0);
+            V x[IT];
+            VT w[IT];
 #pragma unroll
-            for (int it = 0; it < 64 / NS; ++it) {
+            for (int it = 0; it < IT; ++it) {
                 const int src = it * NS + slot;
-                const int32_t j = __shfl(my_col, src);
-                w[it] = __shfl(my_val, src);
+                const int32_t j = __shfl(my_col, sub * G + src);
+                w[it] = __shfl(my_val, sub * G + src);
                 if (src < cnt)
                     x[it] = V::load(X + (int64_t)j * BW + cl * VEC);
                 else
                     x[it] = V{};
             }
 #pragma unroll
-            for (int it = 0; it < 64 / NS; ++it)
+            for (int it = 0; it < IT; ++it)
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) acc[v] += w[it] * x[it].v[v];
         }
 #pragma unroll
-        for (int off = LPR; off < 64; off <<= 1)
+        for (int off = LPR; off < G; off <<= 1)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off);
-        if (slot == 0) {
+        V t;
+        if (rv && slot == 0) {
             V xi = V::load(X + row * BW + cl * VEC);
             const VT dg = diag[row];
-            V t;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) t.v[v] = dg * xi.v[v] - acc[v];
             t.store(T + row * BW + cl * VEC);
-            if (epi) {
-                const double c = cs ? cs[row] : 1.0;
-                double* dst = wacc + grp[row] * BW + cl * VEC;
+        }
+        if (epi) {
+            // rows of one wavefront may share a group: add one row at a time
+            const double c = (rv && cs) ? cs[row] : 1.0;
+            const int gi = rv ? grp[row] : 0;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) dst[v] += c * (double)t.v[v];
+            for (int r = 0; r < RPW; ++r) {
+                if (sub == r && rv && slot == 0) {
+                    double* dst = wacc + gi * BW + cl * VEC;
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) dst[v] += c * (double)t.v[v];
+                }
             }
         }
     }
     if (epi) {
         __syncthreads();
-        for (int o = threadIdx.x; o < h * 32; o += kSpmmThreads) {
-            const int s = o >> 5, jj = o & 31;
+        for (int o = threadIdx.x; o < h * b; o += kSpmmThreads) {
+            const int s = o / b, jj = o - s * b;
             double tot = 0.0;
-            if (jj < BW && jj < b)
-                for (int w = 0; w < kSpmmWaves; ++w) tot += gacc[w * h * BW + s * BW + jj];
-            part[(size_t)blockIdx.x * h * 32 + o] = tot;
+            for (int w = 0; w < kSpmmWaves; ++w) tot += gacc[w * h * BW + s * BW + jj];
+            part[(size_t)blockIdx.x * h * b + o] = tot;
         }
     }
 }
@@ -301,17 +328,28 @@ template <class VT>
 static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* val, const VT* diag, int b,
                         double* part, int nblk, hipStream_t s, const int* skip) {
     size_t lds = part ? (size_t)kSpmmWaves * g->h * BW * sizeof(double) : 0;
-#define SF_SPMM_CASE(W)                                                                                       \
-    case W:                                                                                                   \
-        k_spmm<VT, W><<<nblk, kSpmmThreads, lds, s>>>(g->rowptr, g->col, val, diag, X, T, g->n, g->grp, g->cs, \
-                                                      g->h, b, part, skip);                                   \
+    // rows per wavefront: short rows share a wavefront (at most 4)
+    const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
+    const int rpw = avg <= 24.0 ? 4 : (avg <= 96.0 ? 2 : 1);
+#define SF_SPMM_CASE(W, R)                                                                                     \
+    k_spmm<VT, W, R><<<nblk, kSpmmThreads, lds, s>>>(g->rowptr, g->col, val, diag, X, T, g->n, g->grp, g->cs, \
+                                                     g->h, b, part, skip)
+#define SF_SPMM_RPW(W)                 \
+    case W:                            \
+        if (rpw == 4)                  \
+            SF_SPMM_CASE(W, 4);        \
+        else if (rpw == 2)             \
+            SF_SPMM_CASE(W, 2);        \
+        else                           \
+            SF_SPMM_CASE(W, 1);        \
         break;
     switch (BW) {
-        SF_SPMM_CASE(4)
-        SF_SPMM_CASE(8)
-        SF_SPMM_CASE(16)
-        SF_SPMM_CASE(32)
+        SF_SPMM_RPW(4)
+        SF_SPMM_RPW(8)
+        SF_SPMM_RPW(16)
+        SF_SPMM_RPW(32)
     }
+#undef SF_SPMM_RPW
 #undef SF_SPMM_CASE
 }
 
@@ -398,8 +436,8 @@ int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
     k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
         X, ldx, b, g->n, g->grp, g->cs, h, w.part_in.as<double>(), nullptr);
     double* sums = Rin + 4 * kMaxGroups * 32;
-    k_reduce_partials<<<reduce_grid(h * 32), kRedElems * kRedSlices, 0, s>>>(w.part_in.as<double>(), w.nblk_proj,
-                                                                             h * 32, sums, nullptr);
+    k_reduce_partials<<<reduce_grid(h * b), kRedElems * kRedSlices, 0, s>>>(w.part_in.as<double>(), w.nblk_proj,
+                                                                            h * b, sums, nullptr);
     k_group_finalize<<<1, kFinThreads, 0, s>>>(sums, 1, h, b, g->gpar, nullptr, 0.0, Sx, Rin, nullptr);
     k_proj_inplace<<<grid_rows(g->n * b, 256, 8192), 256, 0, s>>>(X, ldx, b, g->n, g->grp, g->cs, Rin);
     SF_HIP(hipGetLastError());

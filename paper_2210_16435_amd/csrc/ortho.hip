@@ -396,10 +396,17 @@ __global__ __launch_bounds__(256) void k_fin_c(const double* __restrict__ sumC, 
 // ---------------------------------------------------------------------------
 // host side
 
+#ifndef SF_ORTHO_TILES_PER_WAVE
+#define SF_ORTHO_TILES_PER_WAVE 2
+#endif
+#ifndef SF_ORTHO_MAX_BLOCKS
+#define SF_ORTHO_MAX_BLOCKS 512
+#endif
 static int nblk_for(int64_t n) {
     const int64_t ntiles = (n + 15) / 16;
-    int64_t g = (ntiles + kOrWaves * 3 - 1) / (kOrWaves * 3);  // about 3 tiles per wave
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 240));
+    constexpr int per = kOrWaves * SF_ORTHO_TILES_PER_WAVE;  // 16-row tiles per block
+    int64_t g = (ntiles + per - 1) / per;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, SF_ORTHO_MAX_BLOCKS));
 }
 
 size_t ortho_part_doubles(int64_t n) {
