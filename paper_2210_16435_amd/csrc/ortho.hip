@@ -43,7 +43,10 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kOrThreads = 256;
+#ifndef SF_ORTHO_THREADS
+#define SF_ORTHO_THREADS 512
+#endif
+constexpr int kOrThreads = SF_ORTHO_THREADS;
 constexpr int kOrWaves = kOrThreads / 64;
 constexpr int kMaxRT = (kLdMax + 15) / 16;  // 14 row tiles of the Gram products
 
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(256) void k_fin_c(const double* __restrict__ sumC, 
 #define SF_ORTHO_TILES_PER_WAVE 2
 #endif
 #ifndef SF_ORTHO_MAX_BLOCKS
-#define SF_ORTHO_MAX_BLOCKS 512
+#define SF_ORTHO_MAX_BLOCKS 256
 #endif
 static int nblk_for(int64_t n) {
     const int64_t ntiles = (n + 15) / 16;
