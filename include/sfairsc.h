@@ -225,21 +225,29 @@ typedef struct sfairsc_batch_info {
     double max_rel_residual;  /* max_i ||L^s x_i - theta_i x_i|| / sigma   */
     double sigma;
     double gap_ratio;      /* (theta_{k+1} - theta_k) / sigma              */
-    double graph_ms;       /* wall time of this graph's workgroup          */
+    double graph_ms;       /* wall time from the launch's start until the
+                              graph left its block steps                   */
     double batch_ms;       /* wall time of the whole launch                */
-    double phase_ms[8];    /* graph_ms by phase: operator, Gram-Schmidt
-                              passes A, B, C, D, Rayleigh-Ritz, restart
-                              rotation, start block and output            */
+    double phase_ms[8];    /* compute-unit milliseconds spent on this graph
+                              (busy time of the workgroups that worked on
+                              it; each holds a whole compute unit) by
+                              phase: operator, Gram-Schmidt passes A, B,
+                              C, D (with the next block's group sums),
+                              Rayleigh-Ritz, restart rotation, start block
+                              and output                                   */
 } sfairsc_batch_info;
 
 /*
  * The k[i] smallest fair eigenpairs of each of `count` independent graphs
- * (the problem of sfairsc_eigs for every graph), solved in ONE persistent
- * kernel launch: each workgroup takes graphs from a device work queue,
- * largest first, and runs the whole block Krylov-Schur iteration of its
- * graph (deflated operator of eq. asigma with the group-sum projection of
- * eq. mv-Pw, block Gram-Schmidt and Cholesky-QR on the FP64 matrix cores,
- * Rayleigh-Ritz by Jacobi rotations in LDS, Proposition 3.3's output).
+ * (the problem of sfairsc_eigs for every graph), solved in ONE cooperative
+ * persistent kernel launch (every workgroup resident): the block
+ * Krylov-Schur iterations of all graphs (deflated operator of eq. asigma
+ * with the group-sum projection of eq. mv-Pw, block Gram-Schmidt and
+ * Cholesky-QR on the FP64 matrix cores, Rayleigh-Ritz by Jacobi rotations in
+ * LDS, Proposition 3.3's output) advance together in phases separated by
+ * grid barriers; row work is split into 1024-row items spread over all
+ * compute units, per-graph reductions and small factorizations run on one
+ * owner workgroup per graph.
  *
  * graphs     host array of `count` handles, all on the current device.
  * k          host int32[count], 1 <= k[i] <= min(64, n_i - h_i + 1).
@@ -275,10 +283,11 @@ int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count,
  * (floor(log2 n), average degree class <16 / <32 / <64 / >=64, k class
  * <=4 / <=8 / <=16 / >16, sparse-product precision, normalized); for up to
  * per_bucket (1..16) graphs of each bucket, candidate configurations run as
- * timed batched launches (each graph timed by its workgroup's wall clock):
- * first block width x basis size, then the CSR rows per wavefront.  The
- * fastest configuration whose solves all converge is stored in the
- * process-wide tuning table (replacing that bucket's entry).  Synchronises
+ * batched launches, each graph scored by the compute-unit time spent on it
+ * (phase_ms summed): first block width x basis size, then the CSR rows per
+ * wavefront.  The cheapest configuration whose solves all converge is
+ * stored in the process-wide tuning table (replacing that bucket's entry).
+ * Synchronises
  * `stream`.  Errors: E_ARG, E_NOMEM, E_HIP.
  */
 int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count,

@@ -7,21 +7,34 @@
 // twice and Cholesky-QR twice on the FP64 matrix cores, a Rayleigh-Ritz
 // step and the fair output H (Alg. 3 step 3, Proposition 3.3).
 //
-// Design.  One workgroup of 512 threads (8 wavefronts) owns one graph at a
-// time and runs its entire state machine: the Krylov basis and the sparse
-// product blocks live in HBM, while the projected matrix T_m, the
-// Rayleigh-Ritz eigenvectors, the coefficient matrices and all reductions
-// live in the workgroup's LDS (about 130 KB, so one workgroup per compute
-// unit).  Workgroups take graphs from a device work queue (an atomic
-// counter over a list sorted by estimated cost, largest first), so uneven
-// sizes balance over the compute units.  The small symmetric eigenproblem is
-// solved in LDS by cyclic Jacobi with a round-robin ordering (all m/2
-// disjoint rotations of a round are applied together).  Every reduction has
-// a fixed order: results are bitwise reproducible.
+// Design: one cooperative launch, bulk-synchronous.  The block steps of all
+// graphs still iterating advance together, as a fixed sequence of phases
+// separated by grid barriers.
+//   * Row phases (group sums, projection, the CSR product, the four
+//     matrix-core passes, the restart rotation) run over items: 1024
+//     consecutive rows of one graph, one item per workgroup at a time, 64
+//     rows per wavefront.  All graphs' items are spread over all compute
+//     units, so a large graph no longer runs on one compute unit.  An item
+//     reduces its wavefronts' partial sums in LDS and leaves one partial per
+//     item in HBM.
+//   * Graph phases (summing a graph's item partials in item order, the
+//     group-sum tables, the small Cholesky factors, the projected matrix T_m
+//     and the Rayleigh-Ritz step) run on the graph's owner workgroup.  The
+//     small symmetric eigenproblem is solved in LDS by cyclic Jacobi with a
+//     round-robin ordering: each round applies all m/2 disjoint rotations at
+//     once as a two-sided update of 2 x 2 blocks, so a round costs two
+//     workgroup barriers.
+// Every reduction has a fixed order: results are bitwise reproducible for a
+// given device.  A graph leaves the block steps once converged (or out of
+// restarts); the output phases (projection onto null(C^T), FP64
+// certification, signs, H) run once for all graphs at the end.  The launch
+// requires all workgroups to be resident at once (a cooperative launch,
+// which fails cleanly otherwise).
 //
-// The block width b, the basis size and the rows handled together by a
-// wavefront in the sparse product are chosen per graph, by default from a
-// tuning table filled by timed trials (sfairsc_autotune).
+// The block width b, the basis size and the CSR rows handled together by a
+// wavefront are chosen per graph, by default from a tuning table filled by
+// timed trials (sfairsc_autotune).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +50,8 @@
 #include "internal.h"
 #include "wave_chol.h"
 
+namespace cg = cooperative_groups;
+
 namespace sfairsc {
 namespace {
 
@@ -46,20 +61,35 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int NT = 1024;                    // threads of a workgroup
-constexpr int NW = NT / 64;                 // wavefronts
-constexpr int BMAX = 16;                    // widest block
-constexpr int NCVMAX = 80;                  // basis columns before a restart
-constexpr int LDT = NCVMAX + 1;             // LDS row stride of T and Z
-constexpr int RTMAX = (NCVMAX + 15) / 16;   // row tiles of a Gram product
+constexpr int NT = 1024;                        // threads of a workgroup
+constexpr int NW = NT / 64;                     // wavefronts
+constexpr int BMAX = 16;                        // widest block
+constexpr int NCVMAX = 80;                      // basis columns before a restart
+constexpr int LDT = NCVMAX + 1;                 // LDS row stride of the Jacobi matrices
+constexpr int RTMAX = (NCVMAX + 15) / 16;       // row tiles of a Gram product
 constexpr int KCH = (NCVMAX + BMAX + 15) / 16;  // 16-column chunks of an update input
-constexpr int HMAX = kMaxGroups;            // groups
-constexpr int KMAXB = 48;                   // wanted pairs (3 column tiles)
-constexpr int WPART = NW * 8 * 16;          // group-sum wave partials
-constexpr int WTILES = 2048;                // offset of reduced tiles in W
+constexpr int HMAX = kMaxGroups;                // groups
+constexpr int KMAXB = 48;                       // wanted pairs
+#ifndef SF_BATCH_ITEM_ROWS
+#define SF_BATCH_ITEM_ROWS 1024
+#endif
+constexpr int IROWS = SF_BATCH_ITEM_ROWS;       // rows of an item
+constexpr int WROWS = IROWS / NW;               // rows of a wavefront in an item
+static_assert(WROWS % 16 == 0, "a wavefront takes whole 16-row tiles");
+constexpr int WRED = 512;                       // LDS doubles per wavefront partial
+constexpr int PSTRIDE = (RTMAX + 1) * 256;      // doubles of an item's partial slot
+static_assert(HMAX * 16 <= WRED && 2 * 256 <= WRED, "wavefront partial too small");
 
-// Per-graph descriptor (device).
-struct Task {
+// Per-graph small buffers (doubles), one block per graph.
+constexpr int OFF_T = 0;                          // T_m, NCVMAX x NCVMAX
+constexpr int OFF_Z = OFF_T + NCVMAX * NCVMAX;    // rotation, NCVMAX x NCVMAX
+constexpr int OFF_M = OFF_Z + NCVMAX * NCVMAX;    // update coefficients, (NCVMAX + BMAX) x 16
+constexpr int OFF_TAB = OFF_M + (NCVMAX + BMAX) * 16;  // tables: input R, C^T X, output R
+constexpr int OFF_R = OFF_TAB + 3 * HMAX * 16;   // R1, Rc (16 x 16 each)
+constexpr int OFF_AUX = OFF_R + 2 * 256;          // theta [NCVMAX], signs [16]
+constexpr int SMALL_DOUBLES = OFF_AUX + NCVMAX + 16;
+
+struct Graph {
     const int32_t* rowptr;
     const int32_t* col;
     const float* val32;
@@ -73,41 +103,64 @@ struct Task {
     void* xp;            // n x 16 (8-byte slots): projected block
     void* tt;            // n x 16 (8-byte slots): sparse product
     double* H;           // output, column-major n x k
-    double* theta;       // output eigenvalues [k]
+    double* theta;       // output eigenvalues [KMAXB]
+    double* sm;          // small buffers (SMALL_DOUBLES)
     int64_t n;
     int32_t h, k, b, ncv, ld, rows, max_restarts, certify;
+    int32_t item0, nitems;
     double sigma, tol;
     double tol_conv;  // Ritz residual target (below tol with float products)
     uint64_t seed;
 };
 
-struct TaskStat {
+struct GState {
+    int32_t active;  // block steps continue
     int32_t status;  // 0 converged, 1 not converged, 2 breakdown, 3 certification failed, 4 bad shape
-    int32_t restarts, block_steps, converged;
-    double max_rel_residual;  // certified (FP64 operator) or estimated
-    double est_residual;      // Krylov-Schur estimate at the last Rayleigh-Ritz
-    double gap_ratio;
-    uint64_t t_begin, t_end;  // wall clock ticks
-    uint64_t phase[8];        // wall clock ticks per phase (see kPhaseNames)
+    int32_t out;     // the output phases apply (Ritz vectors of the last Rayleigh-Ritz step)
+    int32_t m, restarts, steps, nconv;
+    int32_t rot_m, rot_p, rot_nb;  // pending rotation (rot_p > 0)
+    double est, gap, maxres;
+    uint64_t t_done;
+    uint64_t ph[8];  // compute-unit clock ticks spent on the graph, by phase
+};
+
+struct Item {
+    int32_t g, pad;
+    int64_t row0;  // rows [row0, min(n, row0 + IROWS))
+};
+
+struct Launch {
+    const Graph* graphs;
+    GState* st;
+    const Item* items;
+    double* part;  // nitems x PSTRIDE
+    int* active;   // graphs still in their block steps
+    int* alist;    // items of the selected graphs (see build_list)
+    int* nalist;   // their number
+    uint64_t* t_start;
+    int ng, nitems, max_steps;
 };
 
 struct Shared {
-    double T[NCVMAX * LDT];  // projected matrix; Jacobi workspace; rotation matrix
-    double W[NCVMAX * LDT];  // Ritz eigenvectors; coefficient matrices and reduced tiles; group-sum partials
-    double gA[HMAX * 16], gS[HMAX * 16], gR[HMAX * 16], gZ[HMAX * 16];
-    double R1[256], Ri[256], R2[256], Rc[256];
+    union {
+        struct {
+            double A[NCVMAX * LDT];
+            double Z[NCVMAX * LDT];
+        } j;                    // Jacobi (graph phases)
+        double wred[NW * WRED];  // wavefront partials (row phases)
+    } u;
+    double red[PSTRIDE];
+    double gZ[HMAX * 16];
+    double R1[256], Ri[256], R2[256];
     double theta[NCVMAX], res[NCVMAX];
-    double red[NW * 16];
+    double wsum[NW * 2];
     double jc[NCVMAX / 2], js[NCVMAX / 2];
     int jp[NCVMAX / 2], jq[NCVMAX / 2];
     int perm[NCVMAX];
+    int iscan[NT];
     int iflag[4];
-    int cur;
-    uint64_t ph[8], tmark;
-    Task task;  // the graph being solved
 };
 static_assert(sizeof(Shared) <= 150 * 1024, "LDS budget");
-static_assert(sizeof(Task) % 4 == 0, "task copy");
 
 template <class VT>
 struct Vec16;
@@ -154,112 +207,113 @@ __device__ __forceinline__ double rnd_pm1(uint64_t seed, uint64_t idx) {
     return (double)(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
-// Sum of v over the workgroup (fixed order).
-__device__ double wg_sum(double v, double* red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < NW; ++w) s += red[w];
-    __syncthreads();
-    return s;
-}
+// ===========================================================================
+// Workgroup reductions of wavefront partials (fixed order).
 
-// Phases of a graph's solve timed by the workgroup's wall clock:
-// 0 operator, 1 pass A, 2 pass B, 3 pass C, 4 pass D, 5 Rayleigh-Ritz,
-// 6 restart rotation, 7 start block and output.
-__device__ __forceinline__ void phase_mark(Shared& S, int idx) {
-    if (threadIdx.x == 0) {
-        const uint64_t now = wall_clock64();
-        S.ph[idx] += now - S.tmark;
-        S.tmark = now;
+// Rows of 16 in the wavefronts' partials (wred[w * WRED + 16 r + j], r <
+// rows) summed over the wavefronts, compacted to out[r * cols + j], j < cols.
+__device__ void wg_combine(const double* wred, int rows, int cols, double* __restrict__ out) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * 16; e += NT) {
+        if ((e & 15) >= cols) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += wred[w * WRED + e];
+        out[(e >> 4) * cols + (e & 15)] = s;
     }
+    __syncthreads();
 }
 
-// Add the wavefronts' register tiles (nt tiles of 16 x 16, MFMA D layout)
-// into out[nt * 256] in wavefront order.
-template <int NTL>
-__device__ void sum_tiles(const d4 (&acc)[NTL], int nt, double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < NW; ++w) {
-        if (wave == w) {
+// The wavefronts' Gram tiles summed over the workgroup and compacted:
+// tiles t < ng (from acc[t]) hold rows 16 t ... of a (rows x b) product,
+// stored at out[i * b + j]; with SYRK, acc[NTL - 1] holds a b x b product,
+// stored after it at out[rows * b + i * b + j].  MFMA D layout: lane l,
+// register r hold row 4 r + l / 16, column l % 16 of a tile.
+template <int NTL, bool SYRK>
+__device__ void wg_tiles(const d4 (&acc)[NTL], int ng, int rows, int b, double* wred, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nt = ng + (SYRK ? 1 : 0);
+    for (int t0 = 0; t0 < nt; t0 += 2) {
 #pragma unroll
-            for (int t = 0; t < NTL; ++t) {
-                if (t < nt) {
-                    double* p = out + ((size_t)t * 64 + lane) * 4;
-                    if (w == 0) {
-                        p[0] = acc[t][0];
-                        p[1] = acc[t][1];
-                        p[2] = acc[t][2];
-                        p[3] = acc[t][3];
-                    } else {
-                        p[0] += acc[t][0];
-                        p[1] += acc[t][1];
-                        p[2] += acc[t][2];
-                        p[3] += acc[t][3];
-                    }
-                }
+        for (int r = 0; r < NTL; ++r) {
+            const bool is_syrk = SYRK && r == NTL - 1;
+            const int t = is_syrk ? ng : r;
+            if ((is_syrk || r < ng) && (t == t0 || t == t0 + 1)) {
+                double* p = wred + w * WRED + (t - t0) * 256 + lane * 4;
+                p[0] = acc[r][0];
+                p[1] = acc[r][1];
+                p[2] = acc[r][2];
+                p[3] = acc[r][3];
             }
+        }
+        __syncthreads();
+        const int cnt = min(2, nt - t0) * 256;
+        for (int e = threadIdx.x; e < cnt; e += NT) {
+            const int t = t0 + (e >> 8), l = (e & 255) >> 2, il = 4 * (e & 3) + (l >> 4), j = l & 15;
+            if (j >= b) continue;
+            int dst;
+            if (t < ng) {
+                const int i = 16 * t + il;
+                if (i >= rows) continue;
+                dst = i * b + j;
+            } else {
+                if (il >= b) continue;
+                dst = rows * b + il * b + j;
+            }
+            double s = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) s += wred[v * WRED + e];
+            out[dst] = s;
         }
         __syncthreads();
     }
 }
 
-// As sum_tiles for nt Gram tiles acc[0 .. nt) followed by the Syrk tile
-// acc[NTL - 1], stored at out[nt * 256].
-template <int NTL>
-__device__ void sum_tiles_gs(const d4 (&acc)[NTL], int nt, double* out) {
+// Sum of v over the workgroup (fixed order); two values at once.
+__device__ void wg_sum2(double& a, double& b, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < NW; ++w) {
-        if (wave == w) {
 #pragma unroll
-            for (int t = 0; t < NTL; ++t) {
-                const bool last = t == NTL - 1;
-                if (t < nt || last) {
-                    double* p = out + ((size_t)(last ? nt : t) * 64 + lane) * 4;
-                    if (w == 0) {
-                        p[0] = acc[t][0];
-                        p[1] = acc[t][1];
-                        p[2] = acc[t][2];
-                        p[3] = acc[t][3];
-                    } else {
-                        p[0] += acc[t][0];
-                        p[1] += acc[t][1];
-                        p[2] += acc[t][2];
-                        p[3] += acc[t][3];
-                    }
-                }
-            }
-        }
-        __syncthreads();
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
     }
+    if (lane == 0) {
+        red[2 * wave] = a;
+        red[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    a = 0.0;
+    b = 0.0;
+    for (int w = 0; w < NW; ++w) {
+        a += red[2 * w];
+        b += red[2 * w + 1];
+    }
+    __syncthreads();
 }
 
-// Element (i, j) (j < 16) of a column of 16 x 16 tiles in MFMA D layout.
-__device__ __forceinline__ double tile_el(const double* t, int i, int j) {
-    return t[((size_t)(i >> 4) * 64 + j + 16 * (i & 3)) * 4 + ((i & 15) >> 2)];
-}
+// ===========================================================================
+// Row work of one wavefront: rows [r0, r1) (at most WROWS, a multiple of 16
+// apart from the graph's last rows), no barriers.
 
-// A[s][j] = sum over rows i of group s of c_i X[i][j], j < b (b in {4, 8, 16}).
+// out[s * 16 + j] = sum over rows r in [r0, r1) of group s of c_r X[r][j],
+// j < bw (bw in {4, 8, 16}), s < h.
 template <class XT>
-__device__ __noinline__ void group_sums(const XT* X, int64_t ldx, int64_t n, int b, int h, const int32_t* __restrict__ grp,
-                           const double* __restrict__ cs, double* part, double* A) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane & (b - 1), rl = lane >> ilog2(b), rpw = 64 / b;
+__device__ __noinline__ void w_gsum(const XT* X, int64_t ldx, int64_t r0, int64_t r1, int bw, int h,
+                                    const int32_t* __restrict__ grp, const double* __restrict__ cs,
+                                    double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & (bw - 1), rl = lane >> ilog2(bw), rpw = 64 / bw;
     for (int g0 = 0; g0 < h; g0 += 8) {
         double acc[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) acc[s] = 0.0;
-        const int64_t st = (int64_t)NW * rpw;
-        int64_t i = (int64_t)wave * rpw + rl;
-        for (; i + 3 * st < n; i += 4 * st) {
+        int64_t i = r0 + rl;
+        for (; i + 3 * rpw < r1; i += 4 * rpw) {
             int gi[4];
             double v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int64_t r = i + u * st;
+                const int64_t r = i + u * rpw;
                 gi[u] = grp[r] - g0;
                 v[u] = (cs ? cs[r] : 1.0) * (double)X[r * ldx + col];
             }
@@ -268,120 +322,63 @@ __device__ __noinline__ void group_sums(const XT* X, int64_t ldx, int64_t n, int
 #pragma unroll
                 for (int s = 0; s < 8; ++s) acc[s] += (gi[u] == s) ? v[u] : 0.0;
         }
-        for (; i < n; i += st) {
+        for (; i < r1; i += rpw) {
             const int gi = grp[i] - g0;
             const double v = (cs ? cs[i] : 1.0) * (double)X[i * ldx + col];
 #pragma unroll
             for (int s = 0; s < 8; ++s) acc[s] += (gi == s) ? v : 0.0;
         }
-        for (int off = b; off < 64; off <<= 1)
+        for (int off = bw; off < 64; off <<= 1)
 #pragma unroll
             for (int s = 0; s < 8; ++s) acc[s] += __shfl_xor(acc[s], off);
         if (rl == 0)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) part[(wave * 8 + s) * 16 + col] = acc[s];
-        __syncthreads();
-        if (threadIdx.x < 128) {
-            const int s = threadIdx.x >> 4, j = threadIdx.x & 15;
-            if (j < b && g0 + s < h) {
-                double t = 0.0;
-                for (int w = 0; w < NW; ++w) t += part[(w * 8 + s) * 16 + j];
-                A[(g0 + s) * 16 + j] = t;
-            }
-        }
-        __syncthreads();
+            for (int s = 0; s < 8; ++s)
+                if (g0 + s < h) out[(g0 + s) * 16 + col] = acc[s];
     }
 }
 
-// From the group sums A of a block Z: S = C^T Z (A_s - p_s sum_t A_t,
-// s < h-1), optionally stored in Sout; then S -= sigma * Ssub; U = Ginv S;
-// R_s = U_s - q (s < h-1), R_{h-1} = -q, q = sum_s p_s U_s, so that
-// (C U)_i = c_i R_{g_i}.
-__device__ __noinline__ void group_finalize(const double* A, int h, int b, const double* __restrict__ gpar, double* Sout,
-                               const double* Ssub, double sigma, double* zs, double* R) {
-    const int j = threadIdx.x;
-    if (j < b) {
-        const int m = h - 1;
-        const double* p = gpar;
-        const double* Ginv = gpar + h;
-        double tot = 0.0;
-        for (int s = 0; s < h; ++s) tot += A[s * 16 + j];
-        for (int s = 0; s < m; ++s) {
-            double z = A[s * 16 + j] - p[s] * tot;
-            if (Sout) Sout[s * 16 + j] = z;
-            if (Ssub) z -= sigma * Ssub[s * 16 + j];
-            zs[s * 16 + j] = z;
-        }
-        double q = 0.0;
-        for (int s = 0; s < m; ++s) {
-            double u = 0.0;
-            for (int r = 0; r < m; ++r) u += Ginv[s * m + r] * zs[r * 16 + j];
-            R[s * 16 + j] = u;
-            q += p[s] * u;
-        }
-        for (int s = 0; s < m; ++s) R[s * 16 + j] -= q;
-        R[m * 16 + j] = -q;
-    }
-    __syncthreads();
-}
-
-// out_i = X_i - c_i R_{g_i} (columns j < b), out typed OT with row stride ldo.
+// out_r = X_r - c_r R_{g_r} for rows [r0, r1), columns j < bw.
 template <class OT>
-__device__ __noinline__ void proj_apply(const double* X, int64_t ldx, int64_t n, int b, const int32_t* __restrict__ grp,
-                           const double* __restrict__ cs, const double* R, OT* out, int64_t ldo) {
-    const int lb = ilog2(b);
-    const int64_t tot = n * b;
-    int64_t idx = threadIdx.x;
-    for (; idx + 3 * NT < tot; idx += 4 * NT) {
-        double x[4], c[4], r[4];
-        int64_t ii[4];
-        int jj[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t e = idx + u * NT;
-            ii[u] = e >> lb;
-            jj[u] = (int)(e & (b - 1));
-            x[u] = X[ii[u] * ldx + jj[u]];
-            c[u] = cs ? cs[ii[u]] : 1.0;
-            r[u] = R[grp[ii[u]] * 16 + jj[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) out[ii[u] * ldo + jj[u]] = (OT)(x[u] - c[u] * r[u]);
-    }
-    for (; idx < tot; idx += NT) {
-        const int64_t i = idx >> lb;
-        const int j = (int)(idx & (b - 1));
+__device__ __noinline__ void w_proj(const double* X, int64_t ldx, int64_t r0, int64_t r1, int bw,
+                                    const int32_t* __restrict__ grp, const double* __restrict__ cs,
+                                    const double* __restrict__ R, OT* out, int64_t ldo) {
+    const int lane = threadIdx.x & 63;
+    const int lb = ilog2(bw);
+    const int64_t tot = (r1 - r0) * bw;
+    for (int64_t idx = lane; idx < tot; idx += 64) {
+        const int64_t i = r0 + (idx >> lb);
+        const int j = (int)(idx & (bw - 1));
         const double c = cs ? cs[i] : 1.0;
         out[i * ldo + j] = (OT)(X[i * ldx + j] - c * R[grp[i] * 16 + j]);
     }
 }
 
-// T_i = diag_i X_i - sum_e val_e X_{col_e} (CSR rows; X, T compact n x b).
-// A wavefront handles `rows` rows at once, 64 / rows lanes each; within a
-// row, lanes split into nonzero slots of b / VEC lanes (one 16-byte vector).
+// T_r = diag_r X_r - sum_e val_e X_{col_e} for rows [r0, r1) (X, T compact
+// n x b).  `rows` rows share the wavefront, 64 / rows lanes each; within a
+// row, lanes split into nonzero slots of b / VEC lanes.
 template <class VT>
-__device__ __noinline__ void spmm_rows(const Task& t, const VT* __restrict__ X, VT* __restrict__ T, int b, int rows) {
+__device__ __noinline__ void w_spmm(const Graph& t, const VT* __restrict__ X, VT* __restrict__ T, int64_t r0,
+                                    int64_t r1, int b, int rows) {
     using V = Vec16<VT>;
     constexpr int VEC = V::N;
     const VT* __restrict__ val = pick<VT>(t.val32, t.val64);
     const VT* __restrict__ diag = pick<VT>(t.diag32, t.diag64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int LPR = b / VEC;
-    rows = min(rows, 64 / LPR);  // at least one nonzero slot per row
+    rows = min(rows, 64 / LPR);
     const int G = 64 / rows;
     const int sub = lane / G, sl = lane - sub * G;
     const int NS = G / LPR;
     const int slot = sl / LPR, cl = sl - slot * LPR;
-    const int64_t n = t.n;
-    for (int64_t base = (int64_t)wave * rows; base < n; base += (int64_t)NW * rows) {
+    for (int64_t base = r0; base < r1; base += rows) {
         const int64_t row = base + sub;
         VT acc[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) acc[v] = VT(0);
-        if (row < n) {
+        if (row < r1) {
             const int e0 = t.rowptr[row], e1 = t.rowptr[row + 1];
             int e = e0 + slot;
-            // four gathers in flight
             for (; e + 3 * NS < e1; e += 4 * NS) {
                 int j[4];
                 VT w[4];
@@ -409,7 +406,7 @@ __device__ __noinline__ void spmm_rows(const Task& t, const VT* __restrict__ X, 
         for (int off = LPR; off < G; off <<= 1)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off);
-        if (row < n && slot == 0) {
+        if (row < r1 && slot == 0) {
             const V xi = V::load(X + row * b + cl * VEC);
             const VT dg = diag[row];
             V o;
@@ -420,19 +417,21 @@ __device__ __noinline__ void spmm_rows(const Task& t, const VT* __restrict__ X, 
     }
 }
 
-// Pass A: Y0 = T - C U2 (deflation) into V[:, cv : cv + b]; reduced tiles
-// of V[:, 0:cv]^T Y0 into out.
+// Pass A over 16-row tiles [tile0, tile1): Y0 = T - C U2 into
+// V[:, cv : cv + b]; V[:, 0:cv]^T Y0 summed over the workgroup into out
+// (cv x b, row-major; every wavefront of the workgroup calls it).
 template <class SpT>
-__device__ __noinline__ void pass_a(const Task& t, double* V, int ld, int cv, int b, const SpT* __restrict__ T, const double* R2,
-                       double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __noinline__ void w_pass_a(const Graph& t, double* V, int ld, int cv, int b, const SpT* __restrict__ T,
+                                      const double* __restrict__ R2, int64_t tile0, int64_t tile1, double* wred,
+                                      double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nrt = (cv + 15) >> 4;
     d4 acc[RTMAX];
 #pragma unroll
     for (int r = 0; r < RTMAX; ++r) acc[r] = d4{0, 0, 0, 0};
-    const int64_t n = t.n, ntile = (n + 15) >> 4;
-    for (int64_t tile = wave; tile < ntile; tile += NW) {
+    const int64_t n = t.n;
+    for (int64_t tile = tile0; tile < tile1; ++tile) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t row = tile * 16 + 4 * q + lk;
@@ -453,26 +452,26 @@ __device__ __noinline__ void pass_a(const Task& t, double* V, int ld, int cv, in
             }
         }
     }
-    sum_tiles(acc, nrt, out);
+    wg_tiles<RTMAX, false>(acc, nrt, cv, b, wred, out);
 }
 
-// Ynew = V[:, coff : coff + kin] M (M: kin x 16 in LDS, columns >= b zero)
-// into V[:, yoff : yoff + b], in place (each 16-row tile is read completely
-// by its wavefront before it is written).  GRAM: reduced tiles of
-// V[:, 0:cv]^T Ynew into out[0 : nrt * 256]; SYRK: Ynew^T Ynew into the
-// tile after them.
+// Ynew = V[:, coff : coff + kin] M (M: kin x 16, columns >= b zero) into
+// V[:, yoff : yoff + b] over tiles [tile0, tile1), in place (all inputs of
+// a tile are in registers before its first store).  GRAM: V[:, 0:cv]^T Ynew
+// (cv x b); SYRK: Ynew^T Ynew (b x b) after it; both row-major, summed over
+// the workgroup into out (every wavefront of the workgroup calls it).
 template <bool GRAM, bool SYRK>
-__device__ __noinline__ void pass_upd(int64_t n, double* V, int ld, int coff, int kin, int yoff, int b, int cv, const double* M,
-                         double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __noinline__ void w_upd(int64_t n, double* V, int ld, int coff, int kin, int yoff, int b, int cv,
+                                   const double* __restrict__ M, int64_t tile0, int64_t tile1, double* wred,
+                                   double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nrt = GRAM ? (cv + 15) >> 4 : 0;
-    constexpr int NG = (GRAM ? RTMAX : 0) + 1;  // Gram tiles, then the Syrk tile
+    constexpr int NG = (GRAM ? RTMAX : 0) + 1;
     d4 acc[NG];
 #pragma unroll
     for (int r = 0; r < NG; ++r) acc[r] = d4{0, 0, 0, 0};
-    const int64_t ntile = (n + 15) >> 4;
-    for (int64_t tile = wave; tile < ntile; tile += NW) {
+    for (int64_t tile = tile0; tile < tile1; ++tile) {
         const int64_t row0 = tile * 16;
         d4 D = d4{0, 0, 0, 0};
         {
@@ -522,20 +521,19 @@ __device__ __noinline__ void pass_upd(int64_t n, double* V, int ld, int coff, in
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[NG - 1] = mfma16(D[q], D[q], acc[NG - 1]);
     }
-    if (GRAM || SYRK) sum_tiles_gs(acc, nrt, out);
+    if constexpr (GRAM || SYRK) wg_tiles<NG, true>(acc, nrt, GRAM ? cv : 0, b, wred, out);
 }
 
-// V[:, 0:p] = V[:, 0:m] Z (Z: m x p in LDS, row stride ldz) and, if nb > 0,
-// V[:, p : p + nb] = V[:, src : src + nb]; in place (p + nb <= src or nb = 0,
-// every tile read before it is written).
-__device__ __noinline__ void rotate(int64_t n, double* V, int ld, int m, const double* Z, int ldz, int p, int src, int nb) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// V[:, 0:p] = V[:, 0:m] Z (Z: m x p, row stride zs) and, if nb > 0,
+// V[:, p : p + nb] = V[:, m : m + nb], over tiles [tile0, tile1), in place
+// (every input of a tile is in registers before its first store).
+__device__ __noinline__ void w_rotate(int64_t n, double* V, int ld, int m, const double* __restrict__ Z, int zs,
+                                      int p, int nb, int64_t tile0, int64_t tile1) {
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nct = (p + 15) >> 4;
-    const int64_t ntile = (n + 15) >> 4;
-    for (int64_t tile = wave; tile < ntile; tile += NW) {
+    for (int64_t tile = tile0; tile < tile1; ++tile) {
         const int64_t row0 = tile * 16;
-        // the tile's input rows (lane (li, lk): row row0 + li, columns 16 c + 4 lk ..)
         double4 x[RTMAX];
         {
             const int64_t row = row0 + li;
@@ -551,9 +549,8 @@ __device__ __noinline__ void rotate(int64_t n, double* V, int ld, int m, const d
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t row = row0 + 4 * q + lk;
-            nx[q] = (row < n && li < nb) ? V[row * ld + src + li] : 0.0;
+            nx[q] = (row < n && li < nb) ? V[row * ld + m + li] : 0.0;
         }
-        // every input of the tile is in registers before its first store
         for (int c = 0; c < nct; ++c) {
             const int col = c * 16 + li;
             d4 D = d4{0, 0, 0, 0};
@@ -564,7 +561,7 @@ __device__ __noinline__ void rotate(int64_t n, double* V, int ld, int m, const d
 #pragma unroll
                     for (int st = 0; st < 4; ++st) {
                         const int kr = ch * 16 + 4 * lk + st;
-                        const double bm = (kr < m && col < p) ? Z[kr * ldz + col] : 0.0;
+                        const double bm = (kr < m && col < p) ? Z[kr * zs + col] : 0.0;
                         D = mfma16(xs[st], bm, D);
                     }
                 }
@@ -583,17 +580,133 @@ __device__ __noinline__ void rotate(int64_t n, double* V, int ld, int m, const d
     }
 }
 
-// Load the b x b block of a reduced tile into wavefront 0 (padded with the
-// identity to 16 x 16), factor it, store R (row-major 16 x 16) and R^{-1}.
-// Returns false on every thread if a pivot is <= thresh.
+// Residual partials of the certification, 16 columns:
+// out[j] = sum over rows of (T_r[j] - c_r R2[g_r][j] - theta_j X[r][j])^2.
+__device__ __noinline__ void w_resid(const Graph& t, const double* X, int ld, const double* __restrict__ T,
+                                     const double* __restrict__ R2, const double* __restrict__ th, int kc,
+                                     int64_t r0, int64_t r1, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, rl = lane >> 4;
+    const double thj = col < kc ? th[col] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = r0 + rl; i < r1; i += 4) {
+        const double c = t.cs ? t.cs[i] : 1.0;
+        const double y = T[i * 16 + col] - c * R2[t.grp[i] * 16 + col];
+        const double r = y - thj * X[i * ld + col];
+        acc += r * r;
+    }
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    if (rl == 0) out[col] = acc;
+}
+
+// Sign partials, 16 columns: the largest |c_r X[r][j]| over the rows (lowest
+// row on ties): out[j] = magnitude, out[16 + j] = row, out[32 + j] = value.
+__device__ __noinline__ void w_signs(const Graph& t, const double* X, int ld, int64_t r0, int64_t r1,
+                                     double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, rl = lane >> 4;
+    double best = -1.0, bv = 0.0;
+    int64_t bi = 0;
+    for (int64_t i = r0 + rl; i < r1; i += 4) {
+        const double v = (t.cs ? t.cs[i] : 1.0) * X[i * ld + col];
+        const double a = fabs(v);
+        if (a > best) {
+            best = a;
+            bi = i;
+            bv = v;
+        }
+    }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int64_t oi = __shfl_xor(bi, off);
+        const double ov = __shfl_xor(bv, off);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+            bv = ov;
+        }
+    }
+    if (rl == 0) {
+        out[col] = best;
+        out[16 + col] = (double)bi;
+        out[32 + col] = bv;
+    }
+}
+
+// The signs' maximum over a set of partials (lowest row on ties), 16 columns.
+__device__ void sign_merge(const double* p, double& b0, double& i0, double& v0) {
+    const int j = threadIdx.x & 15;
+    const double ob = p[j], oi = p[16 + j];
+    if (ob > b0 || (ob == b0 && oi < i0)) {
+        b0 = ob;
+        i0 = oi;
+        v0 = p[32 + j];
+    }
+}
+
+// ===========================================================================
+// Graph phases: the graph's owner workgroup.
+
+// dst[e] = sum over the graph's items of part[item][e], e < cnt, in a fixed
+// order (item residues modulo 8, then a fixed tree).
+__device__ void g_reduce(const double* __restrict__ part, int item0, int nitems, int cnt, double* dst) {
+    for (int e = threadIdx.x; e < cnt; e += NT) {
+        const double* p = part + (size_t)item0 * PSTRIDE + e;
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = 0.0;
+        for (int it = 0; it < nitems; it += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (it + u < nitems) a[u] += p[(size_t)(it + u) * PSTRIDE];
+        }
+        dst[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    __syncthreads();
+}
+
+// From the group sums A ([h][bw]) of a block Z: S = C^T Z (A_s - p_s sum_t
+// A_t, s < h-1), optionally stored in Sout; then S -= sigma * Ssub;
+// U = Ginv S; R_s = U_s - q (s < h-1), R_{h-1} = -q, q = sum_s p_s U_s, so
+// that (C U)_i = c_i R_{g_i}.  R and Sout may be global.
+__device__ void g_finalize(const double* A, int h, int bw, const double* __restrict__ gpar, double* Sout,
+                           const double* Ssub, double sigma, double* zs, double* R) {
+    const int j = threadIdx.x;
+    if (j < bw) {
+        const int m = h - 1;
+        const double* p = gpar;
+        const double* Ginv = gpar + h;
+        double tot = 0.0;
+        for (int s = 0; s < h; ++s) tot += A[s * bw + j];
+        for (int s = 0; s < m; ++s) {
+            double z = A[s * bw + j] - p[s] * tot;
+            if (Sout) Sout[s * 16 + j] = z;
+            if (Ssub) z -= sigma * Ssub[s * 16 + j];
+            zs[s * 16 + j] = z;
+        }
+        double q = 0.0;
+        for (int s = 0; s < m; ++s) {
+            double u = 0.0;
+            for (int r = 0; r < m; ++r) u += Ginv[s * m + r] * zs[r * 16 + j];
+            R[s * 16 + j] = u;
+            q += p[s] * u;
+        }
+        for (int s = 0; s < m; ++s) R[s * 16 + j] -= q;
+        R[m * 16 + j] = -q;
+    }
+    __syncthreads();
+}
+
 template <int B>
-__device__ bool chol_wave(const double* tile, int b, double thresh, double* R, double* Rinv) {
+__device__ bool chol_wave(const double* G, int b, double thresh, double* R, double* Rinv) {
     const int j = threadIdx.x;
     double g[B], ri[B];
 #pragma unroll
     for (int i = 0; i < B; ++i) {
         double v = 0.0;
-        if (j < B) v = (i < b && j < b) ? tile_el(tile, i, j) : (i == j ? 1.0 : 0.0);
+        if (j < B) v = (i < b && j < b) ? G[i * b + j] : (i == j ? 1.0 : 0.0);
         g[i] = v;
         ri[i] = 0.0;
     }
@@ -609,13 +722,13 @@ __device__ bool chol_wave(const double* tile, int b, double thresh, double* R, d
 }
 
 // Cholesky factor R (row-major 16 x 16, identity beyond b) and R^{-1} of the
-// b x b block of a reduced tile, by wavefront 0.  Returns false on every
-// thread if a pivot is <= thresh.
-__device__ __noinline__ bool chol16(const double* tile, int b, double thresh, double* R, double* Rinv, Shared& S) {
+// b x b matrix G (row-major), by wavefront 0.  Returns false on every thread
+// of the workgroup if a pivot is <= thresh.
+__device__ __noinline__ bool g_chol(const double* G, int b, double thresh, double* R, double* Rinv, Shared& S) {
     if (threadIdx.x < 64) {
-        const bool ok = b <= 4   ? chol_wave<4>(tile, b, thresh, R, Rinv)
-                        : b <= 8 ? chol_wave<8>(tile, b, thresh, R, Rinv)
-                                 : chol_wave<16>(tile, b, thresh, R, Rinv);
+        const bool ok = b <= 4   ? chol_wave<4>(G, b, thresh, R, Rinv)
+                        : b <= 8 ? chol_wave<8>(G, b, thresh, R, Rinv)
+                                 : chol_wave<16>(G, b, thresh, R, Rinv);
         if (threadIdx.x == 0) S.iflag[0] = ok ? 1 : 0;
     }
     __syncthreads();
@@ -624,33 +737,18 @@ __device__ __noinline__ bool chol16(const double* tile, int b, double thresh, do
     return ok;
 }
 
-// Cholesky-QR twice of the block V[:, c : c + b] in place.
-__device__ __noinline__ bool cholqr2(int64_t n, double* V, int ld, int c, int b, double thresh, Shared& S) {
-    double* M = S.W;
-    double* out = S.W + WTILES;
-    for (int e = threadIdx.x; e < 16 * 16; e += NT) M[e] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
-    __syncthreads();
-    pass_upd<false, true>(n, V, ld, c, b, c, b, 0, M, out);
-    if (!chol16(out, b, thresh, S.R1, S.Ri, S)) return false;
-    for (int e = threadIdx.x; e < 16 * 16; e += NT) M[e] = S.Ri[e];
-    __syncthreads();
-    pass_upd<false, true>(n, V, ld, c, b, c, b, 0, M, out);
-    if (!chol16(out, b, 0.25, S.R2, S.Ri, S)) return false;
-    for (int e = threadIdx.x; e < 16 * 16; e += NT) M[e] = S.Ri[e];
-    __syncthreads();
-    pass_upd<false, false>(n, V, ld, c, b, c, b, 0, M, out);
-    __syncthreads();
-    return true;
-}
-
-// Eigen-decomposition of the symmetric m x m matrix A (LDS, stride lda) by
-// cyclic Jacobi, round-robin ordering.  On return diag(A) holds the
-// eigenvalues and Z (LDS, stride ldz) the eigenvectors as columns.
-__device__ __noinline__ void jacobi(double* A, int lda, int m, double* Z, int ldz, Shared& S) {
+// Eigen-decomposition of the symmetric m x m matrix A (LDS, stride LDT) by
+// cyclic Jacobi, round-robin ordering.  A round's m/2 rotations are disjoint
+// and applied at once: thread blocks of 2 x 2 entries (pair a's rows, pair
+// b's columns) take A <- J^T A J from the old values, so a round needs one
+// barrier after the rotation angles and one after the update.  On return
+// diag(A) holds the eigenvalues and Z (stride LDT) the eigenvectors as
+// columns.
+__device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
     const int t = threadIdx.x;
     for (int idx = t; idx < m * m; idx += NT) {
         const int i = idx / m, j = idx - i * m;
-        Z[i * ldz + j] = (i == j) ? 1.0 : 0.0;
+        Z[i * LDT + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     const int mm = m + (m & 1), np = mm / 2, rr = mm - 1;
@@ -658,14 +756,13 @@ __device__ __noinline__ void jacobi(double* A, int lda, int m, double* Z, int ld
         double off = 0.0, dg = 0.0;
         for (int idx = t; idx < m * m; idx += NT) {
             const int i = idx / m, j = idx - i * m;
-            const double v = A[i * lda + j];
+            const double v = A[i * LDT + j];
             if (i != j)
                 off += v * v;
             else
                 dg += v * v;
         }
-        off = wg_sum(off, S.red);
-        dg = wg_sum(dg, S.red);
+        wg_sum2(off, dg, S.wsum);
         if (!(off > 1e-30 * dg)) break;
         for (int r = 0; r < rr; ++r) {
             if (t < np) {
@@ -684,9 +781,9 @@ __device__ __noinline__ void jacobi(double* A, int lda, int m, double* Z, int ld
                 }
                 double c = 1.0, s = 0.0;
                 if (q < m) {
-                    const double apq = A[p * lda + q];
+                    const double apq = A[p * LDT + q];
                     if (apq != 0.0) {
-                        const double th = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
+                        const double th = (A[q * LDT + q] - A[p * LDT + p]) / (2.0 * apq);
                         const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
                         c = 1.0 / sqrt(1.0 + tt * tt);
                         s = tt * c;
@@ -698,406 +795,606 @@ __device__ __noinline__ void jacobi(double* A, int lda, int m, double* Z, int ld
                 S.js[t] = s;
             }
             __syncthreads();
+            // A <- J^T A J on 2 x 2 blocks; entries with an index >= m (the
+            // padding index of odd m) are neither read nor written
+            for (int idx = t; idx < np * np; idx += NT) {
+                const int a = idx / np, bq = idx - a * np;
+                const double s1 = S.js[a], s2 = S.js[bq];
+                if (s1 == 0.0 && s2 == 0.0) continue;
+                const int p1 = S.jp[a], q1 = S.jq[a], p2 = S.jp[bq], q2 = S.jq[bq];
+                const double c1 = S.jc[a], c2 = S.jc[bq];
+                const bool vq1 = q1 < m, vq2 = q2 < m;
+                const double x00 = A[p1 * LDT + p2];
+                const double x01 = vq2 ? A[p1 * LDT + q2] : 0.0;
+                const double x10 = vq1 ? A[q1 * LDT + p2] : 0.0;
+                const double x11 = (vq1 && vq2) ? A[q1 * LDT + q2] : 0.0;
+                // columns: Y = X J2
+                const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
+                const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
+                // rows: J1^T Y
+                A[p1 * LDT + p2] = c1 * y00 - s1 * y10;
+                if (vq2) A[p1 * LDT + q2] = c1 * y01 - s1 * y11;
+                if (vq1) A[q1 * LDT + p2] = s1 * y00 + c1 * y10;
+                if (vq1 && vq2) A[q1 * LDT + q2] = s1 * y01 + c1 * y11;
+            }
+            // Z <- Z J
             for (int idx = t; idx < m * np; idx += NT) {
                 const int i = idx / np, pr = idx - i * np;
                 const double s = S.js[pr];
                 if (s == 0.0) continue;
                 const int p = S.jp[pr], q = S.jq[pr];
                 const double c = S.jc[pr];
-                double* a = A + i * lda;
-                const double ap = a[p], aq = a[q];
-                a[p] = c * ap - s * aq;
-                a[q] = s * ap + c * aq;
-                double* z = Z + i * ldz;
+                double* z = Z + i * LDT;
                 const double zp = z[p], zq = z[q];
                 z[p] = c * zp - s * zq;
                 z[q] = s * zp + c * zq;
             }
             __syncthreads();
-            for (int idx = t; idx < m * np; idx += NT) {
-                const int j = idx / np, pr = idx - j * np;
-                const double s = S.js[pr];
-                if (s == 0.0) continue;
-                const int p = S.jp[pr], q = S.jq[pr];
-                const double c = S.jc[pr];
-                const double ap = A[p * lda + j], aq = A[q * lda + j];
-                A[p * lda + j] = c * ap - s * aq;
-                A[q * lda + j] = s * ap + c * aq;
-            }
-            __syncthreads();
         }
     }
 }
 
-// Y = L^sigma X for the block X = V[:, c : c + bw] (bw in {4, 8, 16}):
-// on return the sparse product sits in tt, its deflation table in S.gR
-// (Y_i = T_i - c_i R_{g_i}) and C^T X in S.gS.
-template <class VT>
-__device__ __noinline__ void apply_operator(const Task& t, const double* X, int ld, int bw, int rows, Shared& S) {
-    const int64_t n = t.n;
-    VT* xp = static_cast<VT*>(t.xp);
-    VT* tt = static_cast<VT*>(t.tt);
-    group_sums(X, ld, n, bw, t.h, t.grp, t.cs, S.W, S.gA);
-    group_finalize(S.gA, t.h, bw, t.gpar, S.gS, nullptr, 0.0, S.gZ, S.gR);
-    proj_apply<VT>(X, ld, n, bw, t.grp, t.cs, S.gR, xp, bw);
-    __syncthreads();
-    spmm_rows<VT>(t, xp, tt, bw, rows);
-    __syncthreads();
-    group_sums(tt, bw, n, bw, t.h, t.grp, t.cs, S.W, S.gA);
-    group_finalize(S.gA, t.h, bw, t.gpar, nullptr, S.gS, t.sigma, S.gZ, S.gR);
+__device__ __forceinline__ void stop(GState& s, int status, int* active) {
+    s.active = 0;
+    s.status = status;
+    s.t_done = wall_clock64();
+    atomicSub(active, 1);
 }
 
-// Fair output: V[:, 0:k] already holds the Ritz vectors.  Project them onto
-// null(C^T), certify (optional), fix signs, scale and write H.
-__device__ __noinline__ void finish(const Task& t, TaskStat& st, double* V, int ld, Shared& S) {
-    const int64_t n = t.n;
-    const int k = t.k;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane & 15, rl = lane >> 4;
-    double maxres = 0.0;
-    for (int c0 = 0; c0 < k; c0 += 16) {
-        double* X = V + c0;
-        group_sums(X, ld, n, 16, t.h, t.grp, t.cs, S.W, S.gA);
-        group_finalize(S.gA, t.h, 16, t.gpar, nullptr, nullptr, 0.0, S.gZ, S.gR);
-        proj_apply<double>(X, ld, n, 16, t.grp, t.cs, S.gR, X, ld);
+// ===========================================================================
+// The launch.
+
+enum Ph { PH_OP = 0, PH_A, PH_B, PH_C, PH_D, PH_RR, PH_ROT, PH_IO };
+
+// The items of the graphs still in their block steps (out: of the graphs
+// with output), in graph order, into alist / nalist.  Workgroup 0 only.
+__device__ void build_list(const Launch& L, bool out, Shared& S) {
+    int base = 0;
+    for (int g0 = 0; g0 < L.ng; g0 += NT) {
+        const int gi = g0 + threadIdx.x;
+        int cnt = 0;
+        if (gi < L.ng) {
+            const GState& s = L.st[gi];
+            cnt = (out ? s.out : s.active) ? L.graphs[gi].nitems : 0;
+        }
+        S.iscan[threadIdx.x] = cnt;
         __syncthreads();
-        if (t.certify) {
-            apply_operator<double>(t, X, ld, 16, 8, S);
-            const double* T = static_cast<const double*>(t.tt);
-            const double th = (c0 + col < k) ? S.theta[c0 + col] : 0.0;
-            double acc = 0.0;
-            for (int64_t i = (int64_t)wave * 4 + rl; i < n; i += NW * 4) {
-                const double c = t.cs ? t.cs[i] : 1.0;
-                const double y = T[i * 16 + col] - c * S.gR[t.grp[i] * 16 + col];
-                const double r = y - th * X[i * ld + col];
-                acc += r * r;
-            }
-            acc += __shfl_xor(acc, 16);
-            acc += __shfl_xor(acc, 32);
-            if (rl == 0) S.W[wave * 16 + col] = acc;
+        for (int off = 1; off < NT; off <<= 1) {
+            const int v = threadIdx.x >= off ? S.iscan[threadIdx.x - off] : 0;
             __syncthreads();
-            if (threadIdx.x < 16 && c0 + threadIdx.x < k) {
-                double s2 = 0.0;
-                for (int w = 0; w < NW; ++w) s2 += S.W[w * 16 + threadIdx.x];
-                S.res[threadIdx.x] = sqrt(s2) / t.sigma;
-            }
+            S.iscan[threadIdx.x] += v;
             __syncthreads();
-            if (threadIdx.x == 0)
-                for (int j = 0; j < 16 && c0 + j < k; ++j) maxres = fmax(maxres, S.res[j]);
         }
-        // sign: the largest-magnitude entry of each column of H positive
-        // (lowest row on ties)
-        double best = -1.0;
-        int64_t bi = 0;
-        double bv = 0.0;
-        for (int64_t i = (int64_t)wave * 4 + rl; i < n; i += NW * 4) {
-            const double v = (t.cs ? t.cs[i] : 1.0) * X[i * ld + col];
-            const double a = fabs(v);
-            if (a > best) {
-                best = a;
-                bi = i;
-                bv = v;
-            }
+        const int excl = base + S.iscan[threadIdx.x] - cnt;
+        if (cnt) {
+            const int i0 = L.graphs[gi].item0;
+            for (int j = 0; j < cnt; ++j) L.alist[excl + j] = i0 + j;
         }
-#pragma unroll
-        for (int off = 16; off < 64; off <<= 1) {
-            const double ob = __shfl_xor(best, off);
-            const int64_t oi = __shfl_xor(bi, off);
-            const double ov = __shfl_xor(bv, off);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-                bv = ov;
-            }
-        }
-        double* Wb = S.W;
-        int64_t* Wi = reinterpret_cast<int64_t*>(S.W + NW * 16);
-        double* Wv = S.W + 2 * NW * 16;
-        if (rl == 0) {
-            Wb[wave * 16 + col] = best;
-            Wi[wave * 16 + col] = bi;
-            Wv[wave * 16 + col] = bv;
-        }
-        __syncthreads();
-        if (threadIdx.x < 16) {
-            double b0 = -1.0, v0 = 0.0;
-            int64_t i0 = 0;
-            for (int w = 0; w < NW; ++w) {
-                const double ob = Wb[w * 16 + threadIdx.x];
-                const int64_t oi = Wi[w * 16 + threadIdx.x];
-                if (ob > b0 || (ob == b0 && oi < i0)) {
-                    b0 = ob;
-                    i0 = oi;
-                    v0 = Wv[w * 16 + threadIdx.x];
-                }
-            }
-            S.res[16 + threadIdx.x] = v0 < 0.0 ? -1.0 : 1.0;
-        }
-        __syncthreads();
-        const int kc = min(16, k - c0);
-        for (int64_t idx = threadIdx.x; idx < n * kc; idx += NT) {
-            const int j = (int)(idx / n);
-            const int64_t i = idx - (int64_t)j * n;
-            const double c = t.cs ? t.cs[i] : 1.0;
-            t.H[(int64_t)(c0 + j) * n + i] = S.res[16 + j] * c * X[i * ld + j];
-        }
+        base += S.iscan[NT - 1];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && t.certify) st.max_rel_residual = maxres;
+    if (threadIdx.x == 0) *L.nalist = base;
 }
+
+__device__ __forceinline__ void add_ticks(GState& s, int ph, uint64_t t0) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&s.ph[ph], (uint64_t)(wall_clock64() - t0), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Row phase: every workgroup takes the listed items blockIdx.x,
+// + gridDim.x, ...; the body sees g (graph), s (state), it (item), wr0 / wr1
+// (this wavefront's rows), wt0 / wt1 (its 16-row tiles), slot (the item's
+// partial slot) and wp (this wavefront's LDS partial).  COND must be uniform
+// for the graph.
+#define SF_ITEMS(PH, COND, ...)                                                                   \
+    for (int j_ = blockIdx.x, n_ = *L.nalist; j_ < n_; j_ += gridDim.x) {                         \
+        const int it = L.alist[j_];                                                               \
+        const Item itm = L.items[it];                                                             \
+        const Graph& g = L.graphs[itm.g];                                                         \
+        GState& s = L.st[itm.g];                                                                  \
+        if (!(COND)) continue;                                                                    \
+        const uint64_t t0_ = wall_clock64();                                                      \
+        const int64_t wr0 = min(g.n, itm.row0 + (int64_t)wave * WROWS);                          \
+        const int64_t wr1 = min(g.n, wr0 + WROWS);                                                \
+        const int64_t wt0 = wr0 >> 4, wt1 = wr1 > wr0 ? (wr1 + 15) >> 4 : wt0;                  \
+        double* slot = L.part + (size_t)it * PSTRIDE;                                             \
+        double* wp = S.u.wred + wave * WRED;                                                      \
+        (void)wt0;                                                                                \
+        (void)wt1;                                                                                \
+        (void)slot;                                                                               \
+        (void)wp;                                                                                 \
+        __VA_ARGS__;                                                                              \
+        add_ticks(s, PH, t0_);                                                                    \
+    }
+
+// Graph phase: workgroup blockIdx.x owns graphs blockIdx.x, + gridDim.x, ...
+// Every thread reads COND before the body may change the state.
+#define SF_GRAPHS(PH, COND, ...)                                \
+    for (int gi = blockIdx.x; gi < L.ng; gi += gridDim.x) {     \
+        const Graph& g = L.graphs[gi];                          \
+        GState& s = L.st[gi];                                   \
+        const bool on_ = (COND);                                \
+        __syncthreads();                                        \
+        if (!on_) continue;                                     \
+        const uint64_t t0_ = wall_clock64();                    \
+        __VA_ARGS__;                                            \
+        add_ticks(s, PH, t0_);                                  \
+    }
 
 template <class SpT>
-__device__ __noinline__ void solve(const Task& t, TaskStat* stp, Shared& S, uint64_t seed) {
+__global__ __launch_bounds__(NT) void k_batched(Launch L) {
+    __shared__ Shared S;
+    cg::grid_group grid = cg::this_grid();
     const int tid = threadIdx.x;
-    const int64_t n = t.n;
-    const int b = t.b, ld = t.ld, ncv = t.ncv, k = t.k;
-    double* V = t.V;
-    TaskStat st{};
-    if (tid == 0) {
-        st.t_begin = wall_clock64();
-        S.tmark = st.t_begin;
-        for (int i = 0; i < 8; ++i) S.ph[i] = 0;
-    }
-    const double thresh = (1e-10 * t.sigma) * (1e-10 * t.sigma);
-    const double tolabs = t.tol_conv * t.sigma;
-    int status = 0;
-    int m = 0, restarts = 0, steps = 0, nconv = 0;
+    const int wave = tid >> 6;
 
-    if (!(b == 4 || b == 8 || b == 16) || ncv > NCVMAX || ncv % 4 != 0 || ld < ncv + b || ld % 4 != 0 ||
-        k < 1 || k > KMAXB || k + b >= ncv || ld < ((k + 15) / 16) * 16 || t.h < 1 || t.h > HMAX || t.rows < 1 ||
-        t.rows > 64 || (t.rows & (t.rows - 1)) != 0 || n < 2 * (int64_t)ld) {
-        status = 4;
-        goto done;
-    }
+    // ---- set-up and the random start block ----------------------------------
+    if (blockIdx.x == 0 && tid == 0) *L.t_start = wall_clock64();
+    SF_GRAPHS(PH_IO, true, {
+        const bool ok = (g.b == 4 || g.b == 8 || g.b == 16) && g.ncv <= NCVMAX && g.ncv % 4 == 0 &&
+                        g.ld >= g.ncv + g.b && g.ld % 4 == 0 && g.k >= 1 && g.k <= KMAXB && g.k + g.b < g.ncv &&
+                        g.ld >= ((g.k + 15) / 16) * 16 && g.h >= 1 && g.h <= HMAX && g.rows >= 1 && g.rows <= 64 &&
+                        (g.rows & (g.rows - 1)) == 0 && g.n >= 2 * (int64_t)g.ld;
+        if (tid == 0) {
+            s.active = 1;
+            s.status = 0;
+            s.out = 0;
+            s.m = 0;
+            s.restarts = 0;
+            s.steps = 0;
+            s.nconv = 0;
+            s.rot_p = 0;
+            s.est = 0.0;
+            s.gap = 0.0;
+            s.maxres = 0.0;
+            s.t_done = 0;
+            for (int q = 0; q < 8; ++q) s.ph[q] = 0;
+            if (!ok) stop(s, 4, L.active);
+        }
+        for (int e = tid; e < 256; e += NT) g.sm[OFF_M + e] = ((e >> 4) == (e & 15)) ? 1.0 : 0.0;
+    });
+    grid.sync();
+    if (blockIdx.x == 0) build_list(L, false, S);
+    grid.sync();
+    // random start block and its group sums
+    SF_ITEMS(PH_IO, s.active, {
+        const int b = g.b;
+        for (int64_t idx = (tid & 63); idx < (wr1 - wr0) * b; idx += 64) {
+            const int64_t i = wr0 + idx / b;
+            const int j = (int)(idx % b);
+            g.V[i * g.ld + j] = rnd_pm1(g.seed, (uint64_t)(i * b + j));
+        }
+        __syncthreads();
+        w_gsum(g.V, g.ld, wr0, wr1, b, g.h, g.grp, g.cs, wp);
+        wg_combine(S.u.wred, g.h * 16, b, slot);
+    });
+    grid.sync();
+    SF_GRAPHS(PH_IO, s.active, {
+        g_reduce(L.part, g.item0, g.nitems, g.h * g.b, S.red);
+        g_finalize(S.red, g.h, g.b, g.gpar, nullptr, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+    });
+    grid.sync();
+    // projection onto null(C^T), then the Gram matrix (first Cholesky-QR pass, M = I)
+    SF_ITEMS(PH_IO, s.active, {
+        w_proj<double>(g.V, g.ld, wr0, wr1, g.b, g.grp, g.cs, g.sm + OFF_TAB, g.V, g.ld);
+        __syncthreads();
+        w_upd<false, true>(g.n, g.V, g.ld, 0, g.b, 0, g.b, 0, g.sm + OFF_M, wt0, wt1, S.u.wred, slot);
+    });
+    grid.sync();
+    SF_GRAPHS(PH_IO, s.active, {
+        g_reduce(L.part, g.item0, g.nitems, g.b * g.b, S.red);
+        if (!g_chol(S.red, g.b, 0.0, S.R1, S.Ri, S)) {
+            if (tid == 0) stop(s, 2, L.active);
+        } else {
+            for (int e = tid; e < 256; e += NT) g.sm[OFF_M + e] = S.Ri[e];
+        }
+    });
+    grid.sync();
+    SF_ITEMS(PH_IO, s.active,
+             w_upd<false, true>(g.n, g.V, g.ld, 0, g.b, 0, g.b, 0, g.sm + OFF_M, wt0, wt1, S.u.wred, slot));
+    grid.sync();
+    SF_GRAPHS(PH_IO, s.active, {
+        g_reduce(L.part, g.item0, g.nitems, g.b * g.b, S.red);
+        if (!g_chol(S.red, g.b, 0.25, S.R2, S.Ri, S)) {
+            if (tid == 0) stop(s, 2, L.active);
+        } else {
+            for (int e = tid; e < 256; e += NT) g.sm[OFF_M + e] = S.Ri[e];
+        }
+    });
+    grid.sync();
+    // the orthonormal start block, and its group sums for the first operator
+    SF_ITEMS(PH_IO, s.active, {
+        w_upd<false, false>(g.n, g.V, g.ld, 0, g.b, 0, g.b, 0, g.sm + OFF_M, wt0, wt1, S.u.wred, slot);
+        __syncthreads();
+        w_gsum(g.V, g.ld, wr0, wr1, g.b, g.h, g.grp, g.cs, wp);
+        wg_combine(S.u.wred, g.h, g.b, slot);
+    });
+    grid.sync();
+    SF_GRAPHS(PH_IO, s.active, {
+        g_reduce(L.part, g.item0, g.nitems, g.h * g.b, S.red);
+        g_finalize(S.red, g.h, g.b, g.gpar, g.sm + OFF_TAB + HMAX * 16, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+    });
+    grid.sync();
 
-    // random start block, projected onto null(C^T), orthonormalised
-    for (int64_t idx = tid; idx < n * b; idx += NT) {
-        const int64_t i = idx / b;
-        const int j = (int)(idx - i * b);
-        V[i * ld + j] = rnd_pm1(seed, (uint64_t)idx);
-    }
-    __syncthreads();
-    group_sums(V, ld, n, b, t.h, t.grp, t.cs, S.W, S.gA);
-    group_finalize(S.gA, t.h, b, t.gpar, nullptr, nullptr, 0.0, S.gZ, S.gR);
-    proj_apply<double>(V, ld, n, b, t.grp, t.cs, S.gR, V, ld);
-    __syncthreads();
-    if (!cholqr2(n, V, ld, 0, b, 0.0, S)) {
-        status = 2;
-        goto done;
-    }
-
-    for (;;) {
-        // expansions: basis [0, m), current block [m, m + b)
-        phase_mark(S, 7);
-        while (m + b <= ncv) {
-            const int cv = m + b;
-            apply_operator<SpT>(t, V + m, ld, b, t.rows, S);
-            phase_mark(S, 0);
-            double* out = S.W + WTILES;
-            double* M = S.W;
-            pass_a<SpT>(t, V, ld, cv, b, static_cast<const SpT*>(t.tt), S.gR, out);
-            // H1 -> T column block, M1 = [-H1; I]
+    // ---- block steps: basis V[:, 0:m], current block V[:, m : m + b] ----------
+    int listed = -1;  // active count when the item list was built
+    for (int step = 0; step < L.max_steps; ++step) {
+        const int act = __hip_atomic_load(L.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (act <= 0) break;
+        if (act != listed) {
+            if (blockIdx.x == 0) build_list(L, false, S);
+            grid.sync();
+            listed = act;
+        }
+        // restart rotation (if pending), then X' = P X (the tables of X are current)
+        SF_ITEMS(PH_OP, s.active, {
+            if (s.rot_p > 0) {
+                w_rotate(g.n, g.V, g.ld, s.rot_m, g.sm + OFF_Z, NCVMAX, s.rot_p, s.rot_nb, wt0, wt1);
+                add_ticks(s, PH_ROT, t0_);
+                if (tid == 0)
+                    __hip_atomic_fetch_add(&s.ph[PH_OP], (uint64_t)0 - (wall_clock64() - t0_), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            w_proj<SpT>(g.V + s.m, g.ld, wr0, wr1, g.b, g.grp, g.cs, g.sm + OFF_TAB, static_cast<SpT*>(g.xp), g.b);
+        });
+        grid.sync();
+        // sparse product and its group sums
+        SF_ITEMS(PH_OP, s.active, {
+            w_spmm<SpT>(g, static_cast<const SpT*>(g.xp), static_cast<SpT*>(g.tt), wr0, wr1, g.b, g.rows);
+            __syncthreads();
+            w_gsum(static_cast<const SpT*>(g.tt), g.b, wr0, wr1, g.b, g.h, g.grp, g.cs, wp);
+            wg_combine(S.u.wred, g.h, g.b, slot);
+        });
+        grid.sync();
+        SF_GRAPHS(PH_OP, s.active, {
+            if (tid == 0) s.rot_p = 0;
+            g_reduce(L.part, g.item0, g.nitems, g.h * g.b, S.red);
+            g_finalize(S.red, g.h, g.b, g.gpar, nullptr, g.sm + OFF_TAB + HMAX * 16, g.sigma, S.gZ,
+                       g.sm + OFF_TAB + 2 * HMAX * 16);
+        });
+        grid.sync();
+        // pass A: output deflation Y0 = T - C U and H1 = V^T Y0
+        SF_ITEMS(PH_A, s.active,
+                 w_pass_a<SpT>(g, g.V, g.ld, s.m + g.b, g.b, static_cast<const SpT*>(g.tt),
+                               g.sm + OFF_TAB + 2 * HMAX * 16, wt0, wt1, S.u.wred, slot));
+        grid.sync();
+        SF_GRAPHS(PH_A, s.active, {
+            const int m = s.m, b = g.b, cv = m + b;
+            double* T = g.sm + OFF_T;
+            double* M = g.sm + OFF_M;
+            g_reduce(L.part, g.item0, g.nitems, cv * b, S.red);
+            // H1 into T's column block; M1 = [-H1; I]
             for (int e = tid; e < (cv + b) * 16; e += NT) {
                 const int q = e >> 4, j = e & 15;
                 if (q < cv) {
-                    const double hv = j < b ? tile_el(out, q, j) : 0.0;
+                    const double hv = j < b ? S.red[q * b + j] : 0.0;
                     M[e] = -hv;
                     if (j < b) {
-                        S.T[q * LDT + m + j] = hv;
-                        if (q < m) S.T[(m + j) * LDT + q] = hv;
+                        T[q * NCVMAX + m + j] = hv;
+                        if (q < m) T[(m + j) * NCVMAX + q] = hv;
                     }
                 } else {
                     M[e] = (q - cv == j) ? 1.0 : 0.0;
                 }
             }
-            __syncthreads();
-            phase_mark(S, 1);
-            pass_upd<true, true>(n, V, ld, 0, cv + b, cv, b, cv, M, out);
-            // T column block += H2, symmetrised diagonal block
+        });
+        grid.sync();
+        // pass B: Y' = Y0 - V H1; H2 = V^T Y', G1 = Y'^T Y'
+        SF_ITEMS(PH_B, s.active,
+                 w_upd<true, true>(g.n, g.V, g.ld, 0, s.m + 2 * g.b, s.m + g.b, g.b, s.m + g.b, g.sm + OFF_M, wt0,
+                                   wt1, S.u.wred, slot));
+        grid.sync();
+        SF_GRAPHS(PH_B, s.active, {
+            const int m = s.m, b = g.b, cv = m + b;
+            const double thresh = (1e-10 * g.sigma) * (1e-10 * g.sigma);
+            double* T = g.sm + OFF_T;
+            double* M = g.sm + OFF_M;
+            g_reduce(L.part, g.item0, g.nitems, (cv + b) * b, S.red);
             for (int e = tid; e < cv * b; e += NT) {
                 const int q = e / b, j = e - q * b;
-                const double hv = tile_el(out, q, j);
-                S.T[q * LDT + m + j] += hv;
-                if (q < m) S.T[(m + j) * LDT + q] += hv;
+                const double hv = S.red[q * b + j];
+                T[q * NCVMAX + m + j] += hv;
+                if (q < m) T[(m + j) * NCVMAX + q] += hv;
             }
             __syncthreads();
             for (int e = tid; e < b * b; e += NT) {
                 const int i = e / b, j = e - i * b;
                 if (j > i) {
-                    const double a = S.T[(m + i) * LDT + m + j], c = S.T[(m + j) * LDT + m + i];
+                    const double a = T[(m + i) * NCVMAX + m + j], c = T[(m + j) * NCVMAX + m + i];
                     const double mv = 0.5 * (a + c);
-                    S.T[(m + i) * LDT + m + j] = mv;
-                    S.T[(m + j) * LDT + m + i] = mv;
+                    T[(m + i) * NCVMAX + m + j] = mv;
+                    T[(m + j) * NCVMAX + m + i] = mv;
                 }
             }
-            const int nrt = (cv + 15) >> 4;
-            if (!chol16(out + (size_t)nrt * 256, b, thresh, S.R1, S.Ri, S)) {
-                status = 2;
-                goto done;
+            if (!g_chol(S.red + cv * b, b, thresh, S.R1, S.Ri, S)) {
+                if (tid == 0) stop(s, 2, L.active);
+            } else {
+                for (int e = tid; e < 256; e += NT) g.sm[OFF_R + e] = S.R1[e];
+                // M2 = [-H2 R1^{-1}; R1^{-1}]
+                for (int e = tid; e < (cv + b) * 16; e += NT) {
+                    const int q = e >> 4, j = e & 15;
+                    double acc = 0.0;
+                    if (j < b) {
+                        if (q < cv) {
+                            for (int u = 0; u <= j; ++u) acc -= S.red[q * b + u] * S.Ri[u * 16 + j];
+                        } else {
+                            acc = S.Ri[(q - cv) * 16 + j];
+                        }
+                    }
+                    M[e] = acc;
+                }
             }
-            // M2 = [-H2 R1^{-1}; R1^{-1}]
-            for (int e = tid; e < (cv + b) * 16; e += NT) {
-                const int q = e >> 4, j = e & 15;
-                double acc = 0.0;
-                if (j < b) {
-                    if (q < cv) {
-                        for (int u = 0; u <= j; ++u) acc -= tile_el(out, q, u) * S.Ri[u * 16 + j];
-                    } else {
-                        acc = S.Ri[(q - cv) * 16 + j];
+        });
+        grid.sync();
+        // pass C: Y1 = (Y' - V H2) R1^{-1}, G2 = Y1^T Y1
+        SF_ITEMS(PH_C, s.active,
+                 w_upd<false, true>(g.n, g.V, g.ld, 0, s.m + 2 * g.b, s.m + g.b, g.b, s.m + g.b, g.sm + OFF_M,
+                                    wt0, wt1, S.u.wred, slot));
+        grid.sync();
+        SF_GRAPHS(PH_C, s.active, {
+            g_reduce(L.part, g.item0, g.nitems, g.b * g.b, S.red);
+            for (int e = tid; e < 256; e += NT) S.R1[e] = g.sm[OFF_R + e];
+            __syncthreads();
+            if (!g_chol(S.red, g.b, 0.25, S.R2, S.Ri, S)) {
+                if (tid == 0) stop(s, 2, L.active);
+            } else {
+                // coupling Rc = R2 R1; M3 = R2^{-1}
+                for (int e = tid; e < 256; e += NT) {
+                    const int i = e >> 4, j = e & 15;
+                    double acc = 0.0;
+                    for (int u = i; u <= j; ++u) acc += S.R2[i * 16 + u] * S.R1[u * 16 + j];
+                    g.sm[OFF_R + 256 + e] = acc;
+                    g.sm[OFF_M + e] = S.Ri[e];
+                }
+            }
+        });
+        grid.sync();
+        // pass D: the next block, and its group sums
+        SF_ITEMS(PH_D, s.active, {
+            const int cv = s.m + g.b;
+            w_upd<false, false>(g.n, g.V, g.ld, cv, g.b, cv, g.b, 0, g.sm + OFF_M, wt0, wt1, S.u.wred, slot);
+            __syncthreads();
+            w_gsum(g.V + cv, g.ld, wr0, wr1, g.b, g.h, g.grp, g.cs, wp);
+            wg_combine(S.u.wred, g.h, g.b, slot);
+        });
+        grid.sync();
+        // tables of the next block; Rayleigh-Ritz and the restart when the basis is full
+        SF_GRAPHS(PH_D, s.active, {
+            const int b = g.b, k = g.k;
+            const int m = s.m + b;
+            const int restarts = s.restarts, steps = s.steps + 1;
+            g_reduce(L.part, g.item0, g.nitems, g.h * b, S.red);
+            g_finalize(S.red, g.h, b, g.gpar, g.sm + OFF_TAB + HMAX * 16, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+            if (m + b <= g.ncv) {
+                if (tid == 0) {
+                    s.m = m;
+                    s.steps = steps;
+                }
+            } else {
+                const uint64_t trr = wall_clock64();
+                const double* T = g.sm + OFF_T;
+                for (int e = tid; e < m * m; e += NT) {
+                    const int i = e / m, j = e - i * m;
+                    S.u.j.A[i * LDT + j] = T[i * NCVMAX + j];
+                }
+                for (int e = tid; e < 256; e += NT) S.R2[e] = g.sm[OFF_R + 256 + e];  // coupling Rc
+                __syncthreads();
+                g_jacobi(S.u.j.A, m, S.u.j.Z, S);
+                if (tid < m) {
+                    const double w = S.u.j.A[tid * LDT + tid];
+                    int rank = 0;
+                    for (int j = 0; j < m; ++j) {
+                        const double o = S.u.j.A[j * LDT + j];
+                        rank += (o < w || (o == w && j < tid)) ? 1 : 0;
+                    }
+                    S.perm[rank] = tid;
+                    S.theta[rank] = w;
+                }
+                __syncthreads();
+                // residual estimates ||Rc z_last|| of the Ritz pairs
+                if (tid < m) {
+                    const int c = S.perm[tid];
+                    double s2 = 0.0;
+                    for (int i = 0; i < b; ++i) {
+                        double v = 0.0;
+                        for (int j = i; j < b; ++j) v += S.R2[i * 16 + j] * S.u.j.Z[(m - b + j) * LDT + c];
+                        s2 += v * v;
+                    }
+                    S.res[tid] = sqrt(s2);
+                }
+                if (tid == 0) {
+                    bool finite = true;
+                    for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
+                    S.iflag[1] = finite ? 1 : 0;
+                }
+                __syncthreads();
+                const bool finite = S.iflag[1] != 0;
+                int nconv = 0;
+                double est = 0.0;
+                const double tolabs = g.tol_conv * g.sigma;
+                for (int r = 0; r < k; ++r) {
+                    nconv += S.res[r] <= tolabs ? 1 : 0;
+                    est = fmax(est, S.res[r]);
+                }
+                const bool done = nconv == k || restarts >= g.max_restarts;
+                // rotation: the k Ritz vectors when done, else the p kept ones
+                // (k < p <= m - b, p a multiple of b)
+                const int ptarget = max(k + 1, (m + k) / 2);
+                const int nd = max(1, (m - ptarget) / b);
+                const int p = done ? k : m - nd * b;
+                double* Zg = g.sm + OFF_Z;
+                for (int e = tid; e < m * p; e += NT) {
+                    const int q = e / p, r = e - q * p;
+                    Zg[q * NCVMAX + r] = S.u.j.Z[q * LDT + S.perm[r]];
+                }
+                for (int r = tid; r < m; r += NT) g.sm[OFF_AUX + r] = S.theta[r];
+                if (!done) {
+                    double* Tw = g.sm + OFF_T;
+                    for (int e = tid; e < p * p; e += NT) {
+                        const int i = e / p, j = e - i * p;
+                        Tw[i * NCVMAX + j] = (i == j) ? S.theta[i] : 0.0;
                     }
                 }
-                M[e] = acc;
+                if (tid == 0) {
+                    s.steps = steps;
+                    s.nconv = nconv;
+                    s.est = est / g.sigma;
+                    s.gap = m > k ? (S.theta[k] - S.theta[k - 1]) / g.sigma : 0.0;
+                    if (!finite) {
+                        stop(s, 2, L.active);
+                    } else {
+                        s.rot_m = m;
+                        s.rot_p = p;
+                        s.rot_nb = done ? 0 : b;
+                        if (done) {
+                            s.out = 1;
+                            stop(s, nconv == k ? 0 : 1, L.active);
+                        } else {
+                            s.m = p;
+                            s.restarts = restarts + 1;
+                        }
+                    }
+                }
+                // this part of the phase counts as Rayleigh-Ritz time
+                __syncthreads();
+                if (tid == 0) {
+                    const uint64_t d = wall_clock64() - trr;
+                    __hip_atomic_fetch_add(&s.ph[PH_RR], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&s.ph[PH_D], (uint64_t)0 - d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
-            __syncthreads();
-            phase_mark(S, 2);
-            pass_upd<false, true>(n, V, ld, 0, cv + b, cv, b, cv, M, out);
-            if (!chol16(out, b, 0.25, S.R2, S.Ri, S)) {
-                status = 2;
-                goto done;
-            }
-            // Rc = R2 R1; M3 = R2^{-1}
-            for (int e = tid; e < 256; e += NT) {
-                const int i = e >> 4, j = e & 15;
-                double acc = 0.0;
-                for (int u = i; u <= j; ++u) acc += S.R2[i * 16 + u] * S.R1[u * 16 + j];
-                S.Rc[e] = acc;
-                M[e] = S.Ri[e];
-            }
-            __syncthreads();
-            phase_mark(S, 3);
-            pass_upd<false, false>(n, V, ld, cv, b, cv, b, 0, M, out);
-            __syncthreads();
-            phase_mark(S, 4);
-            m = cv;
-            ++steps;
-        }
+        });
+        grid.sync();
+    }
+    // graphs still iterating at the step limit: not converged, no output
+    SF_GRAPHS(PH_IO, s.active, {
+        if (tid == 0) stop(s, 1, L.active);
+    });
+    grid.sync();
 
-        // Rayleigh-Ritz on T[0:m, 0:m]
-        jacobi(S.T, LDT, m, S.W, LDT, S);
-        if (tid < m) S.perm[tid] = tid;
-        __syncthreads();
-        if (tid < m) {
-            const double w = S.T[tid * LDT + tid];
-            int rank = 0;
-            for (int j = 0; j < m; ++j) {
-                const double o = S.T[j * LDT + j];
-                rank += (o < w || (o == w && j < tid)) ? 1 : 0;
+    // ---- output: Ritz vectors, projection, certification, signs, H -------------
+    if (blockIdx.x == 0) build_list(L, true, S);
+    grid.sync();
+    SF_ITEMS(PH_IO, s.out && s.rot_p > 0,
+             w_rotate(g.n, g.V, g.ld, s.rot_m, g.sm + OFF_Z, NCVMAX, s.rot_p, 0, wt0, wt1));
+    grid.sync();
+    for (int c0 = 0; c0 < KMAXB; c0 += 16) {
+        SF_ITEMS(PH_IO, s.out && g.k > c0, {
+            w_gsum(g.V + c0, g.ld, wr0, wr1, 16, g.h, g.grp, g.cs, wp);
+            wg_combine(S.u.wred, g.h, 16, slot);
+        });
+        grid.sync();
+        SF_GRAPHS(PH_IO, s.out && g.k > c0, {
+            g_reduce(L.part, g.item0, g.nitems, g.h * 16, S.red);
+            g_finalize(S.red, g.h, 16, g.gpar, nullptr, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+        });
+        grid.sync();
+        // projection in place; with certification, the group sums of the result
+        SF_ITEMS(PH_IO, s.out && g.k > c0, {
+            w_proj<double>(g.V + c0, g.ld, wr0, wr1, 16, g.grp, g.cs, g.sm + OFF_TAB, g.V + c0, g.ld);
+            if (g.certify) {
+                __syncthreads();
+                w_gsum(g.V + c0, g.ld, wr0, wr1, 16, g.h, g.grp, g.cs, wp);
+                wg_combine(S.u.wred, g.h, 16, slot);
             }
-            S.perm[rank] = tid;
-            S.theta[rank] = w;
-        }
+        });
+        grid.sync();
+        // certification: one FP64 application of the operator to the 16 columns
+        SF_GRAPHS(PH_IO, s.out && g.k > c0 && g.certify, {
+            g_reduce(L.part, g.item0, g.nitems, g.h * 16, S.red);
+            g_finalize(S.red, g.h, 16, g.gpar, g.sm + OFF_TAB + HMAX * 16, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+        });
+        grid.sync();
+        SF_ITEMS(PH_IO, s.out && g.k > c0 && g.certify,
+                 w_proj<double>(g.V + c0, g.ld, wr0, wr1, 16, g.grp, g.cs, g.sm + OFF_TAB,
+                                static_cast<double*>(g.xp), 16));
+        grid.sync();
+        SF_ITEMS(PH_IO, s.out && g.k > c0 && g.certify, {
+            w_spmm<double>(g, static_cast<const double*>(g.xp), static_cast<double*>(g.tt), wr0, wr1, 16, 8);
+            __syncthreads();
+            w_gsum(static_cast<const double*>(g.tt), 16, wr0, wr1, 16, g.h, g.grp, g.cs, wp);
+            wg_combine(S.u.wred, g.h, 16, slot);
+        });
+        grid.sync();
+        SF_GRAPHS(PH_IO, s.out && g.k > c0 && g.certify, {
+            g_reduce(L.part, g.item0, g.nitems, g.h * 16, S.red);
+            g_finalize(S.red, g.h, 16, g.gpar, nullptr, g.sm + OFF_TAB + HMAX * 16, g.sigma, S.gZ,
+                       g.sm + OFF_TAB + 2 * HMAX * 16);
+        });
+        grid.sync();
+        // residual and sign partials
+        SF_ITEMS(PH_IO, s.out && g.k > c0, {
+            if (g.certify) {
+                w_resid(g, g.V + c0, g.ld, static_cast<const double*>(g.tt), g.sm + OFF_TAB + 2 * HMAX * 16,
+                        g.sm + OFF_AUX + c0, min(16, g.k - c0), wr0, wr1, wp);
+            } else if ((tid & 63) < 16) {
+                wp[tid & 63] = 0.0;
+            }
+            w_signs(g, g.V + c0, g.ld, wr0, wr1, wp + 16);
+            __syncthreads();
+            if (tid < 16) {
+                double r2 = 0.0, b0 = -1.0, i0 = 0.0, v0 = 0.0;
+                for (int w = 0; w < NW; ++w) {
+                    r2 += S.u.wred[w * WRED + tid];
+                    sign_merge(S.u.wred + w * WRED + 16, b0, i0, v0);
+                }
+                slot[tid] = r2;
+                slot[16 + tid] = b0;
+                slot[32 + tid] = i0;
+                slot[48 + tid] = v0;
+            }
+            __syncthreads();
+        });
+        grid.sync();
+        SF_GRAPHS(PH_IO, s.out && g.k > c0, {
+            if (tid < 16) {
+                double r2 = 0.0, b0 = -1.0, i0 = 0.0, v0 = 0.0;
+                for (int it = 0; it < g.nitems; ++it) {
+                    const double* p = L.part + (size_t)(g.item0 + it) * PSTRIDE;
+                    r2 += p[tid];
+                    sign_merge(p + 16, b0, i0, v0);
+                }
+                S.res[tid] = sqrt(r2) / g.sigma;
+                g.sm[OFF_AUX + NCVMAX + tid] = v0 < 0.0 ? -1.0 : 1.0;
+            }
+            __syncthreads();
+            if (tid == 0 && g.certify) {
+                double mr = s.maxres;
+                for (int j = 0; j < 16 && c0 + j < g.k; ++j) mr = fmax(mr, S.res[j]);
+                s.maxres = mr;
+            }
+        });
+        grid.sync();
+        // H = sign * C-scaled columns (D^{-1/2} X when normalized), column-major
+        SF_ITEMS(PH_IO, s.out && g.k > c0, {
+            const int kc = min(16, g.k - c0);
+            const int64_t nr = wr1 - wr0;
+            for (int64_t idx = (tid & 63); idx < nr * kc; idx += 64) {
+                const int j = (int)(idx / nr);
+                const int64_t i = wr0 + (idx - (int64_t)j * nr);
+                const double c = g.cs ? g.cs[i] : 1.0;
+                g.H[(int64_t)(c0 + j) * g.n + i] = g.sm[OFF_AUX + NCVMAX + j] * c * g.V[i * g.ld + c0 + j];
+            }
+        });
+        grid.sync();
+    }
+    SF_GRAPHS(PH_IO, s.out, {
+        for (int r = tid; r < g.k; r += NT) g.theta[r] = g.sm[OFF_AUX + r];
         if (tid == 0) {
-            bool finite = true;
-            for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
-            S.iflag[1] = finite ? 1 : 0;
+            if (!g.certify) s.maxres = s.est;
+            if (s.status == 0 && g.certify && s.maxres > g.tol) s.status = 3;
         }
-        __syncthreads();
-        if (!S.iflag[1]) {
-            status = 2;
-            goto done;
-        }
-        // residual estimates ||Rc z_last|| of the Ritz pairs
-        if (tid < m) {
-            const int c = S.perm[tid];
-            double s2 = 0.0;
-            for (int i = 0; i < b; ++i) {
-                double v = 0.0;
-                for (int j = i; j < b; ++j) v += S.Rc[i * 16 + j] * S.W[(m - b + j) * LDT + c];
-                s2 += v * v;
-            }
-            S.res[tid] = sqrt(s2);
-        }
-        __syncthreads();
-        nconv = 0;
-        double est = 0.0;
-        for (int r = 0; r < k; ++r) {
-            nconv += S.res[r] <= tolabs ? 1 : 0;
-            est = fmax(est, S.res[r]);
-        }
-        phase_mark(S, 5);
-        st.est_residual = est / t.sigma;
-        st.gap_ratio = m > k ? (S.theta[k] - S.theta[k - 1]) / t.sigma : 0.0;
-        if (nconv == k || restarts >= t.max_restarts) break;
-
-        // thick restart: keep p Ritz vectors (a multiple of 4, k < p <= m - b)
-        const int ptarget = max(k + 1, (m + k) / 2);
-        const int nd = max(1, (m - ptarget) / b);
-        const int p = m - nd * b;
-        for (int e = tid; e < m * p; e += NT) {
-            const int q = e / p, r = e - q * p;
-            S.T[q * LDT + r] = S.W[q * LDT + S.perm[r]];
-        }
-        __syncthreads();
-        rotate(n, V, ld, m, S.T, LDT, p, m, b);
-        __syncthreads();
-        for (int e = tid; e < p * p; e += NT) {
-            const int i = e / p, j = e - i * p;
-            S.T[i * LDT + j] = (i == j) ? S.theta[i] : 0.0;
-        }
-        __syncthreads();
-        phase_mark(S, 6);
-        m = p;
-        ++restarts;
-    }
-
-    // Ritz vectors V[:, 0:k] = V[:, 0:m] Z[:, 0:k]
-    for (int e = tid; e < m * k; e += NT) {
-        const int q = e / k, r = e - q * k;
-        S.T[q * LDT + r] = S.W[q * LDT + S.perm[r]];
-    }
-    __syncthreads();
-    rotate(n, V, ld, m, S.T, LDT, k, 0, 0);
-    __syncthreads();
-    if (tid == 0) st.max_rel_residual = st.est_residual;
-    finish(t, st, V, ld, S);
-    for (int r = tid; r < k; r += NT) t.theta[r] = S.theta[r];
-    if (nconv < k)
-        status = 1;
-    else if (t.certify && st.max_rel_residual > t.tol)
-        status = 3;
-
-done:
-    __syncthreads();
-    if (tid == 0) {
-        st.status = status;
-        st.restarts = restarts;
-        st.block_steps = steps;
-        st.converged = nconv;
-        st.t_end = wall_clock64();
-        S.ph[7] += st.t_end - S.tmark;
-        for (int i = 0; i < 8; ++i) st.phase[i] = S.ph[i];
-        *stp = st;
-    }
-    __syncthreads();
+    });
 }
 
-template <class SpT>
-__global__ __launch_bounds__(NT) void k_batched(const Task* __restrict__ tasks, TaskStat* __restrict__ stats,
-                                                const int* __restrict__ order, int count, int* queue,
-                                                uint64_t seed) {
-    __shared__ Shared S;
-    for (;;) {
-        if (threadIdx.x == 0) S.cur = atomicAdd(queue, 1);
-        __syncthreads();
-        const int qi = S.cur;
-        __syncthreads();
-        if (qi >= count) break;
-        const int ti = order[qi];
-        {
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(tasks + ti);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(&S.task);
-            for (int w = threadIdx.x; w < (int)(sizeof(Task) / 4); w += NT) dst[w] = src[w];
-        }
-        __syncthreads();
-        solve<SpT>(S.task, stats + ti, S, seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(ti + 1)));
-    }
-}
+#undef SF_ITEMS
+#undef SF_GRAPHS
 
 __global__ void k_set_i32(int* p, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
-
-// ---------------------------------------------------------------------------
 // host side
 
 constexpr double kFloatTolFloor = 5e-7;  // tolerances below: double products
@@ -1195,6 +1492,7 @@ struct BatchWork {
     size_t pin_bytes = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int cus = 0;
+    int grid_f = 0, grid_d = 0;  // resident workgroups of the float / double launch
     int wall_khz = 0;
 };
 std::mutex g_bw_mu;
@@ -1208,16 +1506,17 @@ struct RunItem {
 };
 
 struct RunOut {
-    std::vector<TaskStat> st;
+    std::vector<GState> st;
     std::vector<double> theta;  // [count][KMAXB]
+    uint64_t t_start = 0;
     double kernel_ms = 0.0;
     double tick_ms = 0.0;  // ms per wall-clock tick
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Launch one persistent kernel over the items (each on its own workgroup
-// when count <= compute units).  Synchronises `stream`.
+// One cooperative launch over the items (every workgroup resident at once).
+// Synchronises `stream`.
 int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double sigma_override, int max_restarts,
               int certify, uint64_t seed, hipStream_t stream, RunOut* ro) {
     int dev = 0;
@@ -1228,20 +1527,42 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
     if (!w.cus) {
         hipDeviceProp_t prop;
         SF_HIP(hipGetDeviceProperties(&prop, dev));
-        w.cus = prop.multiProcessorCount;
+        int coop = 0;
+        SF_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+        if (!coop) return set_error(SFAIRSC_E_HIP, "device %d has no cooperative launches", dev);
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        int occ_f = 0, occ_d = 0;
+        SF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, reinterpret_cast<const void*>(&k_batched<float>),
+                                                           NT, 0));
+        SF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_d, reinterpret_cast<const void*>(&k_batched<double>),
+                                                           NT, 0));
+        if (occ_f < 1 || occ_d < 1) return set_error(SFAIRSC_E_HIP, "batched kernel cannot be resident on device %d", dev);
+        w.grid_f = prop.multiProcessorCount * occ_f;
+        w.grid_d = prop.multiProcessorCount * occ_d;
         w.wall_khz = khz;
         SF_HIP(hipEventCreate(&w.e0));
         SF_HIP(hipEventCreate(&w.e1));
+        w.cus = prop.multiProcessorCount;
     }
     const int count = (int)items.size();
-    // workspace layout
-    std::vector<size_t> offV(count), offX(count), offT(count), offH(count);
-    size_t tot = 0;
+    // launch order: estimated cost per row, largest first, so that the
+    // costliest items lead the item lists
     std::vector<double> cost(count);
+    std::vector<int> order(count);
     for (int i = 0; i < count; ++i) {
-        const RunItem& it = items[i];
+        const sfairsc_graph* g = items[i].g;
+        cost[i] = (double)items[i].cfg.b * ((double)g->nnz / (double)std::max<int64_t>(1, g->n) + 3.0 * items[i].cfg.ncv);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    // workspace layout (by launch position)
+    std::vector<size_t> offV(count), offX(count), offT(count), offH(count), offS(count);
+    std::vector<int> item0(count), nit(count);
+    size_t tot = 0;
+    int nitems = 0;
+    for (int i = 0; i < count; ++i) {
+        const RunItem& it = items[order[i]];
         const int64_t n = it.g->n;
         const int ld = std::max(it.cfg.ncv + it.cfg.b, round_up(it.k, 16));
         offV[i] = tot;
@@ -1252,34 +1573,48 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
         tot += align256((size_t)n * 16 * 8);
         offH[i] = tot;
         if (!it.H) tot += align256((size_t)n * it.k * 8);
-        cost[i] = (double)it.g->nnz + 8.0 * (double)n * it.cfg.ncv;
+        offS[i] = tot;
+        tot += align256((size_t)SMALL_DOUBLES * 8);
+        item0[i] = nitems;
+        nit[i] = (int)((n + IROWS - 1) / IROWS);
+        nitems += nit[i];
     }
+    const size_t offPart = tot;
+    tot += align256((size_t)nitems * PSTRIDE * 8);
     SF_TRY(w.big.ensure(std::max<size_t>(tot, 256)));
-    const size_t meta_bytes = align256(sizeof(Task) * count) + align256(sizeof(TaskStat) * count) +
-                              align256(sizeof(double) * KMAXB * count) + align256(sizeof(int) * count) + 256;
+    const size_t b_graphs = align256(sizeof(Graph) * count), b_items = align256(sizeof(Item) * nitems);
+    const size_t b_st = align256(sizeof(GState) * count), b_theta = align256(sizeof(double) * KMAXB * count);
+    const size_t b_list = align256(sizeof(int) * nitems);
+    const size_t meta_bytes = b_graphs + b_items + b_st + b_theta + b_list + 256 + 256;
     SF_TRY(w.meta.ensure(meta_bytes));
-    if (w.pin_bytes < meta_bytes) {
+    const size_t pin_need = std::max(b_graphs + b_items, b_st + b_theta + 256);
+    if (w.pin_bytes < pin_need) {
         if (w.pin) (void)hipHostFree(w.pin);
         w.pin = nullptr;
         w.pin_bytes = 0;
-        SF_HIP(hipHostMalloc(&w.pin, meta_bytes, 0));
-        w.pin_bytes = meta_bytes;
+        SF_HIP(hipHostMalloc(&w.pin, pin_need, 0));
+        w.pin_bytes = pin_need;
     }
     char* base = w.big.as<char>();
     char* mb = w.meta.as<char>();
-    Task* d_tasks = reinterpret_cast<Task*>(mb);
-    TaskStat* d_stats = reinterpret_cast<TaskStat*>(mb + align256(sizeof(Task) * count));
-    double* d_theta = reinterpret_cast<double*>(reinterpret_cast<char*>(d_stats) + align256(sizeof(TaskStat) * count));
-    int* d_order = reinterpret_cast<int*>(reinterpret_cast<char*>(d_theta) + align256(sizeof(double) * KMAXB * count));
-    int* d_queue = reinterpret_cast<int*>(reinterpret_cast<char*>(d_order) + align256(sizeof(int) * count));
+    Graph* d_graphs = reinterpret_cast<Graph*>(mb);
+    Item* d_items = reinterpret_cast<Item*>(mb + b_graphs);
+    GState* d_st = reinterpret_cast<GState*>(mb + b_graphs + b_items);
+    double* d_theta = reinterpret_cast<double*>(mb + b_graphs + b_items + b_st);
+    int* d_active = reinterpret_cast<int*>(mb + b_graphs + b_items + b_st + b_theta);
+    uint64_t* d_tstart = reinterpret_cast<uint64_t*>(mb + b_graphs + b_items + b_st + b_theta + 256);
+    int* d_alist = reinterpret_cast<int*>(mb + b_graphs + b_items + b_st + b_theta + 512);
+    int* d_nalist = d_active + 1;
 
+    // the upload goes through the pinned buffer (stream-ordered with the previous launch's download)
+    SF_HIP(hipStreamSynchronize(stream));
     char* hp = static_cast<char*>(w.pin);
-    Task* h_tasks = reinterpret_cast<Task*>(hp);
-    int* h_order = reinterpret_cast<int*>(hp + ((char*)d_order - mb));
+    Graph* h_graphs = reinterpret_cast<Graph*>(hp);
+    Item* h_items = reinterpret_cast<Item*>(hp + b_graphs);
     for (int i = 0; i < count; ++i) {
-        const RunItem& it = items[i];
+        const RunItem& it = items[order[i]];
         sfairsc_graph* g = it.g;
-        Task t{};
+        Graph t{};
         t.rowptr = g->rowptr;
         t.col = g->col;
         t.val32 = g->val32;
@@ -1294,6 +1629,7 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
         t.tt = base + offT[i];
         t.H = it.H ? it.H : reinterpret_cast<double*>(base + offH[i]);
         t.theta = d_theta + (size_t)i * KMAXB;
+        t.sm = reinterpret_cast<double*>(base + offS[i]);
         t.n = g->n;
         t.h = g->h;
         t.k = it.k;
@@ -1303,41 +1639,65 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
         t.rows = std::min(it.cfg.rows, max_rows(it.cfg.b, dbl));
         t.max_restarts = max_restarts;
         t.certify = certify;
+        t.item0 = item0[i];
+        t.nitems = nit[i];
         t.sigma = sigma_override > 0 ? sigma_override : g->sigma;
         t.tol = tol;
         // float products: converge the Ritz residuals to half the tolerance
         // so that the FP64 certification (which sees the float rounding of
         // the operator) meets tol
         t.tol_conv = dbl ? tol : std::max(0.5 * tol, kFloatTolFloor);
-        t.seed = seed;
-        h_tasks[i] = t;
-        h_order[i] = i;
+        t.seed = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(order[i] + 1));
+        h_graphs[i] = t;
+        for (int j = 0; j < nit[i]; ++j) {
+            Item itm{};
+            itm.g = i;
+            itm.row0 = (int64_t)j * IROWS;
+            h_items[item0[i] + j] = itm;
+        }
     }
-    std::stable_sort(h_order, h_order + count, [&](int a, int b) { return cost[a] > cost[b]; });
-    SF_HIP(hipMemcpyAsync(d_tasks, h_tasks, sizeof(Task) * count, hipMemcpyHostToDevice, stream));
-    SF_HIP(hipMemcpyAsync(d_order, h_order, sizeof(int) * count, hipMemcpyHostToDevice, stream));
-    k_set_i32<<<1, 64, 0, stream>>>(d_queue, 0);
-    const int grid = std::max(1, std::min(count, w.cus));
+    SF_HIP(hipMemcpyAsync(d_graphs, h_graphs, b_graphs + b_items, hipMemcpyHostToDevice, stream));
+    k_set_i32<<<1, 64, 0, stream>>>(d_active, count);
+    SF_HIP(hipGetLastError());
+    Launch L{};
+    L.graphs = d_graphs;
+    L.st = d_st;
+    L.items = d_items;
+    L.part = reinterpret_cast<double*>(base + offPart);
+    L.active = d_active;
+    L.alist = d_alist;
+    L.nalist = d_nalist;
+    L.t_start = d_tstart;
+    L.ng = count;
+    L.nitems = nitems;
+    L.max_steps = (max_restarts + 2) * (NCVMAX / 4) + 4;
+    void* args[] = {&L};
     SF_HIP(hipEventRecord(w.e0, stream));
     if (dbl)
-        k_batched<double><<<grid, NT, 0, stream>>>(d_tasks, d_stats, d_order, count, d_queue, seed);
+        SF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batched<double>), dim3(w.grid_d), dim3(NT),
+                                          args, 0, stream));
     else
-        k_batched<float><<<grid, NT, 0, stream>>>(d_tasks, d_stats, d_order, count, d_queue, seed);
-    SF_HIP(hipGetLastError());
+        SF_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batched<float>), dim3(w.grid_f), dim3(NT),
+                                          args, 0, stream));
     SF_HIP(hipEventRecord(w.e1, stream));
-    // results back through the pinned buffer (the task table is no longer needed)
-    TaskStat* h_stats = reinterpret_cast<TaskStat*>(hp);
-    double* h_theta = reinterpret_cast<double*>(hp + align256(sizeof(TaskStat) * count));
-    SF_HIP(hipStreamSynchronize(stream));
-    SF_HIP(hipMemcpyAsync(h_stats, d_stats, sizeof(TaskStat) * count, hipMemcpyDeviceToHost, stream));
-    SF_HIP(hipMemcpyAsync(h_theta, d_theta, sizeof(double) * KMAXB * count, hipMemcpyDeviceToHost, stream));
+    // results back through the pinned buffer
+    GState* h_st = reinterpret_cast<GState*>(hp);
+    double* h_theta = reinterpret_cast<double*>(hp + b_st);
+    uint64_t* h_t0 = reinterpret_cast<uint64_t*>(hp + b_st + b_theta);
+    SF_HIP(hipMemcpyAsync(h_st, d_st, b_st + b_theta, hipMemcpyDeviceToHost, stream));
+    SF_HIP(hipMemcpyAsync(h_t0, d_tstart, sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
     SF_HIP(hipStreamSynchronize(stream));
     float ms = 0.0f;
     SF_HIP(hipEventElapsedTime(&ms, w.e0, w.e1));
     ro->kernel_ms = ms;
     ro->tick_ms = 1.0 / (double)w.wall_khz;
-    ro->st.assign(h_stats, h_stats + count);
-    ro->theta.assign(h_theta, h_theta + (size_t)KMAXB * count);
+    ro->t_start = *h_t0;
+    ro->st.resize(count);
+    ro->theta.resize((size_t)KMAXB * count);
+    for (int i = 0; i < count; ++i) {
+        ro->st[order[i]] = h_st[i];
+        std::memcpy(ro->theta.data() + (size_t)order[i] * KMAXB, h_theta + (size_t)i * KMAXB, sizeof(double) * KMAXB);
+    }
     return SFAIRSC_OK;
 }
 
@@ -1527,16 +1887,16 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
         const int it = item_of[i];
         bool need_single = it < 0;
         if (it >= 0) {
-            const TaskStat& s = ro.st[it];
+            const GState& s = ro.st[it];
             inf.batch_status = s.status;
             inf.restarts = s.restarts;
-            inf.block_steps = s.block_steps;
-            inf.converged = s.converged;
-            inf.max_rel_residual = s.max_rel_residual;
-            inf.gap_ratio = s.gap_ratio;
+            inf.block_steps = s.steps;
+            inf.converged = s.nconv;
+            inf.max_rel_residual = s.maxres;
+            inf.gap_ratio = s.gap;
             inf.sigma = o.sigma > 0 ? o.sigma : graphs[i]->sigma;
-            inf.graph_ms = (double)(s.t_end - s.t_begin) * ro.tick_ms;
-            for (int p = 0; p < 8; ++p) inf.phase_ms[p] = (double)s.phase[p] * ro.tick_ms;
+            inf.graph_ms = s.t_done >= ro.t_start ? (double)(s.t_done - ro.t_start) * ro.tick_ms : 0.0;
+            for (int p = 0; p < 8; ++p) inf.phase_ms[p] = (double)s.ph[p] * ro.tick_ms;
             if (s.status == 0)
                 std::memcpy(eigvals[i], ro.theta.data() + (size_t)it * KMAXB, sizeof(double) * k[i]);
             else
@@ -1610,9 +1970,10 @@ extern "C" int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count, co
             double s = 0.0;
             bool ok = !trials[t].item_idx.empty();
             for (int ii : trials[t].item_idx) {
-                const TaskStat& st = ro.st[ii];
+                const GState& st = ro.st[ii];
                 if (st.status != 0) ok = false;
-                s += (double)(st.t_end - st.t_begin) * ro.tick_ms;
+                // the graph's compute-unit time over all phases
+                for (int p = 0; p < 8; ++p) s += (double)st.ph[p] * ro.tick_ms;
             }
             (*score)[t] = ok ? s : 1e300;
         }
