@@ -215,7 +215,10 @@ typedef struct sfairsc_batch_info {
     int32_t batch_status;  /* the launch's outcome: 0 converged, 1 not
                               converged, 2 rank-deficient block, 3 FP64
                               certification above tol, 4 shape not
-                              supported; -1 not attempted                   */
+                              supported, 5 handed off (one of the last
+                              three graphs of a batch of >= 32: finished by
+                              sfairsc_eigs from the launch's current Ritz
+                              vectors); -1 not attempted                    */
     int32_t block_width;   /* configuration used in the launch             */
     int32_t max_basis;
     int32_t spmm_rows;     /* CSR rows a wavefront handles together        */
@@ -267,7 +270,10 @@ typedef struct sfairsc_batch_info {
  *
  * Graphs the launch cannot take (k[i] > 48, n_i below twice the basis
  * leading dimension) and graphs whose launch result misses tol are solved by
- * sfairsc_eigs on the same stream.  The library keeps a per-device
+ * sfairsc_eigs on the same stream.  In a batch of at least 32 graphs, the
+ * launch stops once at most three graphs are still iterating (they could
+ * not fill the GPU); those are finished by sfairsc_eigs, warm-started from
+ * their current Ritz vectors.  The library keeps a per-device
  * workspace between calls: calls on one device must not overlap.
  * Synchronises `stream`.  Returns SFAIRSC_OK, SFAIRSC_E_NOT_CONVERGED (some
  * graph's status), E_ARG, E_NOMEM or E_HIP.

@@ -61,7 +61,13 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int NT = 1024;                        // threads of a workgroup
+#ifndef SF_BATCH_THREADS
+#define SF_BATCH_THREADS 1024
+#endif
+#ifndef SF_ITEM_FN
+#define SF_ITEM_FN __noinline__
+#endif
+constexpr int NT = SF_BATCH_THREADS;            // threads of a workgroup
 constexpr int NW = NT / 64;                     // wavefronts
 constexpr int BMAX = 16;                        // widest block
 constexpr int NCVMAX = 80;                      // basis columns before a restart
@@ -115,10 +121,12 @@ struct Graph {
 
 struct GState {
     int32_t active;  // block steps continue
-    int32_t status;  // 0 converged, 1 not converged, 2 breakdown, 3 certification failed, 4 bad shape
+    int32_t status;  // 0 converged, 1 not converged, 2 breakdown, 3 certification failed, 4 bad shape,
+                     // 5 handed off with its current Ritz vectors in V[:, 0:k]
     int32_t out;     // the output phases apply (Ritz vectors of the last Rayleigh-Ritz step)
     int32_t m, restarts, steps, nconv;
     int32_t rot_m, rot_p, rot_nb;  // pending rotation (rot_p > 0)
+
     double est, gap, maxres;
     uint64_t t_done;
     uint64_t ph[8];  // compute-unit clock ticks spent on the graph, by phase
@@ -138,7 +146,9 @@ struct Launch {
     int* alist;    // items of the selected graphs (see build_list)
     int* nalist;   // their number
     uint64_t* t_start;
+    uint64_t* steplog;  // optional: per block step, wall clock and active graphs / items
     int ng, nitems, max_steps;
+    int handoff;  // leave the block steps once at most this many graphs remain
 };
 
 struct Shared {
@@ -154,8 +164,8 @@ struct Shared {
     double R1[256], Ri[256], R2[256];
     double theta[NCVMAX], res[NCVMAX];
     double wsum[NW * 2];
-    double jc[NCVMAX / 2], js[NCVMAX / 2];
-    int jp[NCVMAX / 2], jq[NCVMAX / 2];
+    double2 jcs[NCVMAX / 2];  // Jacobi rotations of a round: (cos, sin)
+    int2 jpq[NCVMAX / 2];     // and their index pairs
     int perm[NCVMAX];
     int iscan[NT];
     int iflag[4];
@@ -298,7 +308,7 @@ __device__ void wg_sum2(double& a, double& b, double* red) {
 // out[s * 16 + j] = sum over rows r in [r0, r1) of group s of c_r X[r][j],
 // j < bw (bw in {4, 8, 16}), s < h.
 template <class XT>
-__device__ __noinline__ void w_gsum(const XT* X, int64_t ldx, int64_t r0, int64_t r1, int bw, int h,
+__device__ SF_ITEM_FN void w_gsum(const XT* X, int64_t ldx, int64_t r0, int64_t r1, int bw, int h,
                                     const int32_t* __restrict__ grp, const double* __restrict__ cs,
                                     double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
@@ -340,7 +350,7 @@ __device__ __noinline__ void w_gsum(const XT* X, int64_t ldx, int64_t r0, int64_
 
 // out_r = X_r - c_r R_{g_r} for rows [r0, r1), columns j < bw.
 template <class OT>
-__device__ __noinline__ void w_proj(const double* X, int64_t ldx, int64_t r0, int64_t r1, int bw,
+__device__ SF_ITEM_FN void w_proj(const double* X, int64_t ldx, int64_t r0, int64_t r1, int bw,
                                     const int32_t* __restrict__ grp, const double* __restrict__ cs,
                                     const double* __restrict__ R, OT* out, int64_t ldo) {
     const int lane = threadIdx.x & 63;
@@ -358,7 +368,7 @@ __device__ __noinline__ void w_proj(const double* X, int64_t ldx, int64_t r0, in
 // n x b).  `rows` rows share the wavefront, 64 / rows lanes each; within a
 // row, lanes split into nonzero slots of b / VEC lanes.
 template <class VT>
-__device__ __noinline__ void w_spmm(const Graph& t, const VT* __restrict__ X, VT* __restrict__ T, int64_t r0,
+__device__ SF_ITEM_FN void w_spmm(const Graph& t, const VT* __restrict__ X, VT* __restrict__ T, int64_t r0,
                                     int64_t r1, int b, int rows) {
     using V = Vec16<VT>;
     constexpr int VEC = V::N;
@@ -421,7 +431,7 @@ __device__ __noinline__ void w_spmm(const Graph& t, const VT* __restrict__ X, VT
 // V[:, cv : cv + b]; V[:, 0:cv]^T Y0 summed over the workgroup into out
 // (cv x b, row-major; every wavefront of the workgroup calls it).
 template <class SpT>
-__device__ __noinline__ void w_pass_a(const Graph& t, double* V, int ld, int cv, int b, const SpT* __restrict__ T,
+__device__ SF_ITEM_FN void w_pass_a(const Graph& t, double* V, int ld, int cv, int b, const SpT* __restrict__ T,
                                       const double* __restrict__ R2, int64_t tile0, int64_t tile1, double* wred,
                                       double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
@@ -461,7 +471,7 @@ __device__ __noinline__ void w_pass_a(const Graph& t, double* V, int ld, int cv,
 // (cv x b); SYRK: Ynew^T Ynew (b x b) after it; both row-major, summed over
 // the workgroup into out (every wavefront of the workgroup calls it).
 template <bool GRAM, bool SYRK>
-__device__ __noinline__ void w_upd(int64_t n, double* V, int ld, int coff, int kin, int yoff, int b, int cv,
+__device__ SF_ITEM_FN void w_upd(int64_t n, double* V, int ld, int coff, int kin, int yoff, int b, int cv,
                                    const double* __restrict__ M, int64_t tile0, int64_t tile1, double* wred,
                                    double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
@@ -527,7 +537,7 @@ __device__ __noinline__ void w_upd(int64_t n, double* V, int ld, int coff, int k
 // V[:, 0:p] = V[:, 0:m] Z (Z: m x p, row stride zs) and, if nb > 0,
 // V[:, p : p + nb] = V[:, m : m + nb], over tiles [tile0, tile1), in place
 // (every input of a tile is in registers before its first store).
-__device__ __noinline__ void w_rotate(int64_t n, double* V, int ld, int m, const double* __restrict__ Z, int zs,
+__device__ SF_ITEM_FN void w_rotate(int64_t n, double* V, int ld, int m, const double* __restrict__ Z, int zs,
                                       int p, int nb, int64_t tile0, int64_t tile1) {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
@@ -582,7 +592,7 @@ __device__ __noinline__ void w_rotate(int64_t n, double* V, int ld, int m, const
 
 // Residual partials of the certification, 16 columns:
 // out[j] = sum over rows of (T_r[j] - c_r R2[g_r][j] - theta_j X[r][j])^2.
-__device__ __noinline__ void w_resid(const Graph& t, const double* X, int ld, const double* __restrict__ T,
+__device__ SF_ITEM_FN void w_resid(const Graph& t, const double* X, int ld, const double* __restrict__ T,
                                      const double* __restrict__ R2, const double* __restrict__ th, int kc,
                                      int64_t r0, int64_t r1, double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
@@ -602,7 +612,7 @@ __device__ __noinline__ void w_resid(const Graph& t, const double* X, int ld, co
 
 // Sign partials, 16 columns: the largest |c_r X[r][j]| over the rows (lowest
 // row on ties): out[j] = magnitude, out[16 + j] = row, out[32 + j] = value.
-__device__ __noinline__ void w_signs(const Graph& t, const double* X, int ld, int64_t r0, int64_t r1,
+__device__ SF_ITEM_FN void w_signs(const Graph& t, const double* X, int ld, int64_t r0, int64_t r1,
                                      double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int col = lane & 15, rl = lane >> 4;
@@ -738,32 +748,35 @@ __device__ __noinline__ bool g_chol(const double* G, int b, double thresh, doubl
 }
 
 // Eigen-decomposition of the symmetric m x m matrix A (LDS, stride LDT) by
-// cyclic Jacobi, round-robin ordering.  A round's m/2 rotations are disjoint
-// and applied at once: thread blocks of 2 x 2 entries (pair a's rows, pair
-// b's columns) take A <- J^T A J from the old values, so a round needs one
-// barrier after the rotation angles and one after the update.  On return
-// diag(A) holds the eigenvalues and Z (stride LDT) the eigenvectors as
-// columns.
+// cyclic Jacobi, round-robin ordering, rotations accumulated into Z (LDS,
+// stride LDT, the identity on entry).  A round's m/2 rotations are disjoint
+// and applied at once: a thread takes the 2 x 2 block of entries (rows of
+// pair a, columns of pair c), a <= c, and writes J_a^T A_ac J_c and its
+// mirror from the old values, so a round needs one barrier after the
+// rotation angles and one after the update.  Rotations whose off-diagonal
+// entry is at most 1e-16 ||A||_F (the rounding level of the rotations
+// themselves) are skipped and blocks of two skipped pairs are not touched;
+// the sweeps stop after one without rotations (at most 40).  On return
+// diag(A) holds the eigenvalues and Z the eigenvectors as columns.
 __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
     const int t = threadIdx.x;
-    for (int idx = t; idx < m * m; idx += NT) {
-        const int i = idx / m, j = idx - i * m;
-        Z[i * LDT + j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
+    constexpr int GR = NT / 32;
+    const int tr = t >> 5, tc = t & 31;  // GR x 32 thread grid
     const int mm = m + (m & 1), np = mm / 2, rr = mm - 1;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        double off = 0.0, dg = 0.0;
-        for (int idx = t; idx < m * m; idx += NT) {
-            const int i = idx / m, j = idx - i * m;
+    double off = 0.0, dg = 0.0;
+    for (int i = tr; i < m; i += GR)
+        for (int j = tc; j < m; j += 32) {
             const double v = A[i * LDT + j];
             if (i != j)
                 off += v * v;
             else
                 dg += v * v;
         }
-        wg_sum2(off, dg, S.wsum);
-        if (!(off > 1e-30 * dg)) break;
+    wg_sum2(off, dg, S.wsum);
+    const double tiny = 1e-16 * sqrt(dg + off);
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (t == 0) S.iflag[2] = 0;
+        __syncthreads();
         for (int r = 0; r < rr; ++r) {
             if (t < np) {
                 int p, q;
@@ -771,66 +784,83 @@ __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
                     p = r;
                     q = rr;
                 } else {
-                    p = (r + t) % rr;
-                    q = (r - t + rr) % rr;
+                    p = r + t;
+                    if (p >= rr) p -= rr;
+                    q = r - t;
+                    if (q < 0) q += rr;
                 }
                 if (p > q) {
                     const int x = p;
                     p = q;
                     q = x;
                 }
-                double c = 1.0, s = 0.0;
+                double c = 1.0, sn = 0.0;
                 if (q < m) {
                     const double apq = A[p * LDT + q];
-                    if (apq != 0.0) {
+                    if (fabs(apq) > tiny) {
                         const double th = (A[q * LDT + q] - A[p * LDT + p]) / (2.0 * apq);
                         const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
                         c = 1.0 / sqrt(1.0 + tt * tt);
-                        s = tt * c;
+                        sn = tt * c;
+                        S.iflag[2] = 1;
                     }
                 }
-                S.jp[t] = p;
-                S.jq[t] = q;
-                S.jc[t] = c;
-                S.js[t] = s;
+                S.jcs[t] = make_double2(c, sn);
+                S.jpq[t] = make_int2(p, q);
             }
             __syncthreads();
-            // A <- J^T A J on 2 x 2 blocks; entries with an index >= m (the
-            // padding index of odd m) are neither read nor written
-            for (int idx = t; idx < np * np; idx += NT) {
-                const int a = idx / np, bq = idx - a * np;
-                const double s1 = S.js[a], s2 = S.js[bq];
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const int p1 = S.jp[a], q1 = S.jq[a], p2 = S.jp[bq], q2 = S.jq[bq];
-                const double c1 = S.jc[a], c2 = S.jc[bq];
-                const bool vq1 = q1 < m, vq2 = q2 < m;
-                const double x00 = A[p1 * LDT + p2];
-                const double x01 = vq2 ? A[p1 * LDT + q2] : 0.0;
-                const double x10 = vq1 ? A[q1 * LDT + p2] : 0.0;
-                const double x11 = (vq1 && vq2) ? A[q1 * LDT + q2] : 0.0;
-                // columns: Y = X J2
-                const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
-                const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
-                // rows: J1^T Y
-                A[p1 * LDT + p2] = c1 * y00 - s1 * y10;
-                if (vq2) A[p1 * LDT + q2] = c1 * y01 - s1 * y11;
-                if (vq1) A[q1 * LDT + p2] = s1 * y00 + c1 * y10;
-                if (vq1 && vq2) A[q1 * LDT + q2] = s1 * y01 + c1 * y11;
+            // A <- J^T A J on 2 x 2 blocks (a <= c, mirrored); entries with an
+            // index >= m (the padding index of odd m) are neither read nor written
+            for (int a = tr; a < np; a += GR) {
+                const double2 cs1 = S.jcs[a];
+                const int2 pq1 = S.jpq[a];
+                const int p1 = pq1.x, q1 = pq1.y;
+                const bool vq1 = q1 < m;
+                for (int cq = a + tc; cq < np; cq += 32) {
+                    const double2 cs2 = S.jcs[cq];
+                    if (cs1.y == 0.0 && cs2.y == 0.0) continue;
+                    const int2 pq2 = S.jpq[cq];
+                    const int p2 = pq2.x, q2 = pq2.y;
+                    const bool vq2 = q2 < m;
+                    const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
+                    const double x00 = A[p1 * LDT + p2];
+                    const double x01 = vq2 ? A[p1 * LDT + q2] : 0.0;
+                    const double x10 = vq1 ? A[q1 * LDT + p2] : 0.0;
+                    const double x11 = (vq1 && vq2) ? A[q1 * LDT + q2] : 0.0;
+                    // columns: Y = X J2
+                    const double y00 = c2 * x00 - s2 * x01, y01 = s2 * x00 + c2 * x01;
+                    const double y10 = c2 * x10 - s2 * x11, y11 = s2 * x10 + c2 * x11;
+                    // rows: J1^T Y
+                    const double z00 = c1 * y00 - s1 * y10, z01 = c1 * y01 - s1 * y11;
+                    const double z10 = s1 * y00 + c1 * y10, z11 = s1 * y01 + c1 * y11;
+                    A[p1 * LDT + p2] = z00;
+                    if (vq2) A[p1 * LDT + q2] = z01;
+                    if (vq1) A[q1 * LDT + p2] = z10;
+                    if (vq1 && vq2) A[q1 * LDT + q2] = z11;
+                    if (cq != a) {
+                        A[p2 * LDT + p1] = z00;
+                        if (vq2) A[q2 * LDT + p1] = z01;
+                        if (vq1) A[p2 * LDT + q1] = z10;
+                        if (vq1 && vq2) A[q2 * LDT + q1] = z11;
+                    }
+                }
             }
             // Z <- Z J
-            for (int idx = t; idx < m * np; idx += NT) {
-                const int i = idx / np, pr = idx - i * np;
-                const double s = S.js[pr];
-                if (s == 0.0) continue;
-                const int p = S.jp[pr], q = S.jq[pr];
-                const double c = S.jc[pr];
-                double* z = Z + i * LDT;
-                const double zp = z[p], zq = z[q];
-                z[p] = c * zp - s * zq;
-                z[q] = s * zp + c * zq;
+            for (int pr = tc; pr < np; pr += 32) {
+                const double2 cs = S.jcs[pr];
+                if (cs.y == 0.0) continue;
+                const int2 pq = S.jpq[pr];
+                for (int i = tr; i < m; i += GR) {
+                    double* z = Z + i * LDT;
+                    const double zp = z[pq.x], zq = z[pq.y];
+                    z[pq.x] = cs.x * zp - cs.y * zq;
+                    z[pq.y] = cs.y * zp + cs.x * zq;
+                }
             }
             __syncthreads();
         }
+        if (S.iflag[2] == 0) break;
+        __syncthreads();
     }
 }
 
@@ -845,6 +875,107 @@ __device__ __forceinline__ void stop(GState& s, int status, int* active) {
 // The launch.
 
 enum Ph { PH_OP = 0, PH_A, PH_B, PH_C, PH_D, PH_RR, PH_ROT, PH_IO };
+
+// The Rayleigh-Ritz step of a graph whose basis is full (m columns), by its
+// owner workgroup: T_m diagonalized by Jacobi in LDS, the Ritz pairs in
+// ascending order, the residual estimates ||Rc z_last||, the convergence
+// test and the restart (or final) rotation, applied by the next row phase.
+__device__ __noinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int* active, Shared& S) {
+    const int tid = threadIdx.x;
+    const uint64_t t0 = wall_clock64();
+    const int b = g.b, k = g.k;
+    const int restarts = s.restarts;
+    double* Ag = g.sm + OFF_T;
+    double* Zg = g.sm + OFF_Z;
+    for (int e = tid; e < m * m; e += NT) {
+        const int i = e / m, j = e - i * m;
+        S.u.j.A[i * LDT + j] = Ag[i * NCVMAX + j];
+        S.u.j.Z[i * LDT + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    g_jacobi(S.u.j.A, m, S.u.j.Z, S);
+    {
+        for (int e = tid; e < 256; e += NT) S.R2[e] = g.sm[OFF_R + 256 + e];  // coupling Rc
+        if (tid < m) {
+            const double w = S.u.j.A[tid * LDT + tid];
+            int rank = 0;
+            for (int j = 0; j < m; ++j) {
+                const double o = S.u.j.A[j * LDT + j];
+                rank += (o < w || (o == w && j < tid)) ? 1 : 0;
+            }
+            S.perm[rank] = tid;
+            S.theta[rank] = w;
+        }
+        __syncthreads();
+        // residual estimates ||Rc z_last|| of the Ritz pairs
+        if (tid < m) {
+            const int c = S.perm[tid];
+            double s2 = 0.0;
+            for (int i = 0; i < b; ++i) {
+                double v = 0.0;
+                for (int j = i; j < b; ++j) v += S.R2[i * 16 + j] * S.u.j.Z[(m - b + j) * LDT + c];
+                s2 += v * v;
+            }
+            S.res[tid] = sqrt(s2);
+        }
+        if (tid == 0) {
+            bool finite = true;
+            for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
+            S.iflag[1] = finite ? 1 : 0;
+        }
+        __syncthreads();
+        const bool finite = S.iflag[1] != 0;
+        int nconv = 0;
+        double est = 0.0;
+        const double tolabs = g.tol_conv * g.sigma;
+        for (int r = 0; r < k; ++r) {
+            nconv += S.res[r] <= tolabs ? 1 : 0;
+            est = fmax(est, S.res[r]);
+        }
+        const bool fin = nconv == k || restarts >= g.max_restarts;
+        // rotation: the k Ritz vectors when finished, else the p kept ones
+        // (k < p <= m - b, p a multiple of b)
+        const int ptarget = max(k + 1, (m + k) / 2);
+        const int nd = max(1, (m - ptarget) / b);
+        const int p = fin ? k : m - nd * b;
+        for (int e = tid; e < m * p; e += NT) {
+            const int q = e / p, r = e - q * p;
+            Zg[q * NCVMAX + r] = S.u.j.Z[q * LDT + S.perm[r]];
+        }
+        for (int r = tid; r < m; r += NT) g.sm[OFF_AUX + r] = S.theta[r];
+        if (!fin) {
+            for (int e = tid; e < p * p; e += NT) {
+                const int i = e / p, j = e - i * p;
+                Ag[i * NCVMAX + j] = (i == j) ? S.theta[i] : 0.0;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            s.nconv = nconv;
+            s.est = est / g.sigma;
+            s.gap = m > k ? (S.theta[k] - S.theta[k - 1]) / g.sigma : 0.0;
+            if (!finite) {
+                stop(s, 2, active);
+            } else {
+                s.rot_m = m;
+                s.rot_p = p;
+                s.rot_nb = fin ? 0 : b;
+                if (fin) {
+                    s.out = 1;
+                    stop(s, nconv == k ? 0 : 1, active);
+                } else {
+                    s.m = p;
+                    s.restarts = restarts + 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0)
+        __hip_atomic_fetch_add(&s.ph[PH_RR], (uint64_t)(wall_clock64() - t0), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
 
 // The items of the graphs still in their block steps (out: of the graphs
 // with output), in graph order, into alist / nalist.  Workgroup 0 only.
@@ -1019,15 +1150,23 @@ __global__ __launch_bounds__(NT) void k_batched(Launch L) {
     grid.sync();
 
     // ---- block steps: basis V[:, 0:m], current block V[:, m : m + b] ----------
-    int listed = -1;  // active count when the item list was built
+    int listed = -1;       // active count when the item list was built
+    int listed_items = 0;  // items in that list
     for (int step = 0; step < L.max_steps; ++step) {
         const int act = __hip_atomic_load(L.active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (act <= 0) break;
+        if (act <= L.handoff) break;
         if (act != listed) {
             if (blockIdx.x == 0) build_list(L, false, S);
             grid.sync();
             listed = act;
+            listed_items = *L.nalist;
         }
+#ifdef SF_BATCH_STEPLOG
+        if (blockIdx.x == 0 && tid == 0 && L.steplog) {
+            L.steplog[2 * step] = wall_clock64();
+            L.steplog[2 * step + 1] = (uint64_t)act | ((uint64_t)listed_items << 32);
+        }
+#endif
         // restart rotation (if pending), then X' = P X (the tables of X are current)
         SF_ITEMS(PH_OP, s.active, {
             if (s.rot_p > 0) {
@@ -1162,115 +1301,30 @@ __global__ __launch_bounds__(NT) void k_batched(Launch L) {
         grid.sync();
         // tables of the next block; Rayleigh-Ritz and the restart when the basis is full
         SF_GRAPHS(PH_D, s.active, {
-            const int b = g.b, k = g.k;
+            const int b = g.b;
             const int m = s.m + b;
-            const int restarts = s.restarts, steps = s.steps + 1;
+            const int steps = s.steps + 1;
             g_reduce(L.part, g.item0, g.nitems, g.h * b, S.red);
             g_finalize(S.red, g.h, b, g.gpar, g.sm + OFF_TAB + HMAX * 16, nullptr, 0.0, S.gZ, g.sm + OFF_TAB);
+            if (tid == 0) s.steps = steps;
             if (m + b <= g.ncv) {
-                if (tid == 0) {
-                    s.m = m;
-                    s.steps = steps;
-                }
+                if (tid == 0) s.m = m;
             } else {
-                const uint64_t trr = wall_clock64();
-                const double* T = g.sm + OFF_T;
-                for (int e = tid; e < m * m; e += NT) {
-                    const int i = e / m, j = e - i * m;
-                    S.u.j.A[i * LDT + j] = T[i * NCVMAX + j];
-                }
-                for (int e = tid; e < 256; e += NT) S.R2[e] = g.sm[OFF_R + 256 + e];  // coupling Rc
-                __syncthreads();
-                g_jacobi(S.u.j.A, m, S.u.j.Z, S);
-                if (tid < m) {
-                    const double w = S.u.j.A[tid * LDT + tid];
-                    int rank = 0;
-                    for (int j = 0; j < m; ++j) {
-                        const double o = S.u.j.A[j * LDT + j];
-                        rank += (o < w || (o == w && j < tid)) ? 1 : 0;
-                    }
-                    S.perm[rank] = tid;
-                    S.theta[rank] = w;
-                }
-                __syncthreads();
-                // residual estimates ||Rc z_last|| of the Ritz pairs
-                if (tid < m) {
-                    const int c = S.perm[tid];
-                    double s2 = 0.0;
-                    for (int i = 0; i < b; ++i) {
-                        double v = 0.0;
-                        for (int j = i; j < b; ++j) v += S.R2[i * 16 + j] * S.u.j.Z[(m - b + j) * LDT + c];
-                        s2 += v * v;
-                    }
-                    S.res[tid] = sqrt(s2);
-                }
-                if (tid == 0) {
-                    bool finite = true;
-                    for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
-                    S.iflag[1] = finite ? 1 : 0;
-                }
-                __syncthreads();
-                const bool finite = S.iflag[1] != 0;
-                int nconv = 0;
-                double est = 0.0;
-                const double tolabs = g.tol_conv * g.sigma;
-                for (int r = 0; r < k; ++r) {
-                    nconv += S.res[r] <= tolabs ? 1 : 0;
-                    est = fmax(est, S.res[r]);
-                }
-                const bool done = nconv == k || restarts >= g.max_restarts;
-                // rotation: the k Ritz vectors when done, else the p kept ones
-                // (k < p <= m - b, p a multiple of b)
-                const int ptarget = max(k + 1, (m + k) / 2);
-                const int nd = max(1, (m - ptarget) / b);
-                const int p = done ? k : m - nd * b;
-                double* Zg = g.sm + OFF_Z;
-                for (int e = tid; e < m * p; e += NT) {
-                    const int q = e / p, r = e - q * p;
-                    Zg[q * NCVMAX + r] = S.u.j.Z[q * LDT + S.perm[r]];
-                }
-                for (int r = tid; r < m; r += NT) g.sm[OFF_AUX + r] = S.theta[r];
-                if (!done) {
-                    double* Tw = g.sm + OFF_T;
-                    for (int e = tid; e < p * p; e += NT) {
-                        const int i = e / p, j = e - i * p;
-                        Tw[i * NCVMAX + j] = (i == j) ? S.theta[i] : 0.0;
-                    }
-                }
-                if (tid == 0) {
-                    s.steps = steps;
-                    s.nconv = nconv;
-                    s.est = est / g.sigma;
-                    s.gap = m > k ? (S.theta[k] - S.theta[k - 1]) / g.sigma : 0.0;
-                    if (!finite) {
-                        stop(s, 2, L.active);
-                    } else {
-                        s.rot_m = m;
-                        s.rot_p = p;
-                        s.rot_nb = done ? 0 : b;
-                        if (done) {
-                            s.out = 1;
-                            stop(s, nconv == k ? 0 : 1, L.active);
-                        } else {
-                            s.m = p;
-                            s.restarts = restarts + 1;
-                        }
-                    }
-                }
-                // this part of the phase counts as Rayleigh-Ritz time
-                __syncthreads();
-                if (tid == 0) {
-                    const uint64_t d = wall_clock64() - trr;
-                    __hip_atomic_fetch_add(&s.ph[PH_RR], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(&s.ph[PH_D], (uint64_t)0 - d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                const uint64_t t1 = wall_clock64();
+                rayleigh_ritz(g, s, m, L.active, S);
+                // counted as Rayleigh-Ritz time by rayleigh_ritz
+                if (tid == 0)
+                    __hip_atomic_fetch_add(&s.ph[PH_D], (uint64_t)0 - (wall_clock64() - t1), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             }
         });
         grid.sync();
     }
-    // graphs still iterating at the step limit: not converged, no output
+    // graphs still iterating (step limit or hand-off): no output here; after a
+    // restart, V[:, 0:k] holds the current Ritz vectors (the expansions since
+    // only append columns)
     SF_GRAPHS(PH_IO, s.active, {
-        if (tid == 0) stop(s, 1, L.active);
+        if (tid == 0) stop(s, s.restarts > 0 ? 5 : 1, L.active);
     });
     grid.sync();
 
@@ -1398,6 +1452,11 @@ __global__ void k_set_i32(int* p, int v) {
 // host side
 
 constexpr double kFloatTolFloor = 5e-7;  // tolerances below: double products
+// Once at most kHandoffGraphs graphs of a batch of at least kHandoffMinBatch
+// remain, they leave the launch (a few graphs cannot fill the grid) and are
+// finished by sfairsc_eigs from their current Ritz vectors.
+constexpr int kHandoffGraphs = 3;
+constexpr int kHandoffMinBatch = 32;
 
 struct Cfg {
     int b = 8, ncv = 48, rows = 1;
@@ -1488,6 +1547,7 @@ void maybe_load_env() {
 // Per-device workspace of batched launches (grow-only).
 struct BatchWork {
     DevBuf big, meta;
+    DevBuf x0;  // warm start of a handed-off graph
     void* pin = nullptr;
     size_t pin_bytes = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1508,6 +1568,8 @@ struct RunItem {
 struct RunOut {
     std::vector<GState> st;
     std::vector<double> theta;  // [count][KMAXB]
+    std::vector<const double*> V;  // each graph's basis (valid until the next launch)
+    std::vector<int> ld;
     uint64_t t_start = 0;
     double kernel_ms = 0.0;
     double tick_ms = 0.0;  // ms per wall-clock tick
@@ -1518,7 +1580,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // One cooperative launch over the items (every workgroup resident at once).
 // Synchronises `stream`.
 int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double sigma_override, int max_restarts,
-              int certify, uint64_t seed, hipStream_t stream, RunOut* ro) {
+              int certify, uint64_t seed, int handoff, hipStream_t stream, RunOut* ro) {
     int dev = 0;
     SF_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return set_error(SFAIRSC_E_ARG, "device index %d out of range", dev);
@@ -1611,6 +1673,8 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
     char* hp = static_cast<char*>(w.pin);
     Graph* h_graphs = reinterpret_cast<Graph*>(hp);
     Item* h_items = reinterpret_cast<Item*>(hp + b_graphs);
+    std::vector<const double*> h_graphs_v(count);
+    std::vector<int> h_graphs_ld(count);
     for (int i = 0; i < count; ++i) {
         const RunItem& it = items[order[i]];
         sfairsc_graph* g = it.g;
@@ -1649,6 +1713,8 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
         t.tol_conv = dbl ? tol : std::max(0.5 * tol, kFloatTolFloor);
         t.seed = seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(order[i] + 1));
         h_graphs[i] = t;
+        h_graphs_v[i] = t.V;
+        h_graphs_ld[i] = t.ld;
         for (int j = 0; j < nit[i]; ++j) {
             Item itm{};
             itm.g = i;
@@ -1668,9 +1734,19 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
     L.alist = d_alist;
     L.nalist = d_nalist;
     L.t_start = d_tstart;
+#ifdef SF_BATCH_STEPLOG
+    DevBuf slog;
+    const char* slog_path = std::getenv("SFAIRSC_BATCH_STEPLOG");
+    if (slog_path) {
+        SF_TRY(slog.ensure(sizeof(uint64_t) * 2 * (size_t)((max_restarts + 2) * (NCVMAX / 4) + 4)));
+        SF_HIP(hipMemsetAsync(slog.p, 0, slog.bytes, stream));
+        L.steplog = slog.as<uint64_t>();
+    }
+#endif
     L.ng = count;
     L.nitems = nitems;
     L.max_steps = (max_restarts + 2) * (NCVMAX / 4) + 4;
+    L.handoff = handoff;
     void* args[] = {&L};
     SF_HIP(hipEventRecord(w.e0, stream));
     if (dbl)
@@ -1692,10 +1768,28 @@ int run_items(const std::vector<RunItem>& items, double tol, bool dbl, double si
     ro->kernel_ms = ms;
     ro->tick_ms = 1.0 / (double)w.wall_khz;
     ro->t_start = *h_t0;
+#ifdef SF_BATCH_STEPLOG
+    if (L.steplog) {
+        std::vector<uint64_t> h(slog.bytes / 8);
+        SF_HIP(hipMemcpy(h.data(), slog.p, slog.bytes, hipMemcpyDeviceToHost));
+        FILE* f = std::fopen(slog_path, "w");
+        if (f) {
+            for (size_t i = 0; i + 1 < h.size() && h[i]; i += 2)
+                std::fprintf(f, "%llu %llu %llu\n", (unsigned long long)(h[i] - *h_t0),
+                             (unsigned long long)(h[i + 1] & 0xffffffffull), (unsigned long long)(h[i + 1] >> 32));
+            std::fclose(f);
+        }
+        slog.release();
+    }
+#endif
     ro->st.resize(count);
     ro->theta.resize((size_t)KMAXB * count);
+    ro->V.resize(count);
+    ro->ld.resize(count);
     for (int i = 0; i < count; ++i) {
         ro->st[order[i]] = h_st[i];
+        ro->V[order[i]] = h_graphs_v[i];
+        ro->ld[order[i]] = h_graphs_ld[i];
         std::memcpy(ro->theta.data() + (size_t)order[i] * KMAXB, h_theta + (size_t)i * KMAXB, sizeof(double) * KMAXB);
     }
     return SFAIRSC_OK;
@@ -1873,7 +1967,8 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
     }
     RunOut ro;
     if (!items.empty())
-        SF_TRY(run_items(items, tol, dbl, o.sigma, max_restarts, o.certify ? 1 : 0, o.seed, stream, &ro));
+        SF_TRY(run_items(items, tol, dbl, o.sigma, max_restarts, o.certify ? 1 : 0, o.seed,
+                         (int)items.size() >= kHandoffMinBatch ? kHandoffGraphs : 0, stream, &ro));
 
     int ret = SFAIRSC_OK;
     for (int i = 0; i < count; ++i) {
@@ -1886,6 +1981,8 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
         inf.batch_ms = ro.kernel_ms;
         const int it = item_of[i];
         bool need_single = it < 0;
+        const double* warm = nullptr;  // hand-off: the launch's current Ritz vectors
+        int warm_ld = 0;
         if (it >= 0) {
             const GState& s = ro.st[it];
             inf.batch_status = s.status;
@@ -1897,10 +1994,15 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
             inf.sigma = o.sigma > 0 ? o.sigma : graphs[i]->sigma;
             inf.graph_ms = s.t_done >= ro.t_start ? (double)(s.t_done - ro.t_start) * ro.tick_ms : 0.0;
             for (int p = 0; p < 8; ++p) inf.phase_ms[p] = (double)s.ph[p] * ro.tick_ms;
-            if (s.status == 0)
+            if (s.status == 0) {
                 std::memcpy(eigvals[i], ro.theta.data() + (size_t)it * KMAXB, sizeof(double) * k[i]);
-            else
+            } else {
                 need_single = true;
+                if (s.status == 5) {
+                    warm = ro.V[it];
+                    warm_ld = ro.ld[it];
+                }
+            }
         } else {
             inf.batch_status = -1;
         }
@@ -1912,6 +2014,19 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
             so.sigma = o.sigma;
             so.certify = o.certify;
             so.max_restarts = o.max_restarts;
+            if (warm) {
+                // the first min(k, 16) Ritz vectors, compacted to n x b0 row-major
+                const int b0 = std::min(k[i], 16);
+                const int64_t n = graphs[i]->n;
+                int dev = 0;
+                SF_HIP(hipGetDevice(&dev));
+                DevBuf& xb = g_bw[dev].x0;
+                SF_TRY(xb.ensure(sizeof(double) * (size_t)n * b0));
+                SF_HIP(hipMemcpy2DAsync(xb.p, sizeof(double) * b0, warm, sizeof(double) * warm_ld, sizeof(double) * b0,
+                                        n, hipMemcpyDeviceToDevice, stream));
+                so.x0 = xb.as<double>();
+                so.b0 = b0;
+            }
             sfairsc_eigs_info si{};
             const int r = sfairsc_eigs(graphs[i], k[i], tol, precision, &so, eigvals[i], H[i], &si, stream);
             inf.path = 1;
@@ -1965,7 +2080,7 @@ extern "C" int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count, co
         score->assign(trials.size(), 1e300);
         if (items.empty()) return SFAIRSC_OK;
         RunOut ro;
-        SF_TRY(run_items(items, tol, dbl, 0.0, 500, 1, 0, stream, &ro));
+        SF_TRY(run_items(items, tol, dbl, 0.0, 500, 1, 0, 0, stream, &ro));
         for (size_t t = 0; t < trials.size(); ++t) {
             double s = 0.0;
             bool ok = !trials[t].item_idx.empty();
