@@ -27,9 +27,11 @@
 // Every reduction has a fixed order: results are bitwise reproducible for a
 // given device.  A graph leaves the block steps once converged (or out of
 // restarts); the output phases (projection onto null(C^T), FP64
-// certification, signs, H) run once for all graphs at the end.  The launch
-// requires all workgroups to be resident at once (a cooperative launch,
-// which fails cleanly otherwise).
+// certification, signs, H) run once for all graphs at the end.  The last few
+// graphs of a large batch cannot fill the GPU: the launch can stop early and
+// leave them, with their current Ritz vectors, to the single-graph solver.
+// The launch requires all workgroups to be resident at once (a cooperative
+// launch, which fails cleanly otherwise).
 //
 // The block width b, the basis size and the CSR rows handled together by a
 // wavefront are chosen per graph, by default from a tuning table filled by
@@ -894,79 +896,77 @@ __device__ __noinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int
     }
     __syncthreads();
     g_jacobi(S.u.j.A, m, S.u.j.Z, S);
-    {
-        for (int e = tid; e < 256; e += NT) S.R2[e] = g.sm[OFF_R + 256 + e];  // coupling Rc
-        if (tid < m) {
-            const double w = S.u.j.A[tid * LDT + tid];
-            int rank = 0;
-            for (int j = 0; j < m; ++j) {
-                const double o = S.u.j.A[j * LDT + j];
-                rank += (o < w || (o == w && j < tid)) ? 1 : 0;
-            }
-            S.perm[rank] = tid;
-            S.theta[rank] = w;
+    for (int e = tid; e < 256; e += NT) S.R2[e] = g.sm[OFF_R + 256 + e];  // coupling Rc
+    if (tid < m) {
+        const double w = S.u.j.A[tid * LDT + tid];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double o = S.u.j.A[j * LDT + j];
+            rank += (o < w || (o == w && j < tid)) ? 1 : 0;
         }
-        __syncthreads();
-        // residual estimates ||Rc z_last|| of the Ritz pairs
-        if (tid < m) {
-            const int c = S.perm[tid];
-            double s2 = 0.0;
-            for (int i = 0; i < b; ++i) {
-                double v = 0.0;
-                for (int j = i; j < b; ++j) v += S.R2[i * 16 + j] * S.u.j.Z[(m - b + j) * LDT + c];
-                s2 += v * v;
-            }
-            S.res[tid] = sqrt(s2);
+        S.perm[rank] = tid;
+        S.theta[rank] = w;
+    }
+    __syncthreads();
+    // residual estimates ||Rc z_last|| of the Ritz pairs
+    if (tid < m) {
+        const int c = S.perm[tid];
+        double s2 = 0.0;
+        for (int i = 0; i < b; ++i) {
+            double v = 0.0;
+            for (int j = i; j < b; ++j) v += S.R2[i * 16 + j] * S.u.j.Z[(m - b + j) * LDT + c];
+            s2 += v * v;
         }
-        if (tid == 0) {
-            bool finite = true;
-            for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
-            S.iflag[1] = finite ? 1 : 0;
+        S.res[tid] = sqrt(s2);
+    }
+    if (tid == 0) {
+        bool finite = true;
+        for (int r = 0; r < m; ++r) finite &= isfinite(S.theta[r]);
+        S.iflag[1] = finite ? 1 : 0;
+    }
+    __syncthreads();
+    const bool finite = S.iflag[1] != 0;
+    int nconv = 0;
+    double est = 0.0;
+    const double tolabs = g.tol_conv * g.sigma;
+    for (int r = 0; r < k; ++r) {
+        nconv += S.res[r] <= tolabs ? 1 : 0;
+        est = fmax(est, S.res[r]);
+    }
+    const bool fin = nconv == k || restarts >= g.max_restarts;
+    // rotation: the k Ritz vectors when finished, else the p kept ones
+    // (k < p <= m - b, p a multiple of b)
+    const int ptarget = max(k + 1, (m + k) / 2);
+    const int nd = max(1, (m - ptarget) / b);
+    const int p = fin ? k : m - nd * b;
+    for (int e = tid; e < m * p; e += NT) {
+        const int q = e / p, r = e - q * p;
+        Zg[q * NCVMAX + r] = S.u.j.Z[q * LDT + S.perm[r]];
+    }
+    for (int r = tid; r < m; r += NT) g.sm[OFF_AUX + r] = S.theta[r];
+    if (!fin) {
+        for (int e = tid; e < p * p; e += NT) {
+            const int i = e / p, j = e - i * p;
+            Ag[i * NCVMAX + j] = (i == j) ? S.theta[i] : 0.0;
         }
-        __syncthreads();
-        const bool finite = S.iflag[1] != 0;
-        int nconv = 0;
-        double est = 0.0;
-        const double tolabs = g.tol_conv * g.sigma;
-        for (int r = 0; r < k; ++r) {
-            nconv += S.res[r] <= tolabs ? 1 : 0;
-            est = fmax(est, S.res[r]);
-        }
-        const bool fin = nconv == k || restarts >= g.max_restarts;
-        // rotation: the k Ritz vectors when finished, else the p kept ones
-        // (k < p <= m - b, p a multiple of b)
-        const int ptarget = max(k + 1, (m + k) / 2);
-        const int nd = max(1, (m - ptarget) / b);
-        const int p = fin ? k : m - nd * b;
-        for (int e = tid; e < m * p; e += NT) {
-            const int q = e / p, r = e - q * p;
-            Zg[q * NCVMAX + r] = S.u.j.Z[q * LDT + S.perm[r]];
-        }
-        for (int r = tid; r < m; r += NT) g.sm[OFF_AUX + r] = S.theta[r];
-        if (!fin) {
-            for (int e = tid; e < p * p; e += NT) {
-                const int i = e / p, j = e - i * p;
-                Ag[i * NCVMAX + j] = (i == j) ? S.theta[i] : 0.0;
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            s.nconv = nconv;
-            s.est = est / g.sigma;
-            s.gap = m > k ? (S.theta[k] - S.theta[k - 1]) / g.sigma : 0.0;
-            if (!finite) {
-                stop(s, 2, active);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s.nconv = nconv;
+        s.est = est / g.sigma;
+        s.gap = m > k ? (S.theta[k] - S.theta[k - 1]) / g.sigma : 0.0;
+        if (!finite) {
+            stop(s, 2, active);
+        } else {
+            s.rot_m = m;
+            s.rot_p = p;
+            s.rot_nb = fin ? 0 : b;
+            if (fin) {
+                s.out = 1;
+                stop(s, nconv == k ? 0 : 1, active);
             } else {
-                s.rot_m = m;
-                s.rot_p = p;
-                s.rot_nb = fin ? 0 : b;
-                if (fin) {
-                    s.out = 1;
-                    stop(s, nconv == k ? 0 : 1, active);
-                } else {
-                    s.m = p;
-                    s.restarts = restarts + 1;
-                }
+                s.m = p;
+                s.restarts = restarts + 1;
             }
         }
     }
@@ -975,7 +975,6 @@ __device__ __noinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int
         __hip_atomic_fetch_add(&s.ph[PH_RR], (uint64_t)(wall_clock64() - t0), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
 }
-
 
 // The items of the graphs still in their block steps (out: of the graphs
 // with output), in graph order, into alist / nalist.  Workgroup 0 only.
