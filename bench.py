@@ -49,6 +49,11 @@ def main():
     )
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument(
+        "--batched-profile",
+        action="store_true",
+        help="only run the 256-graph batched launch three times with the built-in configurations (for profilers)",
+    )
+    ap.add_argument(
         "--copy-calibration",
         action="store_true",
         help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
@@ -63,6 +68,25 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}))
+        return
+    if args.batched_profile:
+        import torch
+
+        import paper_2210_16435_amd as sf
+        from sfairsc_inputs.msbm import batched_graph, batched_specs
+
+        specs = batched_specs()
+        graphs = [batched_graph(s) for s in specs]
+        ks = [s["k"] for s in specs]
+        Gs = [sf.Graph.from_msbm(g, False) for g in graphs]
+        H = [torch.empty((k, g.n), dtype=torch.float64, device="cuda") for g, k in zip(graphs, ks)]
+        sf.tuning_clear()
+        launches = []
+        for _ in range(3):
+            rs = sf.eigs_batched(Gs, ks, tol=1e-6, precision="mixed", H_out=H, raise_not_converged=False)
+            launches.append(round(rs[0].info["batch_ms"], 2))
+        torch.cuda.synchronize()
+        print(json.dumps({"batched_launch_ms": launches, "handed_off": sum(r.info["path"] for r in rs)}))
         return
     if args.gpus != 1:
         print(

@@ -67,7 +67,7 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 #define SF_BATCH_THREADS 1024
 #endif
 #ifndef SF_ITEM_FN
-#define SF_ITEM_FN __noinline__
+#define SF_ITEM_FN __forceinline__
 #endif
 constexpr int NT = SF_BATCH_THREADS;            // threads of a workgroup
 constexpr int NW = NT / 64;                     // wavefronts
@@ -490,21 +490,30 @@ __device__ SF_ITEM_FN void w_upd(int64_t n, double* V, int ld, int coff, int kin
             const int64_t row = row0 + li;
             const bool rv = row < n;
             const double* src = V + row * ld + coff + 4 * lk;
-            double4 x[KCH];
+            // the row chunk in two halves (fewer live registers); every
+            // input of the tile is read before its first store
+            constexpr int KH = (KCH + 1) / 2;
 #pragma unroll
-            for (int c = 0; c < KCH; ++c) {
-                x[c] = make_double4(0, 0, 0, 0);
-                if (rv && c * 16 + 4 * lk < kin) x[c] = *reinterpret_cast<const double4*>(src + c * 16);
-            }
+            for (int hb = 0; hb < 2; ++hb) {
+                double4 x[KH];
 #pragma unroll
-            for (int c = 0; c < KCH; ++c) {
-                if (c * 16 < kin) {
-                    const double xs[4] = {x[c].x, x[c].y, x[c].z, x[c].w};
+                for (int cc = 0; cc < KH; ++cc) {
+                    const int c = hb * KH + cc;
+                    x[cc] = make_double4(0, 0, 0, 0);
+                    if (c < KCH && rv && c * 16 + 4 * lk < kin)
+                        x[cc] = *reinterpret_cast<const double4*>(src + c * 16);
+                }
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int kr = c * 16 + 4 * lk + s;
-                        const double bm = kr < kin ? M[kr * 16 + li] : 0.0;
-                        D = mfma16(xs[s], bm, D);
+                for (int cc = 0; cc < KH; ++cc) {
+                    const int c = hb * KH + cc;
+                    if (c < KCH && c * 16 < kin) {
+                        const double xs[4] = {x[cc].x, x[cc].y, x[cc].z, x[cc].w};
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const int kr = c * 16 + 4 * lk + s;
+                            const double bm = kr < kin ? M[kr * 16 + li] : 0.0;
+                            D = mfma16(xs[s], bm, D);
+                        }
                     }
                 }
             }
@@ -1014,30 +1023,48 @@ __device__ __forceinline__ void add_ticks(GState& s, int ph, uint64_t t0) {
 }
 
 // Row phase: every workgroup takes the listed items blockIdx.x,
-// + gridDim.x, ...; the body sees g (graph), s (state), it (item), wr0 / wr1
-// (this wavefront's rows), wt0 / wt1 (its 16-row tiles), slot (the item's
-// partial slot) and wp (this wavefront's LDS partial).  COND must be uniform
-// for the graph.
-#define SF_ITEMS(PH, COND, ...)                                                                   \
-    for (int j_ = blockIdx.x, n_ = *L.nalist; j_ < n_; j_ += gridDim.x) {                         \
-        const int it = L.alist[j_];                                                               \
-        const Item itm = L.items[it];                                                             \
-        const Graph& g = L.graphs[itm.g];                                                         \
-        GState& s = L.st[itm.g];                                                                  \
-        if (!(COND)) continue;                                                                    \
-        const uint64_t t0_ = wall_clock64();                                                      \
-        const int64_t wr0 = min(g.n, itm.row0 + (int64_t)wave * WROWS);                          \
-        const int64_t wr1 = min(g.n, wr0 + WROWS);                                                \
-        const int64_t wt0 = wr0 >> 4, wt1 = wr1 > wr0 ? (wr1 + 15) >> 4 : wt0;                  \
-        double* slot = L.part + (size_t)it * PSTRIDE;                                             \
-        double* wp = S.u.wred + wave * WRED;                                                      \
-        (void)wt0;                                                                                \
-        (void)wt1;                                                                                \
-        (void)slot;                                                                               \
-        (void)wp;                                                                                 \
-        __VA_ARGS__;                                                                              \
-        add_ticks(s, PH, t0_);                                                                    \
+// + gridDim.x, ... and runs f on each: f(g (graph), s (state), it (item),
+// wr0 / wr1 (this wavefront's rows), wt0 / wt1 (its 16-row tiles), slot (the
+// item's partial slot), wp (this wavefront's LDS partial), tid, wave, S,
+// t0_ (the item's start clock)) returns false, before any work, when the
+// graph does not take part (uniform for the graph).  One non-inlined
+// instance per phase: the row work is inlined into it, so registers are
+// saved once per phase rather than once per item.
+template <class F>
+__device__ __noinline__ void items_phase(Launch L, Shared& S, int ph, F f) {
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int j_ = blockIdx.x, n_ = *L.nalist; j_ < n_; j_ += gridDim.x) {
+        const int it = L.alist[j_];
+        const Item itm = L.items[it];
+        const Graph& g = L.graphs[itm.g];
+        GState& s = L.st[itm.g];
+        const uint64_t t0_ = wall_clock64();
+        const int64_t wr0 = min(g.n, itm.row0 + (int64_t)wave * WROWS);
+        const int64_t wr1 = min(g.n, wr0 + WROWS);
+        const int64_t wt0 = wr0 >> 4, wt1 = wr1 > wr0 ? (wr1 + 15) >> 4 : wt0;
+        double* slot = L.part + (size_t)it * PSTRIDE;
+        double* wp = S.u.wred + wave * WRED;
+        if (f(g, s, it, wr0, wr1, wt0, wt1, slot, wp, tid, wave, S, t0_)) add_ticks(s, ph, t0_);
     }
+}
+
+#define SF_ITEMS(PH, COND, ...)                                                                          \
+    items_phase(L, S, PH,                                                                                \
+                [=](const Graph& g, GState& s, int it, int64_t wr0, int64_t wr1, int64_t wt0, int64_t wt1, \
+                    double* slot, double* wp, int tid, int wave, Shared& S, uint64_t t0_) -> bool {      \
+                    (void)it;                                                                            \
+                    (void)wr0;                                                                           \
+                    (void)wr1;                                                                           \
+                    (void)wt0;                                                                           \
+                    (void)wt1;                                                                           \
+                    (void)slot;                                                                          \
+                    (void)wp;                                                                            \
+                    (void)wave;                                                                          \
+                    (void)t0_;                                                                           \
+                    if (!(COND)) return false;                                                           \
+                    __VA_ARGS__;                                                                         \
+                    return true;                                                                         \
+                })
 
 // Graph phase: workgroup blockIdx.x owns graphs blockIdx.x, + gridDim.x, ...
 // Every thread reads COND before the body may change the state.
