@@ -90,7 +90,7 @@ def main():
         return
     if args.gpus != 1:
         print(
-            "bench.py measures one GPU only: this build has no multi-GPU path "
+            "bench.py measures one GPU only: the library has no multi-GPU path "
             "(each graph's solve runs on a single device).",
             file=sys.stderr,
         )

@@ -14,7 +14,7 @@
 
 namespace sfairsc {
 
-// Limits of this build.
+// Library limits.
 constexpr int kMaxBlock = 32;     // widest block of vectors (columns)
 constexpr int kMaxGroups = 32;    // h
 constexpr int kMaxBasis = 192;    // Krylov basis columns before a restart
