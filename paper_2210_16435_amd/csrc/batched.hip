@@ -761,28 +761,54 @@ __device__ __noinline__ bool g_chol(const double* G, int b, double thresh, doubl
 // Eigen-decomposition of the symmetric m x m matrix A (LDS, stride LDT) by
 // cyclic Jacobi, round-robin ordering, rotations accumulated into Z (LDS,
 // stride LDT, the identity on entry).  A round's m/2 rotations are disjoint
-// and applied at once: a thread takes the 2 x 2 block of entries (rows of
-// pair a, columns of pair c), a <= c, and writes J_a^T A_ac J_c and its
-// mirror from the old values, so a round needs one barrier after the
-// rotation angles and one after the update.  Rotations whose off-diagonal
-// entry is at most 1e-16 ||A||_F (the rounding level of the rotations
-// themselves) are skipped and blocks of two skipped pairs are not touched;
-// the sweeps stop after one without rotations (at most 40).  On return
-// diag(A) holds the eigenvalues and Z the eigenvectors as columns.
+// and applied at once: a thread takes a 2 x 2 block of entries (rows of pair
+// a, columns of pair c, a <= c) and writes J_a^T A_ac J_c and its mirror
+// from the old values, so a round needs one barrier after the rotation
+// angles and one after the update.  The blocks and the (row, pair) updates
+// of Z are spread evenly over the threads once per call.  Rotations whose
+// off-diagonal entry is at most 1e-16 ||A||_F (the rounding level of the
+// rotations themselves) are skipped and blocks of two skipped pairs are not
+// touched; the sweeps stop after one without rotations (at most 40).  On
+// return diag(A) holds the eigenvalues and Z the eigenvectors as columns.
 __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
     const int t = threadIdx.x;
-    constexpr int GR = NT / 32;
-    const int tr = t >> 5, tc = t & 31;  // GR x 32 thread grid
     const int mm = m + (m & 1), np = mm / 2, rr = mm - 1;
-    double off = 0.0, dg = 0.0;
-    for (int i = tr; i < m; i += GR)
-        for (int j = tc; j < m; j += 32) {
-            const double v = A[i * LDT + j];
-            if (i != j)
-                off += v * v;
-            else
-                dg += v * v;
+    // this thread's block (pair ba, pair bc), if any
+    static_assert((NCVMAX / 2) * (NCVMAX / 2 + 1) / 2 <= NT, "one Jacobi block per thread");
+    int ba = -1, bc = -1;
+    {
+        int idx = t, a = 0;
+        if (idx < np * (np + 1) / 2) {
+            while (idx >= np - a) {
+                idx -= np - a;
+                ++a;
+            }
+            ba = a;
+            bc = a + idx;
         }
+    }
+    // this thread's (row, pair) updates of Z
+    constexpr int ZMAX = (NCVMAX * (NCVMAX / 2) + NT - 1) / NT;
+    int zi[ZMAX], zp[ZMAX];
+#pragma unroll
+    for (int u = 0; u < ZMAX; ++u) {
+        const int idx = t + u * NT;
+        zi[u] = -1;
+        zp[u] = 0;
+        if (idx < m * np) {
+            zi[u] = idx / np;
+            zp[u] = idx - zi[u] * np;
+        }
+    }
+    double off = 0.0, dg = 0.0;
+    for (int idx = t; idx < m * m; idx += NT) {
+        const int i = idx / m, j = idx - i * m;
+        const double v = A[i * LDT + j];
+        if (i != j)
+            off += v * v;
+        else
+            dg += v * v;
+    }
     wg_sum2(off, dg, S.wsum);
     const double tiny = 1e-16 * sqrt(dg + off);
     for (int sweep = 0; sweep < 40; ++sweep) {
@@ -820,19 +846,15 @@ __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
                 S.jpq[t] = make_int2(p, q);
             }
             __syncthreads();
-            // A <- J^T A J on 2 x 2 blocks (a <= c, mirrored); entries with an
-            // index >= m (the padding index of odd m) are neither read nor written
-            for (int a = tr; a < np; a += GR) {
-                const double2 cs1 = S.jcs[a];
-                const int2 pq1 = S.jpq[a];
-                const int p1 = pq1.x, q1 = pq1.y;
-                const bool vq1 = q1 < m;
-                for (int cq = a + tc; cq < np; cq += 32) {
-                    const double2 cs2 = S.jcs[cq];
-                    if (cs1.y == 0.0 && cs2.y == 0.0) continue;
-                    const int2 pq2 = S.jpq[cq];
-                    const int p2 = pq2.x, q2 = pq2.y;
-                    const bool vq2 = q2 < m;
+            // A <- J^T A J on this thread's 2 x 2 block (mirrored); entries
+            // with an index >= m (the padding index of odd m) are neither
+            // read nor written
+            if (ba >= 0) {
+                const double2 cs1 = S.jcs[ba], cs2 = S.jcs[bc];
+                if (cs1.y != 0.0 || cs2.y != 0.0) {
+                    const int2 pq1 = S.jpq[ba], pq2 = S.jpq[bc];
+                    const int p1 = pq1.x, q1 = pq1.y, p2 = pq2.x, q2 = pq2.y;
+                    const bool vq1 = q1 < m, vq2 = q2 < m;
                     const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
                     const double x00 = A[p1 * LDT + p2];
                     const double x01 = vq2 ? A[p1 * LDT + q2] : 0.0;
@@ -848,7 +870,7 @@ __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
                     if (vq2) A[p1 * LDT + q2] = z01;
                     if (vq1) A[q1 * LDT + p2] = z10;
                     if (vq1 && vq2) A[q1 * LDT + q2] = z11;
-                    if (cq != a) {
+                    if (bc != ba) {
                         A[p2 * LDT + p1] = z00;
                         if (vq2) A[q2 * LDT + p1] = z01;
                         if (vq1) A[p2 * LDT + q1] = z10;
@@ -857,16 +879,16 @@ __device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
                 }
             }
             // Z <- Z J
-            for (int pr = tc; pr < np; pr += 32) {
-                const double2 cs = S.jcs[pr];
+#pragma unroll
+            for (int u = 0; u < ZMAX; ++u) {
+                if (zi[u] < 0) continue;
+                const double2 cs = S.jcs[zp[u]];
                 if (cs.y == 0.0) continue;
-                const int2 pq = S.jpq[pr];
-                for (int i = tr; i < m; i += GR) {
-                    double* z = Z + i * LDT;
-                    const double zp = z[pq.x], zq = z[pq.y];
-                    z[pq.x] = cs.x * zp - cs.y * zq;
-                    z[pq.y] = cs.y * zp + cs.x * zq;
-                }
+                const int2 pq = S.jpq[zp[u]];
+                double* z = Z + zi[u] * LDT;
+                const double a0 = z[pq.x], a1 = z[pq.y];
+                z[pq.x] = cs.x * a0 - cs.y * a1;
+                z[pq.y] = cs.y * a0 + cs.x * a1;
             }
             __syncthreads();
         }
