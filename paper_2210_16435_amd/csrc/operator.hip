@@ -82,6 +82,76 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_partial(const double* __r
     }
 }
 
+// The same partial sums for a power-of-two width b (4..32), with every lane
+// busy: a wavefront covers 64 / b rows per load, each lane keeps eight
+// groups' sums in registers (all h groups in ceil(h / 8) passes over its
+// rows), and four rows per lane are loaded together.  The block handles a
+// contiguous run of rows; its wavefronts' sums are combined in wavefront
+// order.  part: [gridDim.x][h][b], as k_proj_partial.
+__global__ __launch_bounds__(kProjThreads) void k_proj_partial_p2(const double* __restrict__ X, int ldx, int b,
+                                                                   int64_t n, const int32_t* __restrict__ grp,
+                                                                   const double* __restrict__ cs, int h,
+                                                                   double* __restrict__ part, const int* skip) {
+    if (skip && *skip) return;
+    constexpr int NWV = kProjThreads / 64;
+    __shared__ double wsum[NWV][kMaxGroups * 32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lb = 31 - __clz(b);
+    const int col = lane & (b - 1), rl = lane >> lb, rpw = 64 >> lb;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
+    const int64_t step = (int64_t)NWV * rpw;
+    for (int g0 = 0; g0 < h; g0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        int64_t i = r0 + (int64_t)wave * rpw + rl;
+        for (; i + 3 * step < r1; i += 4 * step) {
+            int gi[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t r = i + u * step;
+                gi[u] = grp[r] - g0;
+                v[u] = (cs ? cs[r] : 1.0) * X[r * ldx + col];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += (gi[u] == q) ? v[u] : 0.0;
+        }
+        for (; i < r1; i += step) {
+            const int gi = grp[i] - g0;
+            const double v = (cs ? cs[i] : 1.0) * X[i * ldx + col];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += (gi == q) ? v : 0.0;
+        }
+        for (int off = b; off < 64; off <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += __shfl_xor(acc[q], off);
+        if (rl == 0)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g0 + q < h) wsum[wave][(g0 + q) * b + col] = acc[q];
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < h * b; o += kProjThreads) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) sum += wsum[w][o];
+        part[(size_t)blockIdx.x * h * b + o] = sum;
+    }
+}
+
+static void launch_proj_partial(const double* X, int ldx, int b, int64_t n, const int32_t* grp, const double* cs,
+                                int h, double* part, int nblk, const int* skip, hipStream_t s) {
+    if (b >= 4 && b <= 32 && (b & (b - 1)) == 0)
+        k_proj_partial_p2<<<nblk, kProjThreads, 0, s>>>(X, ldx, b, n, grp, cs, h, part, skip);
+    else
+        k_proj_partial<<<nblk, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
+            X, ldx, b, n, grp, cs, h, part, skip);
+}
+
 // Combine per-block partial group sums and solve with G^{-1}.
 //   A = sum over blocks;  Z_s = A_s - p_s sum_t A_t  (s < h-1)
 //   if S_sub: Z -= sigma * S_sub   (output side: C^T T - sigma C^T X)
@@ -366,8 +436,7 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
     const int h = g->h;
 
     // S = C^T X, R_in table
-    k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
-        X, ldx, b, n, g->grp, g->cs, h, w.part_in.as<double>(), skip);
+    launch_proj_partial(X, ldx, b, n, g->grp, g->cs, h, w.part_in.as<double>(), w.nblk_proj, skip, s);
     k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx,
                                                Rin, skip);
     const int ga = grid_rows(n * BW, 256, 8192);
@@ -433,8 +502,7 @@ int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
     double* Rin = w.small.as<double>();
     double* Sx = Rin + kMaxGroups * 32;
     const int h = g->h;
-    k_proj_partial<<<w.nblk_proj, kProjThreads, (size_t)(kProjThreads / 32) * h * 32 * sizeof(double), s>>>(
-        X, ldx, b, g->n, g->grp, g->cs, h, w.part_in.as<double>(), nullptr);
+    launch_proj_partial(X, ldx, b, g->n, g->grp, g->cs, h, w.part_in.as<double>(), w.nblk_proj, nullptr, s);
     double* sums = Rin + 4 * kMaxGroups * 32;
     k_reduce_partials<<<reduce_grid(h * b), kRedElems * kRedSlices, 0, s>>>(w.part_in.as<double>(), w.nblk_proj,
                                                                             h * b, sums, nullptr);
