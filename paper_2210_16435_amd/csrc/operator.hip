@@ -22,7 +22,7 @@ namespace sfairsc {
 constexpr int kSpmmThreads = 512;            // 8 waves
 constexpr int kSpmmWaves = kSpmmThreads / 64;
 #ifndef SF_SPMM_MAX_BLOCKS
-#define SF_SPMM_MAX_BLOCKS 512
+#define SF_SPMM_MAX_BLOCKS 1024
 #endif
 constexpr int kSpmmMaxBlocks = SF_SPMM_MAX_BLOCKS;
 constexpr int kProjThreads = 256;
