@@ -182,6 +182,7 @@ def main():
         del G
         torch.cuda.empty_cache()
         extra = {
+            "fair_vs_sc": bench_fair_vs_sc(sf, torch, g, k, tol, normalized, b, results, args.steps, args.warmup),
             "batched_256": bench_batched(sf, torch),
             "backward_200k": bench_backward(sf, torch),
             "mixed_2m": bench_2m(sf, torch),
@@ -241,6 +242,43 @@ def main():
 
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_fair_vs_sc(sf, torch, g, k, tol, normalized, b, fair, steps, warmup):
+    """The cost of fairness on the same kernels: plain spectral clustering is
+    the same solve with one group (F has no columns, so P = I and L^sigma = L),
+    timed like the headline on the same graph, k, tolerance and block width."""
+    import dataclasses
+
+    gs = dataclasses.replace(g, groups=np.zeros(g.n, dtype=np.int32), h=1)
+    G = sf.Graph.from_msbm(gs, normalized)
+    H = torch.empty((k, g.n), dtype=torch.float64, device="cuda")
+    out = {"workload": "the headline graph with one group (plain SC), same k, tol and block width"}
+    for prec in ("mixed", "fp64"):
+        def solve():
+            return G.eigs(k, tol=tol, precision=prec, block_width=b, H_out=H)
+
+        for _ in range(warmup):
+            solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+        fair_ms, fair_r = fair[prec]
+        out[prec] = {
+            "sc_ms": round(ms, 4),
+            "fair_ms": round(fair_ms, 4),
+            "fair_over_sc": round(fair_ms / ms, 3),
+            "sc_block_steps": r.info["block_steps"],
+            "fair_block_steps": fair_r.info["block_steps"],
+            "sc_max_rel_residual": r.info["max_rel_residual"],
+        }
+    _log(f"fair vs sc: {out}")
+    del G, H
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(sf, torch):

@@ -119,6 +119,28 @@ def test_small_random_graphs(case):
     check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, G.sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
 
 
+@pytest.mark.parametrize("normalized", [False, True])
+def test_plain_sc_h1_on_the_same_kernels(normalized):
+    # plain spectral clustering = the fair problem with one group (F has no
+    # columns, P = I, L^sigma = L); the oracle's h = 1 case is the textbook
+    # eigenproblem (pinned in test_oracle_pins); lambda_1 = 0 is the trivial pair
+    import dataclasses
+
+    sf = lib()
+    g0 = workload("msbm-2k-h2")
+    g = dataclasses.replace(g0, groups=np.zeros(g0.n, dtype=np.int32), h=1)
+    k, tol = 5, 1e-10
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, 1, k + 1, normalized)
+    assert abs(lam_ref[0]) <= 1e-10 * lam_ref[1]
+    G = sf.Graph.from_msbm(g, normalized)
+    r = G.eigs(k, tol=tol, precision="fp64")
+    log(f"plain SC normalized={normalized}: info {r.info}")
+    gap = (lam_ref[k] - lam_ref[k - 1]) / G.sigma
+    check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, G.sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
+    rm = G.eigs(k, tol=1e-6, precision="mixed")
+    check_solution(g, rm.eigenvalues, to_np(rm.H), k, normalized, 1e-6, G.sigma, lam_ref, H_ref, 1e-5, 1e-4, gap)
+
+
 def test_complete_graph_breakdown_is_repaired():
     # K_n has only the eigenvalues 0 and n (and sigma after deflation): the
     # Krylov space becomes invariant after a few blocks and must be repaired
