@@ -40,4 +40,4 @@ from .metrics import (  # noqa: F401
     max_principal_angle,
     same_partition,
 )
-from .gradient import eigsum_edge_gradient  # noqa: F401
+from .gradient import eigsum_edge_gradient, eigsum_edge_gradient_normalized  # noqa: F401

@@ -156,6 +156,80 @@ def test_gradient_matches_finite_differences():
         assert grad[a] + grad[b] == pytest.approx(fd, rel=1e-5, abs=1e-8)
 
 
+def _eigsum_csr(W, groups, h, k, normalized):
+    lam, _ = oracle.fair_eigs_dense(W, groups, h, k, normalized)
+    return lam.sum()
+
+
+def test_normalized_gradient_matches_finite_differences():
+    # edges (both stored copies perturbed together) and stored diagonal
+    # entries (perturbed alone: they enter D but not L)
+    g = random_sparse_graph(60, 10, seed=11, h=3)
+    n, k = 60, 4
+    W = g.to_scipy().tolil()
+    for i in (3, 17, 40):
+        W[i, i] = 0.7
+    W = W.tocsr()
+    W.sort_indices()
+    rowptr, col = W.indptr.astype(np.int64), W.indices.astype(np.int64)
+    lam, H = oracle.fair_eigs_dense(W, g.groups, 3, k + 1, True)
+    assert lam[k] - lam[k - 1] > 1e-3
+    d = oracle.degrees(W)
+    assert np.allclose(H.T @ (d[:, None] * H), np.eye(k + 1), atol=1e-10)
+    grad = oracle.eigsum_edge_gradient_normalized(rowptr, col, H[:, :k], lam[:k])
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    rng = np.random.default_rng(1)
+    off = np.flatnonzero(rows < col)
+    picks = [(int(rows[e]), int(col[e])) for e in rng.choice(off, 10, replace=False)] + [(3, 3), (17, 17), (40, 40)]
+    step = 1e-6
+    for i, j in picks:
+        Wp, Wm = W.copy().tolil(), W.copy().tolil()
+        Wp[i, j] += step
+        Wm[i, j] -= step
+        if i != j:
+            Wp[j, i] += step
+            Wm[j, i] -= step
+        fd = (_eigsum_csr(Wp.tocsr(), g.groups, 3, k, True) - _eigsum_csr(Wm.tocsr(), g.groups, 3, k, True)) / (2 * step)
+        a = np.flatnonzero((rows == i) & (col == j))[0]
+        b = np.flatnonzero((rows == j) & (col == i))[0]
+        an = grad[a] + (grad[b] if i != j else 0.0)
+        assert an == pytest.approx(fd, rel=1e-5, abs=1e-8), (i, j)
+    # the unnormalized formula misses the degree term: it must not pass here
+    plain = oracle.eigsum_edge_gradient(rowptr, col, H[:, :k])
+    assert np.abs(plain - grad).max() > 1e-3 * np.abs(grad).max()
+
+
+def test_normalized_gradient_matches_autograd_of_dense_generalized_eigh():
+    torch = pytest.importorskip("torch")
+    g = random_sparse_graph(50, 8, seed=12, h=2)
+    k = 3
+    ei, ej, w = _edge_list(g)
+    wt = torch.tensor(w, dtype=torch.float64, requires_grad=True)
+    n = 50
+    Wd = torch.zeros((n, n), dtype=torch.float64)
+    Wd = Wd.index_put((torch.tensor(ei), torch.tensor(ej)), wt, accumulate=True)
+    Wd = Wd + Wd.T
+    d = Wd.sum(1)
+    L = torch.diag(d) - Wd
+    F = torch.tensor(oracle.fairness_matrix(g.groups, 2))
+    Q, _ = torch.linalg.qr(F, mode="complete")
+    Z = Q[:, 1:]
+    M = Z.T @ L @ Z
+    B = Z.T @ (d[:, None] * Z)
+    C = torch.linalg.cholesky(0.5 * (B + B.T))
+    Ci = torch.linalg.inv(C)
+    S = Ci @ (0.5 * (M + M.T)) @ Ci.T
+    lam = torch.linalg.eigvalsh(0.5 * (S + S.T))
+    lam[:k].sum().backward()
+    lamo, H = oracle.fair_eigs_dense(g.to_scipy(), g.groups, 2, k, True)
+    assert np.allclose(lamo, lam[:k].detach().numpy(), rtol=1e-10, atol=1e-12)
+    grad = oracle.eigsum_edge_gradient_normalized(g.rowptr, g.col, H, lamo)
+    rows = g.row_index()
+    lookup = {(int(r), int(c)): t for t, (r, c) in enumerate(zip(rows, g.col))}
+    per_edge = np.array([grad[lookup[(ei[e], ej[e])]] + grad[lookup[(ej[e], ei[e])]] for e in range(ei.size)])
+    assert np.allclose(per_edge, wt.grad.numpy(), rtol=1e-8, atol=1e-10)
+
+
 def test_gradient_matches_autograd_of_dense_eigh():
     torch = pytest.importorskip("torch")
     g = random_sparse_graph(50, 8, seed=10, h=2)
