@@ -370,7 +370,7 @@ def bench_backward(sf, torch):
     import ctypes
 
     def once():
-        sf._lib.check(lib.sfairsc_eigsum_backward(G._h, ctypes.c_void_p(Hc.data_ptr()), k,
+        sf._lib.check(lib.sfairsc_eigsum_backward(G._h, ctypes.c_void_p(Hc.data_ptr()), k, None,
                                                   ctypes.c_void_p(grad.data_ptr()),
                                                   ctypes.c_void_p(stream.cuda_stream)))
 

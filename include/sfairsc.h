@@ -343,18 +343,27 @@ int sfairsc_labels(sfairsc_graph_t g, const double* H, int32_t kdim,
 /* ---- differentiation -------------------------------------------------- */
 
 /*
- * Gradient of f(W) = sum_{i<=k} lambda_i (the k smallest fair eigenvalues,
- * unnormalized variant) with respect to every stored value w_ij, by the
- * envelope theorem applied to Theorem 2.1 / Proposition 3.3:
- *     grad[e] = 0.5 * sum_l (H[i,l] - H[j,l])^2   for stored entry e = (i,j),
- * so the two stored copies of an edge together carry d f / d w_ij.
- * sigma is held constant.  Valid when lambda_k < lambda_{k+1}.
- * H          device double, column-major n x k (from sfairsc_eigs).
- * grad       device [nnz] in the handle's value dtype.
- * Errors: E_ARG (normalized handles: not supported), E_HIP.  Asynchronous.
+ * Gradient of f(W) = sum_{i<=k} lambda_i (the k smallest fair eigenvalues)
+ * with respect to every stored value w_ij, by the envelope theorem applied
+ * to Theorem 2.1 / Proposition 3.3 (F does not depend on W; sigma is held
+ * constant).  For stored entry e = (i, j):
+ *   unnormalized:  grad[e] = 0.5 * sum_l (H[i,l] - H[j,l])^2
+ *   normalized:    grad[e] = 0.5 * sum_l [(H[i,l] - H[j,l])^2
+ *                                         - lambda_l (H[i,l]^2 + H[j,l]^2)]
+ * (in the normalized variant w_ij also enters d_i and d_j; H is
+ * D-orthonormal there), so the two stored copies of an edge together carry
+ * d f / d w_ij and a stored diagonal entry carries its whole derivative.
+ * Valid when lambda_k < lambda_{k+1}.
+ * H            device double, column-major n x k (from sfairsc_eigs).
+ * eigenvalues  host double[k], the eigenvalues matching the columns of H;
+ *              required for normalized handles, ignored (may be NULL) for
+ *              unnormalized ones.  Read before the call returns.
+ * grad         device [nnz] in the handle's value dtype.
+ * Errors: E_ARG, E_NOMEM, E_HIP.  Asynchronous.
  */
 int sfairsc_eigsum_backward(sfairsc_graph_t g, const double* H, int32_t k,
-                            void* grad, hipStream_t stream);
+                            const double* eigenvalues, void* grad,
+                            hipStream_t stream);
 
 /* ---- diagnostics ------------------------------------------------------ */
 

@@ -243,12 +243,22 @@ class Graph:
         return lab, inertia.value
 
     # -- differentiation -------------------------------------------------
-    def eigsum_backward(self, H: torch.Tensor, stream=None) -> torch.Tensor:
-        """Per stored entry: 0.5 * ||H_i - H_j||^2 (gradient of the sum of the
-        k smallest fair eigenvalues w.r.t. the stored weights)."""
+    def eigsum_backward(self, H: torch.Tensor, eigenvalues=None, stream=None) -> torch.Tensor:
+        """Gradient of the sum of the k smallest fair eigenvalues w.r.t. the
+        stored weights, per stored entry (i, j):
+        0.5 * ||H_i - H_j||^2 (unnormalized), or
+        0.5 * sum_l [(H_il - H_jl)^2 - lambda_l (H_il^2 + H_jl^2)]
+        (normalized; `eigenvalues` = the lambda_l matching H's columns)."""
         Hc = H.to(self.device, torch.float64).t().contiguous()
+        k = Hc.shape[0]
+        lam = None
+        if eigenvalues is not None:
+            lam_np = np.ascontiguousarray(np.asarray(eigenvalues, dtype=np.float64).reshape(-1))
+            if lam_np.size != k:
+                raise ValueError(f"{lam_np.size} eigenvalues for {k} columns")
+            lam = lam_np.ctypes.data_as(ctypes.c_void_p)
         grad = torch.empty(self.nnz, dtype=self.value_dtype, device=self.device)
-        _lib.check(_lib.lib().sfairsc_eigsum_backward(self._h, _ptr(Hc), Hc.shape[0], _ptr(grad), _stream(stream)))
+        _lib.check(_lib.lib().sfairsc_eigsum_backward(self._h, _ptr(Hc), k, lam, _ptr(grad), _stream(stream)))
         return grad
 
 
@@ -355,25 +365,28 @@ def tuning_lookup(n: int, nnz: int, k: int, precision="mixed", normalized: bool 
 
 
 class FairEigSum(torch.autograd.Function):
-    """f(w) = sum of the k smallest fair eigenvalues of the unnormalized
-    variant, as a function of the stored edge weights w (CSR order).
+    """f(w) = sum of the k smallest fair eigenvalues, as a function of the
+    stored edge weights w (CSR order).
 
-    forward(values, rowptr, col, groups, h, k, tol) -> scalar tensor.
-    backward: grad_values = grad_out * 0.5 * ||H_i - H_j||^2 per stored entry
-    (hand-written HIP kernel).  Both stored copies of an edge must receive the
-    same perturbation for the result to be a directional derivative.
+    forward(values, rowptr, col, groups, h, k, tol, normalized=False) ->
+    scalar tensor.  backward: grad_values = grad_out * the per-entry gradient
+    of Graph.eigsum_backward (hand-written HIP kernel).  Both stored copies of
+    an edge must receive the same perturbation for the result to be a
+    directional derivative.
     """
 
     @staticmethod
-    def forward(ctx, values, rowptr, col, groups, h, k, tol=1e-10):
-        g = Graph(rowptr, col, values.detach(), groups, h, normalized=False, device=values.device)
+    def forward(ctx, values, rowptr, col, groups, h, k, tol=1e-10, normalized=False):
+        g = Graph(rowptr, col, values.detach(), groups, h, normalized=bool(normalized), device=values.device)
         res = g.eigs(k, tol=tol, precision="fp64")
         ctx.graph = g
+        ctx.eigenvalues = np.asarray(res.eigenvalues, dtype=np.float64).copy()
         ctx.save_for_backward(res.H)
         return torch.tensor(float(res.eigenvalues.sum()), dtype=values.dtype, device=values.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         (H,) = ctx.saved_tensors
-        grad = ctx.graph.eigsum_backward(H)
-        return grad_out * grad, None, None, None, None, None, None
+        lam = ctx.eigenvalues if ctx.graph.normalized else None
+        grad = ctx.graph.eigsum_backward(H, lam)
+        return grad_out * grad, None, None, None, None, None, None, None

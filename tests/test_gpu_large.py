@@ -107,3 +107,49 @@ def test_gradient_200k_full_size():
         worst = max(worst, abs(fd - an) / bound)
         assert abs(fd - an) <= bound, (e, fd, an)
     log(f"  finite differences: worst |fd - grad| / bound {worst:.2f}")
+
+
+def test_normalized_gradient_200k_full_size():
+    sf = lib()
+    g = workload("msbm-200k-h4-grad")
+    k = 10
+    log(f"msbm-200k-grad normalized: n={g.n} nnz={g.nnz}")
+    vals = torch.from_numpy(g.val.astype(np.float64))
+    G = sf.Graph(g.rowptr, g.col, vals, g.groups, g.h, True)
+    sigma = G.sigma
+    r = G.eigs(k, tol=1e-12, precision="fp64")
+    log(f"  forward info {r.info}")
+    H, lam = to_np(r.H), r.eigenvalues
+    grad = to_np(G.eigsum_backward(r.H, lam))
+    ref = oracle.eigsum_edge_gradient_normalized(g.rowptr, g.col, H, lam)
+    rel = np.abs(grad - ref).max() / np.abs(ref).max()
+    log(f"  backward vs oracle formula rel err {rel:.2e}")
+    assert rel <= 1e-12
+    x0 = r.H.contiguous()
+    rows = g.row_index()
+
+    def f(v):
+        Gp = sf.Graph(g.rowptr, g.col, v, g.groups, g.h, True)
+        rp = Gp.eigs(k, tol=1e-10, precision="fp64", x0=x0)
+        return float(np.sum(rp.eigenvalues))
+
+    rng = np.random.default_rng(6)
+    top = np.argsort(-np.abs(grad))[:8]
+    picks = list(top) + [int(x) for x in rng.choice(g.nnz, 8, replace=False)]
+    step = 1e-4
+    worst = 0.0
+    for e in picks:
+        i, j = rows[e], g.col[e]
+        mate = g.rowptr[j] + np.searchsorted(g.col[g.rowptr[j]:g.rowptr[j + 1]], i)
+        vp = vals.clone()
+        vm = vals.clone()
+        vp[e] += step
+        vp[mate] += step
+        vm[e] -= step
+        vm[mate] -= step
+        fd = (f(vp) - f(vm)) / (2 * step)
+        an = grad[e] + grad[mate]
+        bound = 1e-3 * abs(an) + 4 * k * 2.2e-16 * sigma / step + 1e-10
+        worst = max(worst, abs(fd - an) / bound)
+        assert abs(fd - an) <= bound, (e, fd, an)
+    log(f"  finite differences: worst |fd - grad| / bound {worst:.2f}")
