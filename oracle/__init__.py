@@ -41,3 +41,11 @@ from .metrics import (  # noqa: F401
     same_partition,
 )
 from .gradient import eigsum_edge_gradient, eigsum_edge_gradient_normalized  # noqa: F401
+from .general_f import (  # noqa: F401
+    membership_fairness_matrix,
+    general_constraint_matrix,
+    range_basis,
+    fair_eigs_dense_general,
+    fair_eigs_implicit_general,
+    apply_deflated_operator_general,
+)

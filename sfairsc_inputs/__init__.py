@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the s-FairSC solver and its CPU oracle.
 
-This package only *generates* inputs: graphs (CSR adjacency), group labels and
-planted clusters.  It contains none of the method's arithmetic (no Laplacian,
+This package only *generates* inputs: graphs (CSR adjacency), group labels,
+planted clusters, random placeholder constraint matrices and group
+memberships.  It contains none of the method's arithmetic (no Laplacian,
 no projection, no eigensolver, no k-means), so both the GPU library's tests and
 the oracle's tests can draw the same inputs from it without sharing code.
 """
@@ -15,3 +16,4 @@ from .msbm import (  # noqa: F401
     WORKLOADS,
     random_sparse_graph,
 )
+from .general import random_laplacian, overlapping_memberships  # noqa: F401
