@@ -19,7 +19,9 @@
  *
  * Method (Section 3.3-3.4, Alg. 3): the k smallest eigenpairs of the deflated
  * operator L^sigma = P (L_n - sigma I) P + sigma I (eq. asigma), with
- * P = I - C (C^T C)^{-1} C^T applied from the group labels (eq. mv-Pw) and
+ * P = I - C (C^T C)^{-1} C^T applied from the group labels (eq. mv-Pw;
+ * or from an orthonormal basis of range(C) for a general F, see
+ * sfairsc_graph_set_constraint) and
  * sigma = ||L_n||_1 (Appendix B.3), found by a block Krylov-Schur
  * (thick-restart Lanczos) eigensolver; then k-means on the rows of H
  * (Alg. 3 step 4).  Proposition 3.3 makes these exactly the fair solution.
@@ -99,9 +101,41 @@ int sfairsc_graph_create(sfairsc_graph_t* out, int64_t n, int64_t nnz,
 /* Release every device buffer of the handle (synchronises the device). */
 void sfairsc_graph_destroy(sfairsc_graph_t g);
 
+/*
+ * Replace the handle's constraint by a general matrix F (n x m): the fair
+ * problem becomes min tr(H^T L H) under F^T H = 0 (eq. normal-prob-fair
+ * with any F), as in the paper's random-Laplacian workload, whose F is a
+ * random placeholder (Section 5), and in overlapping groups (Section 6).
+ * The group labels given at creation are no longer used by any solve.
+ *
+ * F          device double, column-major n x m, leading dimension ldf >= n;
+ *            read during the call only.  1 <= m <= 32.
+ * center     1: use F_0 = F - 1 mu^T with mu the column means (for 0/1
+ *            memberships G, possibly overlapping, this is Lemma 2.1's
+ *            G - 1 z^T with every column kept); 0: use F as given.
+ * rank_tol   singular values of C = D^{-1/2} F (normalized) or C = F below
+ *            rank_tol times the largest are treated as zero, the
+ *            rank-revealing step for a rank-deficient F; 0 selects 1e-6.
+ *            Must lie in [1e-7, 1) (the rank is read from the Gram matrix).
+ * rank       host int32 (may be NULL): the rank r kept.  Solves then allow
+ *            k <= n - r and sfairsc_graph_query reports r.
+ *
+ * The handle keeps an orthonormal basis Q (n x r, padded to 4, 8, 16 or 32
+ * columns) of range(C); the operator applies P = I - Q Q^T.  Batched solves
+ * hand such handles to the single-graph solver.  Synchronises `stream`.
+ * Errors: E_ARG (sizes, rank_tol, F zero or non-finite, r >= n; the handle
+ * then has no general constraint, its group constraint applies again),
+ * E_NOMEM, E_HIP.
+ */
+int sfairsc_graph_set_constraint(sfairsc_graph_t g, const double* F,
+                                 int64_t ldf, int32_t m, int32_t center,
+                                 double rank_tol, int32_t* rank,
+                                 hipStream_t stream);
+
 typedef struct sfairsc_graph_stats {
     int64_t n, nnz;
-    int32_t h, normalized, value_dtype, reserved;
+    int32_t h, normalized, value_dtype;
+    int32_t constraint_rank; /* h - 1, or the rank of a general F          */
     double sigma;      /* ||L_n||_1 (normalized) or ||L||_1 = 2 max_i d_i   */
     double min_degree, max_degree;
 } sfairsc_graph_stats;

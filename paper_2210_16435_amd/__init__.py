@@ -151,7 +151,27 @@ class Graph:
     def stats(self) -> dict:
         st = _lib.GraphStats()
         _lib.check(_lib.lib().sfairsc_graph_query(self._h, ctypes.byref(st)))
-        return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def set_constraint(self, F, center: bool = False, rank_tol: float = 0.0, stream=None) -> int:
+        """Constrain by a general n x m matrix F (F^T H = 0) instead of the
+        group labels; center=True subtracts the column means first (0/1
+        memberships, possibly overlapping).  Returns the rank kept."""
+        Ft = torch.as_tensor(F).to(self.device, torch.float64)
+        if Ft.dim() == 1:
+            Ft = Ft[:, None]
+        if Ft.shape[0] != self.n:
+            raise ValueError(f"F has {Ft.shape[0]} rows, the graph {self.n} vertices")
+        Fc = Ft.t().contiguous()  # column-major storage for the library
+        rank = ctypes.c_int32(0)
+        _lib.check(
+            _lib.lib().sfairsc_graph_set_constraint(
+                self._h, _ptr(Fc), self.n, int(Fc.shape[0]), int(bool(center)), float(rank_tol), ctypes.byref(rank),
+                _stream(stream)
+            )
+        )
+        self.constraint_rank = int(rank.value)
+        return self.constraint_rank
 
     @property
     def sigma(self) -> float:

@@ -52,7 +52,7 @@ class GraphStats(ctypes.Structure):
         ("h", ctypes.c_int32),
         ("normalized", ctypes.c_int32),
         ("value_dtype", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("constraint_rank", ctypes.c_int32),
         ("sigma", ctypes.c_double),
         ("min_degree", ctypes.c_double),
         ("max_degree", ctypes.c_double),
@@ -146,6 +146,7 @@ PROTOTYPES = {
     "sfairsc_graph_create": (_int, [ctypes.POINTER(_vp), _i64, _i64, _vp, _vp, _vp, _int, _vp, _i32, _int, _vp]),
     "sfairsc_graph_destroy": (None, [_vp]),
     "sfairsc_graph_query": (_int, [_vp, ctypes.POINTER(GraphStats)]),
+    "sfairsc_graph_set_constraint": (_int, [_vp, _vp, _i64, _i32, _i32, _dbl, ctypes.POINTER(_i32), _vp]),
     "sfairsc_apply_operator": (_int, [_vp, _vp, _vp, _i32, _int, _dbl, _vp]),
     "sfairsc_spmm": (_int, [_vp, _vp, _vp, _i32, _int, _vp]),
     "sfairsc_eigs_opts_init": (None, [ctypes.POINTER(EigsOpts)]),

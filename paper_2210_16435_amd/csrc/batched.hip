@@ -1955,7 +1955,7 @@ static int check_batch_args(const sfairsc_graph_t* graphs, int32_t count, const 
         if (graphs[i]->device != dev)
             return set_error(SFAIRSC_E_ARG, "graph %d lives on device %d, current device is %d", i, graphs[i]->device,
                              dev);
-        const int64_t kmax = std::min<int64_t>(kMaxK, graphs[i]->n - graphs[i]->h + 1);
+        const int64_t kmax = std::min<int64_t>(kMaxK, free_dim(graphs[i]));
         if (k[i] < 1 || k[i] > kmax) return set_error(SFAIRSC_E_ARG, "k[%d] = %d outside [1, %lld]", i, k[i], (long long)kmax);
     }
     return SFAIRSC_OK;
@@ -2003,7 +2003,8 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
         c.rows = std::min(c.rows, max_rows(c.b, dbl));
         cfgs[i] = c;
         const int ld = std::max(c.ncv + c.b, round_up(k[i], 16));
-        const bool ok = cfg_valid(c, k[i]) && k[i] <= KMAXB && g->n >= 2 * (int64_t)ld;
+        // a general constraint matrix has no group form: single-graph solver
+        const bool ok = cfg_valid(c, k[i]) && k[i] <= KMAXB && g->n >= 2 * (int64_t)ld && !g->qbas;
         if (!ok) {
             if (o.block_width || o.max_basis) {
                 if (!cfg_valid(c, k[i]) || k[i] > KMAXB)
@@ -2110,7 +2111,7 @@ extern "C" int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count, co
     std::map<Key, std::vector<int>> reps;
     for (int i = 0; i < count; ++i) {
         sfairsc_graph* g = graphs[i];
-        if (k[i] > KMAXB) continue;
+        if (k[i] > KMAXB || g->qbas) continue;
         auto& v = reps[key_of(g->n, g->nnz, k[i], dbl, g->normalized)];
         if ((int)v.size() < per_bucket) v.push_back(i);
     }

@@ -1151,7 +1151,7 @@ extern "C" void sfairsc_eigs_opts_init(sfairsc_eigs_opts* o) {
 extern "C" int sfairsc_eigs(sfairsc_graph_t g, int32_t k, double tol, int precision, const sfairsc_eigs_opts* opts,
                             double* eigvals, double* H, sfairsc_eigs_info* info, hipStream_t stream) {
     if (!g || !eigvals || !H) return set_error(SFAIRSC_E_ARG, "NULL argument");
-    if (k < 1 || k > kMaxK || k > g->n - g->h + 1) return set_error(SFAIRSC_E_ARG, "k=%d out of range", k);
+    if (k < 1 || k > kMaxK || k > free_dim(g)) return set_error(SFAIRSC_E_ARG, "k=%d out of range", k);
     if (!(tol > 0.0) || !(tol < 1.0)) return set_error(SFAIRSC_E_ARG, "tol must lie in (0, 1)");
     if (precision != SFAIRSC_PREC_FP64 && precision != SFAIRSC_PREC_MIXED)
         return set_error(SFAIRSC_E_ARG, "unknown precision %d", precision);

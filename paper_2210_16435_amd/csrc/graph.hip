@@ -253,6 +253,10 @@ static void free_graph(sfairsc_graph* g) {
     k.part.release();
     k.misc.release();
     g->gw.hrow.release();
+    (void)hipFree(g->qbas);
+    g->cw.part.release();
+    g->cw.small.release();
+    g->cw.cbuf.release();
     delete g;
 }
 
@@ -473,7 +477,7 @@ extern "C" int sfairsc_graph_query(sfairsc_graph_t g, sfairsc_graph_stats* out) 
     out->h = g->h;
     out->normalized = g->normalized;
     out->value_dtype = g->value_dtype;
-    out->reserved = 0;
+    out->constraint_rank = g->qbas ? g->qrank : g->h - 1;
     out->sigma = g->sigma;
     out->min_degree = g->dmin;
     out->max_degree = g->dmax;

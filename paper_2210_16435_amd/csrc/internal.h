@@ -88,6 +88,14 @@ struct GradWork {
     DevBuf hrow;  // H staged row-major for the backward kernel
 };
 
+// Workspace of a general constraint matrix (basis Q of range(C)).
+struct ConWork {
+    DevBuf part;   // per-block partial sums, kConMaxBlocks x 32 x 32 doubles
+    DevBuf small;  // reduced sums and small coefficient matrices
+    DevBuf cbuf;   // C during set-up, n x qld
+};
+constexpr int kConMaxBlocks = 256;
+
 }  // namespace sfairsc
 
 struct sfairsc_graph {
@@ -109,13 +117,23 @@ struct sfairsc_graph {
     std::vector<int64_t> count; // group sizes
     std::vector<double> p;      // group fractions |V_s| / n
     std::vector<double> ginv;   // (C^T C)^{-1}, (h-1) x (h-1)
+    // General constraint (replaces the group form when set): Q, row-major
+    // n x qld with qld in {4, 8, 16, 32}, orthonormal columns spanning
+    // range(C), columns qrank..qld-1 zero.
+    double* qbas = nullptr;
+    int qrank = 0, qld = 0;
     sfairsc::OpWork op;
     sfairsc::EigWork eig;
     sfairsc::KmWork km;
     sfairsc::GradWork gw;
+    sfairsc::ConWork cw;
 };
 
 namespace sfairsc {
+
+// Dimension of the constrained subspace: n minus the number of independent
+// constraints (h - 1 groups, or the rank of a general F).
+inline int64_t free_dim(const sfairsc_graph* g) { return g->qbas ? g->n - g->qrank : g->n - g->h + 1; }
 
 // Apply Y = L^sigma X for X, Y in row-major blocks with leading dimensions.
 // b <= 32.  mixed = float sparse product.  If timing events are given, the
@@ -128,6 +146,19 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy,
 // X <- P X = X - C (C^T C)^{-1} C^T X in place (X double, ldx, b <= 32).
 int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
 
+// General constraint (g->qbas set): the projection steps of the operator
+// with P = I - Q Q^T.
+//   gen_project_in:  S = Q^T X (kept in the handle's workspace) and
+//                    X' = X - Q S written compact (stride BW) as float or double.
+//   gen_correct:     Y = T - Q (Q^T T - sigma S), T compact stride BW (float
+//                    or double), Y double with leading dimension ldy.
+//   gen_project:     X <- X - Q Q^T X in place.
+int gen_project_in(sfairsc_graph* g, const double* X, int ldx, int b, int BW, bool to_float, void* Xp,
+                   hipStream_t s, const int* skip);
+int gen_correct(sfairsc_graph* g, const void* T, bool t_float, int BW, int b, double sigma, double* Y, int ldy,
+                hipStream_t s, const int* skip);
+int gen_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
+
 // The operator up to (not including) the output deflation: projection, SpMM
 // with its C^T T epilogue and the deflation table.  Y = T - C R_out (row i:
 // T_i - c_i rtab[g_i]) is left to the caller (fused into its next pass).
@@ -135,7 +166,7 @@ struct OpOut {
     const void* t;       // n x BW compact, float if is_float else double
     bool is_float;
     int BW;
-    const double* rtab;  // [h][32]
+    const double* rtab;  // [h][32]; nullptr: t already holds Y (general constraint)
 };
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out);

@@ -423,10 +423,40 @@ static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* 
 #undef SF_SPMM_CASE
 }
 
+// The operator with a general constraint (g->qbas): X' = X - Q Q^T X
+// compact, the sparse product without the group epilogue, then
+// Y = T - Q (Q^T T - sigma Q^T X) into Y (double, leading dimension ldy).
+static int gen_apply(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
+                     hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, double* Y, int ldy) {
+    OpWork& w = g->op;
+    const int BW = pad_width(b);
+    SF_TRY(gen_project_in(g, X, ldx, b, BW, mixed != 0, w.xp.p, s, skip));
+    if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+    if (mixed)
+        launch_spmm<float>(g, BW, w.xp.as<float>(), w.t.as<float>(), g->val32, g->diag32, b, nullptr, w.nblk_spmm,
+                           s, skip);
+    else
+        launch_spmm<double>(g, BW, w.xp.as<double>(), w.t.as<double>(), g->val64, g->diag64, b, nullptr,
+                            w.nblk_spmm, s, skip);
+    if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+    SF_HIP(hipGetLastError());
+    return gen_correct(g, w.t.p, mixed != 0, BW, b, sigma, Y, ldy, s, skip);
+}
+
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
     SF_TRY(ensure_op(g));
+    if (g->qbas) {
+        // Y lands in the (no longer needed) projected-input buffer, in double
+        const int BW = pad_width(b);
+        SF_TRY(gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, g->op.xp.as<double>(), BW));
+        out->t = g->op.xp.p;
+        out->is_float = false;
+        out->BW = BW;
+        out->rtab = nullptr;
+        return SFAIRSC_OK;
+    }
     OpWork& w = g->op;
     const int BW = pad_width(b);
     const int64_t n = g->n;
@@ -468,6 +498,11 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
 
 int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
              hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
+    if (g->qbas) {
+        if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+        SF_TRY(ensure_op(g));
+        return gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, Y, ldy);
+    }
     OpOut o;
     SF_TRY(op_apply_t(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, &o));
     const int64_t n = g->n;
@@ -497,6 +532,7 @@ __global__ __launch_bounds__(256) void k_proj_inplace(double* __restrict__ X, in
 
 int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    if (g->qbas) return gen_project(g, X, ldx, b, s);
     SF_TRY(ensure_op(g));
     OpWork& w = g->op;
     double* Rin = w.small.as<double>();

@@ -18,7 +18,7 @@ struct OrthoArgs {
     int BW;
     const int32_t* grp;
     const double* cs;   // d^{-1/2} or nullptr
-    const double* rtab; // deflation table [h][32]
+    const double* rtab; // deflation table [h][32]; nullptr: t already holds Y
     double* T;          // projected matrix (device, ldt x ldt)
     int ldt;
     double thresh;      // Cholesky pivot threshold (rank deficiency)

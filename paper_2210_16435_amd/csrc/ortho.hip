@@ -112,14 +112,16 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
             const int64_t row = tile * 16 + q * 4 + lk;
             const bool rv = row < n;
             double y[BJ];
-            const double c = (rv && cs) ? cs[row] : 1.0;
-            const int gi = rv ? grp[row] : 0;
+            // Rtab == nullptr: T already holds Y (general constraint)
+            const double c = (rv && cs && Rtab) ? cs[row] : 1.0;
+            const int gi = (rv && Rtab) ? grp[row] : 0;
 #pragma unroll
             for (int jt = 0; jt < BJ; ++jt) {
                 const int col = jt * 16 + li;
                 double v = 0.0;
                 if (rv && col < b) {
-                    v = (double)T[row * BW + col] - c * Rtab[gi * 32 + col];
+                    v = (double)T[row * BW + col];
+                    if (Rtab) v -= c * Rtab[gi * 32 + col];
                     V[row * ld + cv + col] = v;
                 }
                 y[jt] = v;
