@@ -54,6 +54,11 @@ def main():
         help="only run the 256-graph batched launch three times with the built-in configurations (for profilers)",
     )
     ap.add_argument(
+        "--random-laplacian-profile",
+        action="store_true",
+        help="only run the n = 10,000 random-Laplacian fair solve (h = 5, k = 10) three times (for profilers)",
+    )
+    ap.add_argument(
         "--copy-calibration",
         action="store_true",
         help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
@@ -87,6 +92,24 @@ def main():
             launches.append(round(rs[0].info["batch_ms"], 2))
         torch.cuda.synchronize()
         print(json.dumps({"batched_launch_ms": launches, "handed_off": sum(r.info["path"] for r in rs)}))
+        return
+    if args.random_laplacian_profile:
+        import torch
+
+        import paper_2210_16435_amd as sf
+        from sfairsc_inputs import random_laplacian
+
+        g, F = random_laplacian(10000, 0.01, 4, seed=10041)
+        G = sf.Graph.from_msbm(g, True)
+        G.set_constraint(torch.from_numpy(F))
+        H = torch.empty((10, g.n), dtype=torch.float64, device="cuda")
+        ms = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = G.eigs(10, tol=1e-8, precision="mixed", H_out=H)
+            torch.cuda.synchronize()
+            ms.append(round((time.perf_counter() - t0) * 1e3, 2))
+        print(json.dumps({"random_laplacian_solve_ms": ms, "block_steps": r.info["block_steps"], "nnz": g.nnz}))
         return
     if args.gpus != 1:
         print(
@@ -183,6 +206,7 @@ def main():
         torch.cuda.empty_cache()
         extra = {
             "fair_vs_sc": bench_fair_vs_sc(sf, torch, g, k, tol, normalized, b, results, args.steps, args.warmup),
+            "random_laplacian": bench_random_laplacian(sf, torch),
             "batched_256": bench_batched(sf, torch),
             "backward_200k": bench_backward(sf, torch),
             "mixed_2m": bench_2m(sf, torch),
@@ -279,6 +303,46 @@ def bench_fair_vs_sc(sf, torch, g, k, tol, normalized, b, fair, steps, warmup):
     del G, H
     torch.cuda.empty_cache()
     return out
+
+
+def bench_random_laplacian(sf, torch):
+    """The paper's Experiment 4: s-FairSC (Alg. 3) against SC (Alg. 1) on the
+    random-Laplacian workload (random sparse symmetric W of density 0.01,
+    a uniform random placeholder F with h - 1 = 4 columns), n in {5000,
+    10000}, k in {5, 8, 10}; normalized variant, tol 1e-8, float sparse
+    products.  The fair solves use the general-F projection."""
+    from sfairsc_inputs import random_laplacian
+
+    rows = []
+    for n in (5000, 10000):
+        g, F = random_laplacian(n, 0.01, 4, seed=41 + n)
+        Gf = sf.Graph.from_msbm(g, True)
+        Gf.set_constraint(torch.from_numpy(F))
+        Gs = sf.Graph.from_msbm(g, True)  # one group: plain SC
+        for k in (5, 8, 10):
+            H = torch.empty((k, n), dtype=torch.float64, device="cuda")
+            row = {"n": n, "nnz": g.nnz, "k": k}
+            for name, G in (("fair", Gf), ("sc", Gs)):
+                G.eigs(k, tol=1e-8, precision="mixed", H_out=H)
+                torch.cuda.synchronize()
+                reps = 2
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    r = G.eigs(k, tol=1e-8, precision="mixed", H_out=H)
+                torch.cuda.synchronize()
+                row[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3 / reps, 3)
+                row[f"{name}_block_steps"] = r.info["block_steps"]
+            row["fair_over_sc"] = round(row["fair_ms"] / row["sc_ms"], 3)
+            rows.append(row)
+            _log(f"random laplacian: {row}")
+        del Gf, Gs
+        torch.cuda.empty_cache()
+    ratios = np.array([r["fair_over_sc"] for r in rows])
+    return {
+        "workload": "random Laplacian, density 0.01, h = 5 (random placeholder F), normalized, tol 1e-8, mixed",
+        "runs": rows,
+        "fair_over_sc_geomean": round(float(np.exp(np.log(ratios).mean())), 3),
+    }
 
 
 def bench_batched(sf, torch):

@@ -141,3 +141,31 @@ def test_operator_propositions(normalized):
     a = oracle.apply_deflated_operator(Wg, gg.groups, 3, normalized, s2, Xr)
     b = oracle.apply_deflated_operator_general(Wg, oracle.fairness_matrix(gg.groups, 3), normalized, s2, Xr)
     assert np.allclose(a, b, atol=1e-11 * s2 * np.abs(Xr).max())
+
+
+@pytest.mark.parametrize("normalized", [False, True])
+def test_gradient_formulas_hold_for_a_general_F(normalized):
+    # F does not depend on W, so the envelope argument is unchanged
+    g, F = random_laplacian(70, 0.15, 3, seed=9)
+    n, k = 70, 4
+    W = g.to_scipy()
+    lam, H, _ = oracle.fair_eigs_dense_general(W, F, k + 1, normalized)
+    assert (lam[k] - lam[k - 1]) / lam[k] > 1e-3
+    if normalized:
+        grad = oracle.eigsum_edge_gradient_normalized(g.rowptr, g.col, H[:, :k], lam[:k])
+    else:
+        grad = oracle.eigsum_edge_gradient(g.rowptr, g.col, H[:, :k])
+    rows = g.row_index()
+    rng = np.random.default_rng(4)
+    step = 1e-6
+    for e in rng.choice(np.flatnonzero(rows < g.col), 8, replace=False):
+        i, j = int(rows[e]), int(g.col[e])
+        vals = []
+        for sgn in (1.0, -1.0):
+            Wp = W.copy().tolil()
+            Wp[i, j] += sgn * step
+            Wp[j, i] += sgn * step
+            vals.append(oracle.fair_eigs_dense_general(Wp.tocsr(), F, k, normalized)[0].sum())
+        fd = (vals[0] - vals[1]) / (2 * step)
+        mate = np.flatnonzero((rows == j) & (g.col == i))[0]
+        assert grad[e] + grad[mate] == pytest.approx(fd, rel=1e-5, abs=1e-8)
