@@ -49,3 +49,4 @@ from .general_f import (  # noqa: F401
     fair_eigs_implicit_general,
     apply_deflated_operator_general,
 )
+from .lsqr import lsqr, project_lsqr, membership_constraint_matrix  # noqa: F401
