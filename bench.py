@@ -59,6 +59,11 @@ def main():
         help="only run the n = 10,000 random-Laplacian fair solve (h = 5, k = 10) three times (for profilers)",
     )
     ap.add_argument(
+        "--lsqr-profile",
+        action="store_true",
+        help="only run the n = 50,000 headline graph with one-hot memberships through LSQR twice (for profilers)",
+    )
+    ap.add_argument(
         "--copy-calibration",
         action="store_true",
         help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
@@ -92,6 +97,27 @@ def main():
             launches.append(round(rs[0].info["batch_ms"], 2))
         torch.cuda.synchronize()
         print(json.dumps({"batched_launch_ms": launches, "handed_off": sum(r.info["path"] for r in rs)}))
+        return
+    if args.lsqr_profile:
+        import scipy.sparse as sp
+        import torch
+
+        import paper_2210_16435_amd as sf
+        from sfairsc_inputs import WORKLOADS, workload
+
+        name = "msbm-50k-h5-normalized"
+        p = WORKLOADS[name][1]
+        g = workload(name, relabel_seed=2)
+        G = sf.Graph.from_msbm(g, True)
+        G.set_memberships(sp.csr_matrix(np.eye(g.h)[g.groups]), center=True, inner_tol=1e-12)
+        H = torch.empty((p["k"], g.n), dtype=torch.float64, device="cuda")
+        ms = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            r = G.eigs(p["k"], tol=p["tol"], precision="mixed", block_width=p["block"], H_out=H)
+            torch.cuda.synchronize()
+            ms.append(round((time.perf_counter() - t0) * 1e3, 2))
+        print(json.dumps({"lsqr_solve_ms": ms, "block_steps": r.info["block_steps"], "lsqr": G.lsqr_stats()}))
         return
     if args.random_laplacian_profile:
         import torch
@@ -207,6 +233,7 @@ def main():
         extra = {
             "fair_vs_sc": bench_fair_vs_sc(sf, torch, g, k, tol, normalized, b, results, args.steps, args.warmup),
             "random_laplacian": bench_random_laplacian(sf, torch),
+            "lsqr_memberships": bench_lsqr(sf, torch, g, k, tol, b),
             "batched_256": bench_batched(sf, torch),
             "backward_200k": bench_backward(sf, torch),
             "mixed_2m": bench_2m(sf, torch),
@@ -343,6 +370,62 @@ def bench_random_laplacian(sf, torch):
         "runs": rows,
         "fair_over_sc_geomean": round(float(np.exp(np.log(ratios).mean())), 3),
     }
+
+
+def bench_lsqr(sf, torch, g, k, tol, b):
+    """The inexact projection by LSQR (inner-outer iteration): (a) the
+    headline graph with its groups given as one-hot memberships, against the
+    closed-form group path on the same graph, k, tol and block width;
+    (b) many overlapping groups (n = 100,000, degree 20, m = 2,000 groups,
+    20% of vertices in two), k = 10, tol 1e-8, where only LSQR applies."""
+    import scipy.sparse as sp
+
+    from sfairsc_inputs import overlapping_memberships, random_sparse_graph
+
+    out = {}
+    H = torch.empty((k, g.n), dtype=torch.float64, device="cuda")
+    Gl = sf.Graph.from_msbm(g, True)
+    Gl.set_memberships(sp.csr_matrix(np.eye(g.h)[g.groups]), center=True, inner_tol=1e-12)
+    Gg = sf.Graph.from_msbm(g, True)
+    row = {}
+    for name, G in (("lsqr", Gl), ("closed_form", Gg)):
+        G.eigs(k, tol=tol, precision="mixed", block_width=b, H_out=H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = G.eigs(k, tol=tol, precision="mixed", block_width=b, H_out=H)
+        torch.cuda.synchronize()
+        row[f"{name}_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        row[f"{name}_block_steps"] = r.info["block_steps"]
+    st = Gl.lsqr_stats()
+    row["lsqr_steps_per_projection"] = round(st["steps"] / max(st["solves"], 1), 2)
+    row["lsqr_max_steps"] = st["max_steps"]
+    row["lsqr_over_closed_form"] = round(row["lsqr_ms"] / row["closed_form_ms"], 2)
+    out["headline_graph_one_hot"] = row
+    del Gl, Gg, H
+    gm = random_sparse_graph(100000, 20, seed=77, h=2)
+    M = overlapping_memberships(gm.n, 2000, 0.2, seed=78)
+    G = sf.Graph.from_msbm(gm, True)
+    G.set_memberships(sp.csr_matrix(M), center=True, inner_tol=1e-12)
+    H = torch.empty((10, gm.n), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    r = G.eigs(10, tol=1e-8, precision="mixed", H_out=H)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    st = G.lsqr_stats()
+    out["many_groups"] = {
+        "workload": "n = 100,000, degree 20, m = 2,000 overlapping groups, normalized, k = 10, tol 1e-8, mixed",
+        "nnz": gm.nnz,
+        "ms": round(ms, 2),
+        "block_steps": r.info["block_steps"],
+        "max_rel_residual": r.info["max_rel_residual"],
+        "lsqr_solves": st["solves"],
+        "lsqr_steps_per_projection": round(st["steps"] / max(st["solves"], 1), 2),
+        "lsqr_unconverged": st["unconverged"],
+    }
+    _log(f"lsqr: {out}")
+    del G, H
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(sf, torch):

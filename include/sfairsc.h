@@ -132,6 +132,50 @@ int sfairsc_graph_set_constraint(sfairsc_graph_t g, const double* F,
                                  double rank_tol, int32_t* rank,
                                  hipStream_t stream);
 
+/*
+ * Replace the handle's constraint by a sparse 0/1 membership matrix G
+ * (n x m, a vertex may belong to several groups, m up to 2^20) whose
+ * projection is computed iteratively: P w = w - C x with x from LSQR on
+ * min ||C x - w||_2 (Section 3.4 (ii): an iterative least-squares solver
+ * inside the eigensolver, an inner-outer iteration), where
+ * C = D^{-1/2} (G - 1 z^T) (normalized) or G - 1 z^T, z = G^T 1 / n
+ * (center = 1, Lemma 2.1's centring with every column kept) or z = 0.
+ * For many groups this replaces both the closed form of the group path
+ * (h <= 32) and the dense basis of sfairsc_graph_set_constraint (m <= 32).
+ *
+ * rowptr, colidx  device int32 CSR of G: rowptr[n+1] (rowptr[0] = 0,
+ *            non-decreasing), colidx[nnz] in [0, m), strictly increasing
+ *            within a row.  Read during the call only (copied to the host
+ *            to build the member lists).
+ * inner_tol  LSQR stops a column when its estimate of
+ *            ||C^T r|| / (||C||_est ||r||) falls to inner_tol; 0 selects
+ *            1e-12.  The projection error is then about
+ *            inner_tol * cond(C) * ||r||: the eigensolver's tolerance
+ *            should stay above it.  Must lie in [1e-15, 1).
+ * max_inner  LSQR steps per solve (0 selects 200), at most 1e5.
+ *
+ * Each projection is one cooperative launch (every step's reductions in a
+ * fixed order).  Solves allow k <= n - m (m bounds the rank of C from
+ * above; LSQR needs no rank).  sfairsc_graph_query reports m.  Batched
+ * solves hand such handles to the single-graph solver.  Synchronises
+ * `stream`.  Errors: E_ARG (sizes, CSR structure, tolerances; the handle
+ * then has no membership constraint, its group constraint applies again),
+ * E_NOMEM, E_HIP.
+ */
+int sfairsc_graph_set_memberships(sfairsc_graph_t g, int32_t m,
+                                  const int32_t* rowptr, const int32_t* colidx,
+                                  int32_t center, double inner_tol,
+                                  int32_t max_inner, hipStream_t stream);
+
+/*
+ * LSQR counters of a handle with a membership constraint, accumulated over
+ * every projection since the constraint was set: out[0] solves (one per
+ * projection of a block), out[1] LSQR steps in total, out[2] the most steps
+ * of one solve, out[3] columns that reached max_inner unconverged.
+ * Synchronises `stream`.  Errors: E_ARG (no membership constraint), E_HIP.
+ */
+int sfairsc_lsqr_stats(sfairsc_graph_t g, int64_t* out, hipStream_t stream);
+
 typedef struct sfairsc_graph_stats {
     int64_t n, nnz;
     int32_t h, normalized, value_dtype;

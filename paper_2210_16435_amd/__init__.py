@@ -173,6 +173,32 @@ class Graph:
         self.constraint_rank = int(rank.value)
         return self.constraint_rank
 
+    def set_memberships(self, G, center: bool = True, inner_tol: float = 0.0, max_inner: int = 0, stream=None):
+        """Constrain by a sparse 0/1 membership matrix G (scipy sparse or
+        dense, n x m; overlapping groups allowed) with the projection
+        computed by LSQR inside the eigensolver."""
+        import scipy.sparse as sp
+
+        Gc = sp.csr_matrix(G)
+        Gc.sort_indices()
+        if Gc.shape[0] != self.n:
+            raise ValueError(f"G has {Gc.shape[0]} rows, the graph {self.n} vertices")
+        rp = torch.from_numpy(Gc.indptr.astype(np.int32)).to(self.device)
+        ci = torch.from_numpy(Gc.indices.astype(np.int32)).to(self.device)
+        _lib.check(
+            _lib.lib().sfairsc_graph_set_memberships(
+                self._h, int(Gc.shape[1]), _ptr(rp), _ptr(ci), int(bool(center)), float(inner_tol), int(max_inner),
+                _stream(stream)
+            )
+        )
+
+    def lsqr_stats(self, stream=None) -> dict:
+        """LSQR counters of a membership constraint (solves, steps, max
+        steps of one solve, unconverged columns)."""
+        out = (ctypes.c_int64 * 4)()
+        _lib.check(_lib.lib().sfairsc_lsqr_stats(self._h, out, _stream(stream)))
+        return {"solves": out[0], "steps": out[1], "max_steps": out[2], "unconverged": out[3]}
+
     @property
     def sigma(self) -> float:
         return self.stats()["sigma"]

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfairsc.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["graph.hip", "operator.hip", "general.hip", "ortho.hip", "eigs.hip", "kmeans.hip", "backward.hip",
+HIP_SOURCES = ["graph.hip", "operator.hip", "general.hip", "lsqr.hip", "ortho.hip", "eigs.hip", "kmeans.hip", "backward.hip",
                "batched.hip"]
 CXX_SOURCES = ["symeig.cpp"]
 

@@ -2004,7 +2004,7 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
         cfgs[i] = c;
         const int ld = std::max(c.ncv + c.b, round_up(k[i], 16));
         // a general constraint matrix has no group form: single-graph solver
-        const bool ok = cfg_valid(c, k[i]) && k[i] <= KMAXB && g->n >= 2 * (int64_t)ld && !g->qbas;
+        const bool ok = cfg_valid(c, k[i]) && k[i] <= KMAXB && g->n >= 2 * (int64_t)ld && !g->qbas && !g->memb;
         if (!ok) {
             if (o.block_width || o.max_basis) {
                 if (!cfg_valid(c, k[i]) || k[i] > KMAXB)
@@ -2111,7 +2111,7 @@ extern "C" int sfairsc_autotune(const sfairsc_graph_t* graphs, int32_t count, co
     std::map<Key, std::vector<int>> reps;
     for (int i = 0; i < count; ++i) {
         sfairsc_graph* g = graphs[i];
-        if (k[i] > KMAXB || g->qbas) continue;
+        if (k[i] > KMAXB || g->qbas || g->memb) continue;
         auto& v = reps[key_of(g->n, g->nnz, k[i], dbl, g->normalized)];
         if ((int)v.size() < per_bucket) v.push_back(i);
     }

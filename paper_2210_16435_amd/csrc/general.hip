@@ -448,6 +448,8 @@ extern "C" int sfairsc_graph_set_constraint(sfairsc_graph_t g, const double* F, 
     if (!(rank_tol >= 1e-7 && rank_tol < 1.0))
         return set_error(SFAIRSC_E_ARG, "rank_tol=%g outside [1e-7, 1)", rank_tol);
     int r = 0;
+    (void)hipStreamSynchronize(stream);
+    free_memb(g);
     const int st = set_constraint_impl(g, F, ldf, m, center, rank_tol, &r, stream);
     if (st != SFAIRSC_OK) {
         (void)hipStreamSynchronize(stream);

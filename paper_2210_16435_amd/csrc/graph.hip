@@ -254,6 +254,7 @@ static void free_graph(sfairsc_graph* g) {
     k.misc.release();
     g->gw.hrow.release();
     (void)hipFree(g->qbas);
+    free_memb(g);
     g->cw.part.release();
     g->cw.small.release();
     g->cw.cbuf.release();
@@ -477,7 +478,7 @@ extern "C" int sfairsc_graph_query(sfairsc_graph_t g, sfairsc_graph_stats* out) 
     out->h = g->h;
     out->normalized = g->normalized;
     out->value_dtype = g->value_dtype;
-    out->constraint_rank = g->qbas ? g->qrank : g->h - 1;
+    out->constraint_rank = g->memb ? g->memb->m : g->qbas ? g->qrank : g->h - 1;
     out->sigma = g->sigma;
     out->min_degree = g->dmin;
     out->max_degree = g->dmax;

@@ -96,6 +96,24 @@ struct ConWork {
 };
 constexpr int kConMaxBlocks = 256;
 
+// A sparse 0/1 membership matrix G (n x m) whose projection is computed by
+// LSQR (C = D^{-1/2} (G - 1 z^T) or G - 1 z^T).
+constexpr int kMaxMembers = 1 << 20;
+struct Memb {
+    int m = 0, nseg = 0;
+    double inner_tol = 1e-12;
+    int max_inner = 200;
+    int32_t* grow = nullptr;       // [n+1] memberships of each vertex
+    int32_t* gcol = nullptr;       // [nnz_G]
+    int32_t* tcol = nullptr;       // [nnz_G] members of each group, by group
+    int32_t* seg_start = nullptr;  // [nseg+1] segments of tcol (<= 1024 members)
+    int32_t* seg_group = nullptr;  // [nseg]
+    int32_t* gseg = nullptr;       // [m+1] segments of each group
+    double* z = nullptr;           // [m] column means (0 without centring)
+    long long* stats = nullptr;    // solves, steps, max steps, unconverged columns
+    DevBuf work;                   // u, v, d, x, x1, sums, partials
+};
+
 }  // namespace sfairsc
 
 struct sfairsc_graph {
@@ -122,6 +140,8 @@ struct sfairsc_graph {
     // range(C), columns qrank..qld-1 zero.
     double* qbas = nullptr;
     int qrank = 0, qld = 0;
+    // Sparse membership constraint projected by LSQR (replaces both forms).
+    sfairsc::Memb* memb = nullptr;
     sfairsc::OpWork op;
     sfairsc::EigWork eig;
     sfairsc::KmWork km;
@@ -133,7 +153,10 @@ namespace sfairsc {
 
 // Dimension of the constrained subspace: n minus the number of independent
 // constraints (h - 1 groups, or the rank of a general F).
-inline int64_t free_dim(const sfairsc_graph* g) { return g->qbas ? g->n - g->qrank : g->n - g->h + 1; }
+// (a membership matrix counts m, an upper bound of its rank).
+inline int64_t free_dim(const sfairsc_graph* g) {
+    return g->memb ? g->n - g->memb->m : g->qbas ? g->n - g->qrank : g->n - g->h + 1;
+}
 
 // Apply Y = L^sigma X for X, Y in row-major blocks with leading dimensions.
 // b <= 32.  mixed = float sparse product.  If timing events are given, the
@@ -158,6 +181,16 @@ int gen_project_in(sfairsc_graph* g, const double* X, int ldx, int b, int BW, bo
 int gen_correct(sfairsc_graph* g, const void* T, bool t_float, int BW, int b, double sigma, double* Y, int ldy,
                 hipStream_t s, const int* skip);
 int gen_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
+
+// The same three steps for a membership constraint, each one LSQR solve
+// (one cooperative launch).  lsqr_correct uses the solution of the last
+// lsqr_project_in: Y = T - C (x_T - sigma x_X).
+int lsqr_project_in(sfairsc_graph* g, const double* X, int ldx, int b, int BW, bool to_float, void* Xp,
+                    hipStream_t s, const int* skip);
+int lsqr_correct(sfairsc_graph* g, const void* T, bool t_float, int BW, int b, double sigma, double* Y, int ldy,
+                 hipStream_t s, const int* skip);
+int lsqr_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
+void free_memb(sfairsc_graph* g);
 
 // The operator up to (not including) the output deflation: projection, SpMM
 // with its C^T T epilogue and the deflation table.  Y = T - C R_out (row i:

@@ -423,14 +423,19 @@ static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* 
 #undef SF_SPMM_CASE
 }
 
-// The operator with a general constraint (g->qbas): X' = X - Q Q^T X
+// The operator with a general constraint (g->qbas: X' = X - Q Q^T X, or
+// g->memb: the same projections by LSQR).  For g->qbas: X' = X - Q Q^T X
 // compact, the sparse product without the group epilogue, then
 // Y = T - Q (Q^T T - sigma Q^T X) into Y (double, leading dimension ldy).
 static int gen_apply(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                      hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, double* Y, int ldy) {
     OpWork& w = g->op;
     const int BW = pad_width(b);
-    SF_TRY(gen_project_in(g, X, ldx, b, BW, mixed != 0, w.xp.p, s, skip));
+    if (g->memb) {
+        SF_TRY(lsqr_project_in(g, X, ldx, b, BW, mixed != 0, w.xp.p, s, skip));
+    } else {
+        SF_TRY(gen_project_in(g, X, ldx, b, BW, mixed != 0, w.xp.p, s, skip));
+    }
     if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
     if (mixed)
         launch_spmm<float>(g, BW, w.xp.as<float>(), w.t.as<float>(), g->val32, g->diag32, b, nullptr, w.nblk_spmm,
@@ -440,6 +445,7 @@ static int gen_apply(sfairsc_graph* g, const double* X, int ldx, int b, int mixe
                             w.nblk_spmm, s, skip);
     if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
     SF_HIP(hipGetLastError());
+    if (g->memb) return lsqr_correct(g, w.t.p, mixed != 0, BW, b, sigma, Y, ldy, s, skip);
     return gen_correct(g, w.t.p, mixed != 0, BW, b, sigma, Y, ldy, s, skip);
 }
 
@@ -447,7 +453,7 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
     SF_TRY(ensure_op(g));
-    if (g->qbas) {
+    if (g->qbas || g->memb) {
         // Y lands in the (no longer needed) projected-input buffer, in double
         const int BW = pad_width(b);
         SF_TRY(gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, g->op.xp.as<double>(), BW));
@@ -498,7 +504,7 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
 
 int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
              hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
-    if (g->qbas) {
+    if (g->qbas || g->memb) {
         if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
         SF_TRY(ensure_op(g));
         return gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, Y, ldy);
@@ -532,6 +538,7 @@ __global__ __launch_bounds__(256) void k_proj_inplace(double* __restrict__ X, in
 
 int op_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    if (g->memb) return lsqr_project(g, X, ldx, b, s);
     if (g->qbas) return gen_project(g, X, ldx, b, s);
     SF_TRY(ensure_op(g));
     OpWork& w = g->op;
