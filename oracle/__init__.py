@@ -26,6 +26,7 @@ from .fairsc import (  # noqa: F401
     shift_sigma,
     fair_eigs_dense,
     fair_eigs_implicit,
+    fair_eigs_deflated,
     deflated_operator_dense,
     apply_deflated_operator,
     residual_norms,

@@ -271,6 +271,23 @@ def test_tier_b_matches_tier_a(normalized):
     assert oracle.max_principal_angle(HA[:, :5], HB[:, :5], d) < 1e-7
 
 
+@pytest.mark.parametrize("normalized", [False, True])
+def test_cpu_sfairsc_pipeline_matches_tier_a(normalized):
+    # Proposition 3.3: the k smallest eigenpairs of the deflated operator are
+    # the fair ones (the CPU pipeline timed as the method-matched baseline)
+    g = workload("msbm-2k-h2")
+    W = g.to_scipy()
+    k = 6
+    lamA, HA = oracle.fair_eigs_dense(W, g.groups, g.h, k, normalized)
+    lamS, HS = oracle.fair_eigs_deflated(W, g.groups, g.h, k, normalized)
+    scale = oracle.shift_sigma(W, normalized)
+    assert np.allclose(lamA, lamS, rtol=1e-10, atol=1e-11 * scale)
+    d = oracle.degrees(W) if normalized else None
+    assert oracle.max_principal_angle(HA[:, :5], HS[:, :5], d) < 1e-7
+    # the deflated eigenvalue sigma stays out of the k smallest
+    assert lamS.max() < 0.9 * scale
+
+
 # --- planted recovery (Section 4, Experiment 1) ---------------------------------
 
 
