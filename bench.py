@@ -184,14 +184,31 @@ def main():
 
     # SpMM kernel durations (HIP events inside the library, separate runs)
     spmm = {}
+    phase_break = {}
     for prec in precs:
         tot_ms, launches = 0.0, 0
+        acc = {"spmm_ms": 0.0, "operator_ms": 0.0, "ortho_ms": 0.0, "restart_ms": 0.0, "rr_host_ms": 0.0}
         for _ in range(3):
             r = solve(prec, timing=True)
             slot = 1 if prec == "mixed" else 0
             tot_ms += r.info["spmm_ms"][slot]
             launches += r.info["spmm_launches"][slot]
+            acc["spmm_ms"] += sum(r.info["spmm_ms"])
+            acc["operator_ms"] += r.info["operator_ms"]
+            acc["ortho_ms"] += r.info["ortho_ms"]
+            acc["restart_ms"] += r.info["restart_ms"]
+            acc["rr_host_ms"] += r.info["rr_ms"]
         spmm[prec] = (tot_ms / max(launches, 1), launches / 3)
+        # per solve: SpMM, the rest of the operator (projections, C^T T),
+        # CGS2 + Cholesky-QR, restart rotation (GPU event time), host RR
+        ph = {key: v / 3 for key, v in acc.items()}
+        phase_break[prec] = {
+            "spmm_ms": round(ph["spmm_ms"], 3),
+            "projection_ms": round(max(ph["operator_ms"] - ph["spmm_ms"], 0.0), 3),
+            "cgs2_cholqr_ms": round(ph["ortho_ms"], 3),
+            "restart_ms": round(ph["restart_ms"], 3),
+            "rayleigh_ritz_host_ms": round(ph["rr_host_ms"], 3),
+        }
 
     # labels (Alg. 3 step 4) once, for the record
     torch.cuda.synchronize()
@@ -273,6 +290,7 @@ def main():
         "block_steps": r_head.info["block_steps"],
         "graph_setup_ms": round(setup_ms, 3),
         "kmeans_ms": round(kmeans_ms, 3),
+        "phase_breakdown": phase_break,
         "spmm_gbps": round(achieved, 1),
         "roofline": {
             "kernel": f"k_spmm<float,{b}>" if head == "mixed" else f"k_spmm<double,{b}>",

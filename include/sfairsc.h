@@ -249,6 +249,11 @@ typedef struct sfairsc_eigs_info {
                                   FP32-SpMM phase; 0 otherwise             */
     double rr_ms;              /* host time spent in Rayleigh-Ritz (small
                                   dense eigensolves), all phases           */
+    /* time_kernels: summed GPU time between event pairs around the block
+       steps' operator applications (projections, sparse product, C^T T),
+       their orthogonalisation (CGS2 + Cholesky-QR) and the restart
+       rotations; 0 otherwise */
+    double operator_ms, ortho_ms, restart_ms;
 } sfairsc_eigs_info;
 
 /* Fill *opts with the defaults (all automatic, seed 0, certify 1). */

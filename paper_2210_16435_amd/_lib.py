@@ -89,6 +89,9 @@ class EigsInfo(ctypes.Structure):
         ("gap_ratio", ctypes.c_double),
         ("phase1_ms", ctypes.c_double),
         ("rr_ms", ctypes.c_double),
+        ("operator_ms", ctypes.c_double),
+        ("ortho_ms", ctypes.c_double),
+        ("restart_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -105,6 +108,9 @@ class EigsInfo(ctypes.Structure):
             "gap_ratio": self.gap_ratio,
             "phase1_ms": self.phase1_ms,
             "rr_ms": self.rr_ms,
+            "operator_ms": self.operator_ms,
+            "ortho_ms": self.ortho_ms,
+            "restart_ms": self.restart_ms,
         }
 
 

@@ -63,7 +63,8 @@ def build(verbose: bool = False) -> str:
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        jobs.append(["g++", "-O3", "-march=x86-64-v3", "-fPIC", "-std=c++17", "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append(["g++", "-O3", "-march=x86-64-v3", "-fopenmp-simd", "-fPIC", "-std=c++17", "-c",
+                     os.path.join(CSRC, src), "-o", obj])
     workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
     with cf.ThreadPoolExecutor(workers) as ex:
         for out in ex.map(_run, jobs):

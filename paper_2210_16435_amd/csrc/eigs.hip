@@ -433,6 +433,12 @@ struct Solver {
     bool timing = false;
     std::vector<hipEvent_t> evs;
     size_t ev_used = 0;
+    // phase timing: begin/end event pairs, kind 0 operator (projections,
+    // sparse product, C^T T), 1 orthogonalisation (CGS2 + Cholesky-QR),
+    // 2 restart rotation
+    std::vector<hipEvent_t> pev;
+    std::vector<int> pkind;
+    size_t pev_used = 0;
     hipEvent_t ev_rr = nullptr;  // the Rayleigh-Ritz inputs have reached the host
     sfairsc_eigs_info* info = nullptr;
     double thresh = 0.0;
@@ -623,7 +629,9 @@ struct Solver {
             e0 = evs[ev_used++];
             e1 = evs[ev_used++];
         }
+        SF_TRY(phase_mark(0, true));
         SF_TRY(op_apply(g, X, ldx, Y, ldy, bb, mixed, sigma, s, e0, e1, flag));
+        SF_TRY(phase_mark(0, false));
         if (info) {
             info->operator_applies += bb;
             info->spmm_launches[mixed ? 1 : 0] += 1;
@@ -648,7 +656,9 @@ struct Solver {
             e0 = evs[ev_used++];
             e1 = evs[ev_used++];
         }
+        SF_TRY(phase_mark(0, true));
         SF_TRY(op_apply_t(g, V + c, ld, b, mixed, sigma, s, e0, e1, flag, o));
+        SF_TRY(phase_mark(0, false));
         if (info) {
             info->operator_applies += b;
             info->spmm_launches[mixed ? 1 : 0] += 1;
@@ -680,7 +690,9 @@ struct Solver {
         a.rc = Rc;
         a.flag = flag;
         a.stream = s;
-        return ortho_expand(a);
+        SF_TRY(phase_mark(1, true));
+        SF_TRY(ortho_expand(a));
+        return phase_mark(1, false);
     }
 
     int expand(int c) {
@@ -699,7 +711,28 @@ struct Solver {
         return SFAIRSC_OK;
     }
 
-    // Sum the elapsed times of recorded SpMM event pairs (stream synced).
+    int phase_mark(int kind, bool begin) {
+        if (!timing) return SFAIRSC_OK;
+        if (begin) {
+            if (pev_used + 2 > pev.size()) {
+                for (int i = 0; i < 64; ++i) {
+                    hipEvent_t e;
+                    SF_HIP(hipEventCreate(&e));
+                    pev.push_back(e);
+                }
+                pkind.resize(pev.size() / 2);
+            }
+            pkind[pev_used / 2] = kind;
+            SF_HIP(hipEventRecord(pev[pev_used], s));
+        } else {
+            SF_HIP(hipEventRecord(pev[pev_used + 1], s));
+            pev_used += 2;
+        }
+        return SFAIRSC_OK;
+    }
+
+    // Sum the elapsed times of recorded SpMM and phase event pairs (stream
+    // synced).
     int harvest_timing() {
         if (!timing || !info) return SFAIRSC_OK;
         double tot = 0.0;
@@ -710,11 +743,19 @@ struct Solver {
         }
         info->spmm_ms[mixed ? 1 : 0] += tot;
         ev_used = 0;
+        for (size_t i = 0; i + 1 < pev_used; i += 2) {
+            float ms = 0.f;
+            SF_HIP(hipEventElapsedTime(&ms, pev[i], pev[i + 1]));
+            const int kd = pkind[i / 2];
+            (kd == 0 ? info->operator_ms : kd == 1 ? info->ortho_ms : info->restart_ms) += ms;
+        }
+        pev_used = 0;
         return SFAIRSC_OK;
     }
 
     ~Solver() {
         for (auto e : evs) (void)hipEventDestroy(e);
+        for (auto e : pev) (void)hipEventDestroy(e);
         if (ev_rr) (void)hipEventDestroy(ev_rr);
     }
 };
@@ -955,7 +996,9 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         for (int i = 0; i < b; ++i) Qp[off + (size_t)i * b + i] = 1.0;
         SF_TRY(S.upload(S.Q, Qp.data(), Qp.size() * sizeof(double)));
         SF_TRY(S.upload(S.theta, w.data(), p * sizeof(double)));
+        SF_TRY(S.phase_mark(2, true));
         SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
+        SF_TRY(S.phase_mark(2, false));
         std::swap(S.V, S.V2);
         k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.theta);
         SF_HIP(hipGetLastError());

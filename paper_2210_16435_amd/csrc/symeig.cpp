@@ -36,7 +36,8 @@ struct Tridiag {
     std::vector<double> d, e;   // T = tridiag(e, d, e), e[i] couples i and i+1
 };
 
-// Householder reduction (row-major A, n x n, symmetric).
+// Householder reduction (row-major A, n x n, symmetric; only the lower
+// triangle, j <= i, is read and updated).
 void tridiagonalize(int n, const double* A, Tridiag& t) {
     t.n = n;
     t.a.assign(A, A + (size_t)n * n);
@@ -65,23 +66,34 @@ void tridiagonalize(int n, const double* A, Tridiag& t) {
         const double beta = 2.0 / vtv;
         t.e[k] = alpha;
         t.beta[k] = beta;
-        // p = beta B v with B = a[k+1:, k+1:] (symmetric: accumulate rows
-        // scaled by v, a vectorisable axpy);  B <- B - v w^T - w v^T
-        for (int i = 0; i < m; ++i) p[i] = 0.0;
-        for (int j = 0; j < m; ++j) {
-            const double* row = &a[(size_t)(k + 1 + j) * n + k + 1];
-            const double vj = v[j];
-            for (int i = 0; i < m; ++i) p[i] += vj * row[i];
-        }
-        for (int i = 0; i < m; ++i) p[i] *= beta;
-        double ptv = 0.0;
-        for (int i = 0; i < m; ++i) ptv += p[i] * v[i];
-        const double kf = 0.5 * beta * ptv;
-        for (int i = 0; i < m; ++i) w[i] = p[i] - kf * v[i];
+        // p = beta B v with B = a[k+1:, k+1:] from its lower triangle: row i
+        // (entries j < i) contributes a dot product to p_i and an axpy to
+        // p_j, both over contiguous memory;  then B <- B - v w^T - w v^T on
+        // the lower triangle
+        double* __restrict__ pp = p.data();
+        const double* __restrict__ vv = v.data();
+        for (int i = 0; i < m; ++i) pp[i] = 0.0;
         for (int i = 0; i < m; ++i) {
-            double* row = &a[(size_t)(k + 1 + i) * n + k + 1];
-            const double vi = v[i], wi = w[i];
-            for (int j = 0; j < m; ++j) row[j] -= vi * w[j] + wi * v[j];
+            const double* __restrict__ row = &a[(size_t)(k + 1 + i) * n + k + 1];
+            const double vi = vv[i];
+            double s0 = 0.0;
+#pragma omp simd reduction(+ : s0)
+            for (int j = 0; j < i; ++j) {
+                s0 += row[j] * vv[j];
+                pp[j] += vi * row[j];
+            }
+            pp[i] += s0 + row[i] * vi;
+        }
+        for (int i = 0; i < m; ++i) pp[i] *= beta;
+        double ptv = 0.0;
+        for (int i = 0; i < m; ++i) ptv += pp[i] * vv[i];
+        const double kf = 0.5 * beta * ptv;
+        double* __restrict__ ww = w.data();
+        for (int i = 0; i < m; ++i) ww[i] = pp[i] - kf * vv[i];
+        for (int i = 0; i < m; ++i) {
+            double* __restrict__ row = &a[(size_t)(k + 1 + i) * n + k + 1];
+            const double vi = vv[i], wi = ww[i];
+            for (int j = 0; j <= i; ++j) row[j] -= vi * ww[j] + wi * vv[j];
         }
         // keep the reflector, contiguous
         for (int i = 0; i < m; ++i) t.refl[(size_t)k * n + i] = v[i];
@@ -143,8 +155,9 @@ void tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, double* Z
                     early = true;
                     break;
                 }
-                s = f / r;
-                c = g / r;
+                const double ir = 1.0 / r;
+                s = f * ir;
+                c = g * ir;
                 g = d[i + 1] - p;
                 r = (d[i] - g) * s + 2.0 * c * bb;
                 p = s * r;

@@ -19,7 +19,7 @@ def results(tmp_path_factory):
         pytest.skip("no C++ compiler")
     d = tmp_path_factory.mktemp("symeig")
     exe = d / "symeig_check"
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I" + CSRC, os.path.join(ROOT, "tests", "host", "symeig_check.cpp"),
+    subprocess.run(["g++", "-O2", "-fopenmp-simd", "-std=c++17", "-I" + CSRC, os.path.join(ROOT, "tests", "host", "symeig_check.cpp"),
                     os.path.join(CSRC, "symeig.cpp"), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
     return [ln.split() for ln in out if ln.strip()]
