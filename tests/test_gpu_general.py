@@ -218,3 +218,49 @@ def test_bad_constraints_are_rejected_and_the_group_constraint_returns():
     assert np.allclose(res.eigenvalues, ref.eigenvalues, rtol=1e-10)
     assert G.set_constraint(torch.from_numpy(F[:, :5].copy())) == 5
     assert G.stats()["constraint_rank"] == 5
+
+
+def test_widest_constraint_and_padded_leading_dimension():
+    # m = 32 columns (the widest basis), F stored with ldf > n
+    sf = lib()
+    import ctypes
+
+    g, F = random_laplacian(900, 0.03, 32, seed=62)
+    W = g.to_scipy()
+    G = sf.Graph.from_msbm(g, True)
+    ldf = g.n + 7
+    Fp = np.zeros((32, ldf))
+    Fp[:, : g.n] = F.T
+    Fp[:, g.n:] = np.nan  # padding is never read
+    Fd = torch.from_numpy(Fp).cuda()
+    rank = ctypes.c_int32(0)
+    code = sf._lib.lib().sfairsc_graph_set_constraint(G._h, ctypes.c_void_p(Fd.data_ptr()), ldf, 32, 0, 0.0,
+                                                      ctypes.byref(rank), None)
+    assert code == 0 and rank.value == 32
+    X = np.random.default_rng(3).standard_normal((g.n, 8))
+    ref = oracle.apply_deflated_operator_general(W, F, True, G.sigma, X)
+    Y = to_np(G.apply_operator(torch.from_numpy(X)))
+    assert np.abs(Y - ref).max() <= 1e-12 * G.sigma * np.abs(X).max()
+
+
+def test_switching_between_constraint_forms():
+    sf = lib()
+    import scipy.sparse as sp
+
+    g = random_sparse_graph(700, 14, seed=63, h=3)
+    W = g.to_scipy()
+    k = 4
+    G = sf.Graph.from_msbm(g, True)
+    ref = G.eigs(k, tol=1e-10).eigenvalues
+    F = np.random.default_rng(4).random((g.n, 5))
+    assert G.set_constraint(torch.from_numpy(F)) == 5
+    lamF, _, _ = oracle.fair_eigs_dense_general(W, F, k, True)
+    assert eig_parity(G.eigs(k, tol=1e-10).eigenvalues, lamF, 0) <= 1e-9
+    M = overlapping_memberships(g.n, 6, 0.2, seed=5)
+    G.set_memberships(sp.csr_matrix(M), inner_tol=1e-13)
+    assert G.stats()["constraint_rank"] == 6
+    lamM, _, _ = oracle.fair_eigs_dense_general(W, oracle.membership_fairness_matrix(M), k, True)
+    assert eig_parity(G.eigs(k, tol=1e-10).eigenvalues, lamM, 0) <= 1e-9
+    # back to the group matrix of Lemma 2.1 through the dense form
+    assert G.set_constraint(torch.from_numpy(oracle.fairness_matrix(g.groups, 3))) == 2
+    assert eig_parity(G.eigs(k, tol=1e-10).eigenvalues, ref, 0) <= 1e-9

@@ -173,3 +173,35 @@ def test_bad_memberships_are_rejected():
     assert code == sf.E_ARG
     # the group constraint applies again
     assert G.stats()["constraint_rank"] == 1
+
+
+def test_uncentred_memberships_and_an_unused_group():
+    # F = G without centring; group 7 has no member (a zero column of C)
+    sf = lib()
+    g = random_sparse_graph(800, 12, seed=83, h=2)
+    W = g.to_scipy()
+    M = overlapping_memberships(g.n, 7, 0.25, seed=84)
+    M8 = np.concatenate([M, np.zeros((g.n, 1))], axis=1)
+    for normalized in (False, True):
+        G = sf.Graph.from_msbm(g, normalized)
+        G.set_memberships(sp.csr_matrix(M8), center=False, inner_tol=1e-13)
+        X = np.random.default_rng(5).standard_normal((g.n, 4))
+        ref = oracle.apply_deflated_operator_general(W, M8, normalized, G.sigma, X)
+        Y = to_np(G.apply_operator(torch.from_numpy(X)))
+        assert np.abs(Y - ref).max() <= 1e-9 * G.sigma * np.abs(X).max()
+        lam, _, r = oracle.fair_eigs_dense_general(W, M8, 4, normalized)
+        assert r == 7
+        res = G.eigs(4, tol=1e-9)
+        assert eig_parity(res.eigenvalues, lam, 0) <= 1e-8
+
+
+def test_step_cap_is_reported():
+    sf = lib()
+    g = random_sparse_graph(600, 12, seed=85, h=2)
+    M = overlapping_memberships(g.n, 30, 0.3, seed=86)
+    G = sf.Graph.from_msbm(g, False)
+    G.set_memberships(sp.csr_matrix(M), inner_tol=1e-14, max_inner=2)
+    X = torch.from_numpy(np.random.default_rng(6).standard_normal((g.n, 3)))
+    G.apply_operator(X)
+    st = G.lsqr_stats()
+    assert st["solves"] == 2 and st["max_steps"] == 2 and st["unconverged"] > 0
