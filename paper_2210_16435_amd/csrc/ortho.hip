@@ -88,8 +88,10 @@ __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, 
 }
 
 // Pass A.  Y0 from the sparse product T (compact stride BW, type TT) and the
-// deflation table Rtab; partial V[:, 0:cv]^T Y0 (nrt x BJ tiles).
-template <int BJ, class TT>
+// deflation table Rtab; partial V[:, 0:cv]^T Y0 (nrt x BJ tiles).  RT bounds
+// nrt (4, 8 or kMaxRT): the accumulators and the loads in flight are sized by
+// it, so the common small bases keep their registers for loads.
+template <int BJ, class TT, int RT>
 __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, int ld, int64_t n, int cv, int b,
                                                         const TT* __restrict__ T, int BW,
                                                         const int32_t* __restrict__ grp,
@@ -98,41 +100,148 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                                                         const int* skip) {
     if (skip && *skip) return;
     extern __shared__ double lds[];
+    // the deflation table (kMaxGroups x 32 doubles; the rows past h are read
+    // but never used), so that its lookups wait for no global load
+    __shared__ double rtab_s[BJ == 1 ? kMaxGroups * 32 : 1];
+    if constexpr (BJ == 1) {
+        if (Rtab)
+            for (int e = threadIdx.x; e < kMaxGroups * 32; e += kOrThreads) rtab_s[e] = Rtab[e];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nrt = (cv + 15) >> 4;
-    d4 acc[kMaxRT * BJ];
+    d4 acc[RT * BJ];
 #pragma unroll
-    for (int t = 0; t < kMaxRT * BJ; ++t) acc[t] = d4{0, 0, 0, 0};
+    for (int t = 0; t < RT * BJ; ++t) acc[t] = d4{0, 0, 0, 0};
     const int64_t ntiles = (n + 15) >> 4;
     const int64_t wstride = (int64_t)gridDim.x * kOrWaves;
     for (int64_t tile = (int64_t)blockIdx.x * kOrWaves + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
+        if constexpr (BJ == 1 && RT <= 8) {
+            // a small basis: every load of the tile (4 steps) first
+            double yraw[4];
+            double araw[4][RT];
+            double cq[4];
+            int gq[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t row = tile * 16 + q * 4 + lk;
-            const bool rv = row < n;
-            double y[BJ];
-            // Rtab == nullptr: T already holds Y (general constraint)
-            const double c = (rv && cs && Rtab) ? cs[row] : 1.0;
-            const int gi = (rv && Rtab) ? grp[row] : 0;
-#pragma unroll
-            for (int jt = 0; jt < BJ; ++jt) {
-                const int col = jt * 16 + li;
-                double v = 0.0;
-                if (rv && col < b) {
-                    v = (double)T[row * BW + col];
-                    if (Rtab) v -= c * Rtab[gi * 32 + col];
-                    V[row * ld + cv + col] = v;
-                }
-                y[jt] = v;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = tile * 16 + q * 4 + lk;
+                const int64_t rs = row < n ? row : 0;
+                cq[q] = (cs && Rtab) ? cs[rs] : 1.0;
+                gq[q] = Rtab ? grp[rs] : 0;
             }
 #pragma unroll
-            for (int rt = 0; rt < kMaxRT; ++rt) {
-                if (rt < nrt) {
-                    const int col = rt * 16 + li;
-                    const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = tile * 16 + q * 4 + lk;
+                const int64_t rs = row < n ? row : 0;
+                yraw[q] = (double)T[rs * BW + (li < b ? li : 0)];
 #pragma unroll
-                    for (int jt = 0; jt < BJ; ++jt) acc[rt * BJ + jt] = mfma(a, y[jt], acc[rt * BJ + jt]);
+                for (int rt = 0; rt < RT; ++rt) {
+                    const int col = rt * 16 + li;
+                    araw[q][rt] = V[rs * ld + (rt < nrt && col < cv ? col : 0)];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = tile * 16 + q * 4 + lk;
+                const bool rv = row < n;
+                double y = 0.0;
+                if (rv && li < b) {
+                    y = yraw[q];
+                    if (Rtab) y -= cq[q] * rtab_s[gq[q] * 32 + li];
+                    V[row * ld + cv + li] = y;
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < nrt) {
+                        const double a = (rv && rt * 16 + li < cv) ? araw[q][rt] : 0.0;
+                        acc[rt] = mfma(a, y, acc[rt]);
+                    }
+                }
+            }
+        } else if constexpr (BJ == 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // every load of the step first, so that they are in flight
+                // together: rows past n read row 0 and columns past b or cv
+                // read column 0 (always in bounds), and the value is replaced
+                // by zero only where it is used (a select right after a load
+                // would wait for it)
+                const int64_t row = tile * 16 + q * 4 + lk;
+                const bool rv = row < n;
+                const int64_t rs = rv ? row : 0;
+                double yraw[BJ];
+                double araw[RT];
+                // the row's scale and group first: the table lookup waits
+                // for them only
+                const double c = (cs && Rtab) ? cs[rs] : 1.0;
+                const int gi = Rtab ? grp[rs] : 0;
+#pragma unroll
+                for (int jt = 0; jt < BJ; ++jt) {
+                    const int col = jt * 16 + li;
+                    yraw[jt] = (double)T[rs * BW + (col < b ? col : 0)];
+                }
+                // unconditional loads (no branch between them): a tile past
+                // nrt re-reads the row's first element, in tile 0's line
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const int col = rt * 16 + li;
+                    araw[rt] = V[rs * ld + (rt < nrt && col < cv ? col : 0)];
+                }
+                // Y0 = T - c_i Rtab[g_i] (Rtab == nullptr: T already holds Y, a
+                // general constraint) into the new block's columns
+                double y[BJ];
+#pragma unroll
+                for (int jt = 0; jt < BJ; ++jt) {
+                    const int col = jt * 16 + li;
+                    double v = 0.0;
+                    if (rv && col < b) {
+                        v = yraw[jt];
+                        if (Rtab) v -= c * rtab_s[gi * 32 + col];
+                        V[row * ld + cv + col] = v;
+                    }
+                    y[jt] = v;
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < nrt) {
+                        const bool ok = rv && rt * 16 + li < cv;
+                        const double a = ok ? araw[rt] : 0.0;
+#pragma unroll
+                        for (int jt = 0; jt < BJ; ++jt) acc[rt * BJ + jt] = mfma(a, y[jt], acc[rt * BJ + jt]);
+                    }
+                }
+            }
+        } else {
+            // two column tiles of the block: the registers of the hoisted
+            // form above would spill
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = tile * 16 + q * 4 + lk;
+                const bool rv = row < n;
+                double y[BJ];
+                // Rtab == nullptr: T already holds Y (general constraint)
+                const double c = (rv && cs && Rtab) ? cs[row] : 1.0;
+                const int gi = (rv && Rtab) ? grp[row] : 0;
+#pragma unroll
+                for (int jt = 0; jt < BJ; ++jt) {
+                    const int col = jt * 16 + li;
+                    double v = 0.0;
+                    if (rv && col < b) {
+                        v = (double)T[row * BW + col];
+                        if (Rtab) v -= c * Rtab[gi * 32 + col];
+                        V[row * ld + cv + col] = v;
+                    }
+                    y[jt] = v;
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < nrt) {
+                        const int col = rt * 16 + li;
+                        const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+#pragma unroll
+                        for (int jt = 0; jt < BJ; ++jt) acc[rt * BJ + jt] = mfma(a, y[jt], acc[rt * BJ + jt]);
+                    }
                 }
             }
         }
@@ -147,7 +256,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
 // same wavefront).
 //   GRAM: partial [V[:, 0:cv]^T Ynew (nrt x BJ tiles); Ynew^T Ynew (BJ x BJ)]
 //   SYRK: partial Ynew^T Ynew
-template <int BJ, bool GRAM, bool SYRK>
+template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
@@ -174,7 +283,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nrt = GRAM ? (cv + 15) >> 4 : 0;
-    constexpr int NG = GRAM ? kMaxRT * BJ : 1;
+    constexpr int NG = GRAM ? RT * BJ : 1;
     d4 accg[NG];
     d4 accs[BJ * BJ];
 #pragma unroll
@@ -231,11 +340,31 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
         // Gram and Syrk from registers (rows past n hold zeros)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (GRAM) {
+            if constexpr (GRAM && BJ == 1) {
+                // the step's loads first, unconditionally (row 0 / column 0
+                // stand in past n or cv), zeroed only where used, so that
+                // they are all in flight together
+                const int64_t row = row0 + 4 * q + lk;
+                const bool rv = row < n;
+                const int64_t rs = rv ? row : 0;
+                double araw[RT];
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const int col = rt * 16 + li;
+                    araw[rt] = V[rs * ld + (rt < nrt && col < cv ? col : 0)];
+                }
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < nrt) {
+                        const double a = (rv && rt * 16 + li < cv) ? araw[rt] : 0.0;
+                        accg[rt] = mfma(a, D[0][q], accg[rt]);
+                    }
+                }
+            } else if constexpr (GRAM) {
                 const int64_t row = row0 + 4 * q + lk;
                 const bool rv = row < n;
 #pragma unroll
-                for (int rt = 0; rt < kMaxRT; ++rt) {
+                for (int rt = 0; rt < RT; ++rt) {
                     if (rt < nrt) {
                         const int col = rt * 16 + li;
                         const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
@@ -427,14 +556,35 @@ size_t ortho_small_doubles() {
     return (size_t)(kMaxRT * 2 + 4) * 256 * 2 + (size_t)kLdMax * kMaxBlock * 3 + 4 * kMaxBlock * kMaxBlock;
 }
 
+// Row-tile bound of the Gram products for cv basis columns.
+static int rt_bound(int cv) {
+    const int nrt = (cv + 15) / 16;
+    return nrt <= 4 ? 4 : nrt <= 8 ? 8 : kMaxRT;
+}
+
 template <class TT>
 static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int cv, int b,
                      const TT* T, int BW, const int32_t* grp, const double* cs, const double* Rtab, double* part,
                      const int* skip) {
-    if (BJ == 1)
-        k_pass_a<1, TT><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, part, skip);
-    else
-        k_pass_a<2, TT><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, part, skip);
+#define SF_PASS_A(BJV, RTV) \
+    k_pass_a<BJV, TT, RTV><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, part, skip)
+    const int rt = rt_bound(cv);
+    if (BJ == 1) {
+        if (rt == 4)
+            SF_PASS_A(1, 4);
+        else if (rt == 8)
+            SF_PASS_A(1, 8);
+        else
+            SF_PASS_A(1, kMaxRT);
+    } else {
+        if (rt == 4)
+            SF_PASS_A(2, 4);
+        else if (rt == 8)
+            SF_PASS_A(2, 8);
+        else
+            SF_PASS_A(2, kMaxRT);
+    }
+#undef SF_PASS_A
 }
 
 template <bool GRAM, bool SYRK>
@@ -445,12 +595,27 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
         Vout = V;
         ldo = ld;
     }
-    if (BJ == 1)
-        k_pass_upd<1, GRAM, SYRK>
-            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles);
-    else
-        k_pass_upd<2, GRAM, SYRK>
-            <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles);
+#define SF_PASS_U(BJV, RTV)                                                                                 \
+    k_pass_upd<BJV, GRAM, SYRK, RTV>                                                                        \
+        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles)
+    // the row-tile bound matters only for the Gram product
+    const int rt = GRAM ? rt_bound(cv) : kMaxRT;
+    if (BJ == 1) {
+        if (rt == 4)
+            SF_PASS_U(1, 4);
+        else if (rt == 8)
+            SF_PASS_U(1, 8);
+        else
+            SF_PASS_U(1, kMaxRT);
+    } else {
+        if (rt == 4)
+            SF_PASS_U(2, 4);
+        else if (rt == 8)
+            SF_PASS_U(2, 8);
+        else
+            SF_PASS_U(2, kMaxRT);
+    }
+#undef SF_PASS_U
 }
 
 int ortho_expand(const OrthoArgs& a) {
