@@ -14,10 +14,12 @@
 // wavefronts); one wavefront sums a segment and a group adds its segments in
 // order, so every reduction has a fixed order.
 //
-// One cooperative launch runs a whole solve: four grid barriers per LSQR
+// One cooperative launch runs a whole solve: three grid barriers per LSQR
 // step (after the n-space update of u, after the segment sums, after the
-// m-space update of v, after its reduction).  Workgroup 0 reduces the
-// per-workgroup partials in a fixed order and publishes the sums, so every
+// m-space update of v).  The sums of u's partials are reduced by workgroup 0
+// while the grid computes the segment sums and published for the next
+// barrier; those of v (and the final ones) are reduced by every workgroup
+// itself, the grid being small.  Either way the order is fixed, so every
 // workgroup holds bitwise the same scalars and leaves the loop at the same
 // step (converged columns, or max_inner).
 #include <hip/hip_cooperative_groups.h>
@@ -249,9 +251,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lsqr(LsqrArgs a) {
 
     group_phase(true);
     grid.sync();
-    ls_reduce_by_first(a.part2, b, a.res + 64, r0, r1, red);
-    grid.sync();
-    ls_read(a.res + 64, b, r0, r1);
+    ls_grid_reduce(a.part2, b, r0, r1, red);
     if (tid < b) {
         alpha[tid] = std::sqrt(r0[tid]);
         zv[tid] = r1[tid];
@@ -319,9 +319,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lsqr(LsqrArgs a) {
         __syncthreads();
         group_phase(false);
         grid.sync();
-        ls_reduce_by_first(a.part2, b, a.res + 64, r0, r1, red);
-        grid.sync();
-        ls_read(a.res + 64, b, r0, r1);
+        ls_grid_reduce(a.part2, b, r0, r1, red);
         if (tid < b && live[tid]) {
             const double an = std::sqrt(r0[tid]), bn = beta[tid];
             const double rho = std::sqrt(rhobar[tid] * rhobar[tid] + bn * bn);
@@ -365,9 +363,7 @@ __global__ __launch_bounds__(kLsThreads) void k_lsqr(LsqrArgs a) {
         ls_block_partials(q0, 0.0, BWc, b, red, a.part);
     }
     grid.sync();
-    ls_reduce_by_first(a.part, b, a.res, r0, r1, red);
-    grid.sync();
-    ls_read(a.res, b, r0, r1);
+    ls_grid_reduce(a.part, b, r0, r1, red);
     if (MODE == LS_IN && blockIdx.x == 0 && tid < b) a.zx1[tid] = r0[tid];
 
     // output rows: W - C x (LS_OUT: x - sigma x1)
