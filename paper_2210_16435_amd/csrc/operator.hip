@@ -169,20 +169,24 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     const int P = kFinThreads / O;    // threads per output
     const int t = threadIdx.x;
     {
-        // four independent accumulators keep several partial loads in flight
+        // eight independent accumulators keep several partial loads in flight
         const int o = t % O, sub = t / O;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0, s6 = 0.0, s7 = 0.0;
         if (sub < P) {
             int blk = sub;
-            for (; blk + 3 * P < nblk; blk += 4 * P) {
+            for (; blk + 7 * P < nblk; blk += 8 * P) {
                 s0 += part[(size_t)blk * O + o];
                 s1 += part[(size_t)(blk + P) * O + o];
                 s2 += part[(size_t)(blk + 2 * P) * O + o];
                 s3 += part[(size_t)(blk + 3 * P) * O + o];
+                s4 += part[(size_t)(blk + 4 * P) * O + o];
+                s5 += part[(size_t)(blk + 5 * P) * O + o];
+                s6 += part[(size_t)(blk + 6 * P) * O + o];
+                s7 += part[(size_t)(blk + 7 * P) * O + o];
             }
             for (; blk < nblk; blk += P) s0 += part[(size_t)blk * O + o];
         }
-        red[t] = (s0 + s1) + (s2 + s3);
+        red[t] = ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
     }
     __syncthreads();
     if (t < O) {

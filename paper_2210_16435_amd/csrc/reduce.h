@@ -1,6 +1,6 @@
 // Deterministic reduction of per-block partial sums: out[e] = sum over
-// blocks b (in increasing b, 16 interleaved slices combined in slice order)
-// of part[b][e].  Each workgroup covers 64 elements with 16 slices, so the
+// blocks b of part[b][e], in a fixed order (16 interleaved slices, each
+// split over four accumulators, combined in slice order).  Each workgroup covers 64 elements with 16 slices, so the
 // partials are read by ceil(O / 64) workgroups in parallel.
 #pragma once
 
@@ -20,10 +20,19 @@ __global__ __launch_bounds__(kRedElems * kRedSlices) void k_reduce_partials(cons
     __shared__ double red[kRedElems * kRedSlices];
     const int el = threadIdx.x % kRedElems, sl = threadIdx.x / kRedElems;
     const int e = blockIdx.x * kRedElems + el;
-    double s = 0.0;
-    if (e < O)
-        for (int blk = sl; blk < nblk; blk += kRedSlices) s += part[(size_t)blk * O + e];
-    red[threadIdx.x] = s;
+    // four independent accumulators keep several loads in flight
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (e < O) {
+        int blk = sl;
+        for (; blk + 3 * kRedSlices < nblk; blk += 4 * kRedSlices) {
+            s0 += part[(size_t)blk * O + e];
+            s1 += part[(size_t)(blk + kRedSlices) * O + e];
+            s2 += part[(size_t)(blk + 2 * kRedSlices) * O + e];
+            s3 += part[(size_t)(blk + 3 * kRedSlices) * O + e];
+        }
+        for (; blk < nblk; blk += kRedSlices) s0 += part[(size_t)blk * O + e];
+    }
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (sl == 0 && e < O) {
         double t = 0.0;
