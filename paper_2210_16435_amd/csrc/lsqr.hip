@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -407,18 +408,24 @@ static int pow2_at_least(int b) {
 
 template <class TT, class OT, int MODE>
 static int launch_lsqr(sfairsc_graph* g, LsqrArgs& a, hipStream_t s) {
-    static std::map<int, int> occ_of_device;  // blocks per CU
+    // blocks per CU of this kernel, per device (calls on distinct handles
+    // may come from several host threads)
+    static std::map<int, int> occ_of_device;
+    static std::mutex occ_mutex;
     int dev = 0;
     SF_HIP(hipGetDevice(&dev));
-    auto it = occ_of_device.find(dev);
-    int per_cu;
-    if (it == occ_of_device.end()) {
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(occ_mutex);
+        auto it = occ_of_device.find(dev);
+        if (it != occ_of_device.end()) per_cu = it->second;
+    }
+    if (per_cu == 0) {
         SF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_lsqr<TT, OT, MODE>),
                                                            kLsThreads, 0));
         if (per_cu < 1) return set_error(SFAIRSC_E_HIP, "LSQR kernel cannot be resident");
+        std::lock_guard<std::mutex> lock(occ_mutex);
         occ_of_device[dev] = per_cu;
-    } else {
-        per_cu = it->second;
     }
     int cus = 0;
     SF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
