@@ -59,6 +59,16 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// A load through a global-address-space pointer.  The kernel reaches its
+// buffers through pointers stored in memory, so the compiler cannot prove
+// they are global and emits flat loads; a flat load counts against the LDS
+// counter too, and waiting for one then waits for every outstanding one.
+// All buffers here are device memory.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+    return *((const __attribute__((address_space(1))) T*)p);
+}
+
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -450,15 +460,24 @@ __device__ SF_ITEM_FN void w_pass_a(const Graph& t, double* V, int ld, int cv, i
             const bool rv = row < n;
             double y = 0.0;
             if (rv && li < b) {
-                const double c = t.cs ? t.cs[row] : 1.0;
-                y = (double)T[row * b + li] - c * R2[t.grp[row] * 16 + li];
+                const double c = t.cs ? gload(t.cs + row) : 1.0;
+                y = (double)gload(T + row * b + li) - c * gload(R2 + gload(t.grp + row) * 16 + li);
                 V[row * ld + cv + li] = y;
+            }
+            // every basis load of the step first, unconditionally (row 0 /
+            // column 0 stand in past n or cv), zeroed only at the use: a
+            // select right after a load would wait for it
+            const int64_t rs = rv ? row : 0;
+            double araw[RTMAX];
+#pragma unroll
+            for (int rt = 0; rt < RTMAX; ++rt) {
+                const int col = rt * 16 + li;
+                araw[rt] = gload(V + rs * ld + (rt < nrt && col < cv ? col : 0));
             }
 #pragma unroll
             for (int rt = 0; rt < RTMAX; ++rt) {
                 if (rt < nrt) {
-                    const int col = rt * 16 + li;
-                    const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+                    const double a = (rv && rt * 16 + li < cv) ? araw[rt] : 0.0;
                     acc[rt] = mfma16(a, y, acc[rt]);
                 }
             }
@@ -500,8 +519,10 @@ __device__ SF_ITEM_FN void w_upd(int64_t n, double* V, int ld, int coff, int kin
                 for (int cc = 0; cc < KH; ++cc) {
                     const int c = hb * KH + cc;
                     x[cc] = make_double4(0, 0, 0, 0);
-                    if (c < KCH && rv && c * 16 + 4 * lk < kin)
-                        x[cc] = *reinterpret_cast<const double4*>(src + c * 16);
+                    if (c < KCH && rv && c * 16 + 4 * lk < kin) {
+                        const d4 v = gload(reinterpret_cast<const d4*>(src + c * 16));
+                        x[cc] = make_double4(v[0], v[1], v[2], v[3]);
+                    }
                 }
 #pragma unroll
                 for (int cc = 0; cc < KH; ++cc) {
@@ -511,7 +532,7 @@ __device__ SF_ITEM_FN void w_upd(int64_t n, double* V, int ld, int coff, int kin
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
                             const int kr = c * 16 + 4 * lk + s;
-                            const double bm = kr < kin ? M[kr * 16 + li] : 0.0;
+                            const double bm = kr < kin ? gload(M + kr * 16 + li) : 0.0;
                             D = mfma16(xs[s], bm, D);
                         }
                     }
@@ -526,13 +547,20 @@ __device__ SF_ITEM_FN void w_upd(int64_t n, double* V, int ld, int coff, int kin
         if (GRAM) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                // the step's basis loads first (as in w_pass_a)
                 const int64_t row = row0 + 4 * q + lk;
                 const bool rv = row < n;
+                const int64_t rs = rv ? row : 0;
+                double araw[RTMAX];
+#pragma unroll
+                for (int rt = 0; rt < RTMAX; ++rt) {
+                    const int col = rt * 16 + li;
+                    araw[rt] = gload(V + rs * ld + (rt < nrt && col < cv ? col : 0));
+                }
 #pragma unroll
                 for (int rt = 0; rt < RTMAX; ++rt) {
                     if (rt < nrt) {
-                        const int col = rt * 16 + li;
-                        const double a = (rv && col < cv) ? V[row * ld + col] : 0.0;
+                        const double a = (rv && rt * 16 + li < cv) ? araw[rt] : 0.0;
                         acc[rt] = mfma16(a, D[q], acc[rt]);
                     }
                 }
