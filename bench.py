@@ -302,6 +302,7 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": by,
             "launch_ms": per_launch_ms,
+            "l2_fill": spmm_l2_fill(head, b, per_launch_ms),
         },
         "cpu_baseline": cpu,
         "other_workloads": extra,
@@ -611,9 +612,8 @@ def _source_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def spmm_traffic(prec, b):
-    """Measured HBM bytes per SpMM launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's readings), or None if
+def spmm_counters(prec, b):
+    """Counter readings per SpMM launch from the committed summary, or None if
     absent or taken on a different version of the kernel source."""
     name = f"spmm_{'f32' if prec == 'mixed' else 'f64'}_b{b}_msbm50k_counters.md"
     path = os.path.join(ROOT, "profiles", name)
@@ -626,10 +626,37 @@ def spmm_traffic(prec, b):
             vals[k_.strip().strip("-").strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != _source_hash():
         return None
+    return vals
+
+
+def _counter(vals, key):
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key]) if vals else None
     except (KeyError, ValueError):
         return None
+
+
+def spmm_traffic(prec, b):
+    """Measured HBM bytes per SpMM launch (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's readings), or None."""
+    return _counter(spmm_counters(prec, b), "hbm_bytes_per_launch")
+
+
+# L2 -> L1 fill ceiling: 8 XCDs, each L2 with 16 channels of 128 bytes per
+# clock, at 2.4 GHz
+L2_FILL_PEAK_GBPS = 8 * 16 * 128 * 2.4
+
+
+def spmm_l2_fill(prec, b, launch_ms):
+    """Line fills from the L2 into the L1s per SpMM launch (TCP_TCC_READ_REQ
+    x bytes per request, from the committed summary) against the L2's fill
+    ceiling, or None."""
+    by = _counter(spmm_counters(prec, b), "l2_to_l1_bytes_per_launch")
+    if by is None or launch_ms <= 0:
+        return None
+    rate = by / (launch_ms * 1e-3) / 1e9
+    return {"bytes": by, "achieved": round(rate, 1), "peak": round(L2_FILL_PEAK_GBPS, 1), "unit": "GB/s",
+            "frac": round(rate / L2_FILL_PEAK_GBPS, 4)}
 
 
 def cpu_baseline(g, k, normalized):

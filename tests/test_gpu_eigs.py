@@ -221,3 +221,20 @@ def test_msbm_50k_normalized_fp64_and_mixed():
         r = G.eigs(k, tol=tol, precision=prec)
         log(f"  info {r.info}")
         check_solution(g, r.eigenvalues, to_np(r.H), k, True, tol, G.sigma, lam_ref, None, rtol)
+
+
+def test_kernel_timing_mode_reports_the_phases():
+    # time_kernels: GPU event time of the operator (which contains the sparse
+    # product), the orthogonalisation and the restart rotation; zero otherwise
+    sf = lib()
+    g = random_sparse_graph(3000, 20, seed=91, h=3)
+    G = sf.Graph.from_msbm(g, True)
+    r = G.eigs(6, tol=1e-9, precision="fp64", block_width=8, max_basis=32, time_kernels=True)
+    i = r.info
+    log(f"timing info {i}")
+    assert i["operator_ms"] > 0 and i["ortho_ms"] > 0
+    assert (i["restart_ms"] > 0) == (i["restarts"] > 0)
+    assert i["operator_ms"] >= sum(i["spmm_ms"]) > 0
+    r0 = G.eigs(6, tol=1e-9, precision="fp64", block_width=8, max_basis=32)
+    assert r0.info["operator_ms"] == 0 and r0.info["ortho_ms"] == 0 and r0.info["restart_ms"] == 0
+    assert np.allclose(r0.eigenvalues, r.eigenvalues, rtol=1e-10)
