@@ -170,6 +170,7 @@ def main():
 
     precs = ["mixed", "fp64"] if args.only == "both" else [args.only]
     results = {}
+    H_keep = {}
     for prec in precs:
         for _ in range(args.warmup):
             solve(prec)
@@ -180,6 +181,7 @@ def main():
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
         results[prec] = (ms, r)
+        H_keep[prec] = r.H.double().cpu().numpy()
         print(f"[bench] {prec}: {ms:.3f} ms/solve info={r.info}", file=sys.stderr, flush=True)
 
     # SpMM kernel durations (HIP events inside the library, separate runs)
@@ -239,6 +241,21 @@ def main():
         lam = r_head.eigenvalues
         acc = float(np.max(np.abs(lam - ref) / np.maximum(np.abs(ref), ref[1])))
 
+    # the mixed solve against the FP64 solve: eigenvalues and the largest
+    # principal angle between the two eigenspaces (D-inner product for the
+    # normalized variant, where H^T D H = I)
+    agree = None
+    if "mixed" in results and "fp64" in results:
+        Wd = g.to_scipy()
+        wgt = np.asarray(Wd.sum(axis=1)).ravel() if normalized else np.ones(g.n)
+        Hm, Hf = H_keep["mixed"], H_keep["fp64"]
+        cosines = np.linalg.svd(Hm.T @ (wgt[:, None] * Hf), compute_uv=False)
+        lm, lf = results["mixed"][1].eigenvalues, results["fp64"][1].eigenvalues
+        agree = {
+            "eig_rel_diff": float(np.max(np.abs(lm - lf) / np.maximum(np.abs(lf), lf[1]))),
+            "max_principal_angle": float(np.arccos(min(1.0, float(cosines.min())))),
+        }
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, k, normalized)
@@ -286,6 +303,7 @@ def main():
         else None,
         "max_rel_residual": r_head.info["max_rel_residual"],
         "eig_rel_err_vs_oracle": acc,
+        "mixed_vs_fp64_solution": agree,
         "restarts": r_head.info["restarts"],
         "block_steps": r_head.info["block_steps"],
         "graph_setup_ms": round(setup_ms, 3),
@@ -677,10 +695,19 @@ def cpu_baseline(g, k, normalized):
     t0 = time.perf_counter()
     oracle.fair_eigs_deflated(W, g.groups, g.h, k, normalized, tol=1e-10)
     s2 = time.perf_counter() - t0
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
     return {
         "value": round(s * 1e3, 1),
         "unit": "ms",
         "cores": threads,
+        "host": {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model},
         "kind": "oracle",
         "sample": "one full FP64 solve of the same graph (scipy ARPACK on the implicit-nullspace operator; "
         "matvecs single-threaded, BLAS threads as counted)",
