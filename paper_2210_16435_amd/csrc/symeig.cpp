@@ -6,8 +6,9 @@
 //   * Householder reduction to tridiagonal form Q^T A Q = T (reflectors kept);
 //   * all eigenvalues of T by implicitly shifted QL iterations;
 //   * eigenvectors of T for the m wanted eigenvalues only, by inverse
-//     iteration with a pivoted tridiagonal LU, re-orthogonalised within
-//     clusters of close eigenvalues; then back-transformed, x = Q y.
+//     iteration with a pivoted tridiagonal LU (several shifts in lockstep),
+//     re-orthogonalised within clusters of close eigenvalues; then
+//     back-transformed, x = Q y.
 // The full-vector variant (all n eigenvectors by accumulating every QL
 // rotation) is kept for tests and tiny orders.
 #include <algorithm>
@@ -23,6 +24,8 @@ namespace sfairsc {
 namespace {
 
 constexpr double kEps = std::numeric_limits<double>::epsilon();
+constexpr int kLanes = 8;  // shifts whose inverse iterations run in lockstep
+constexpr int kWY = 4;     // reflectors applied together in the back-transform
 
 // sqrt(a^2 + b^2) without the overflow guards of std::hypot: the projected
 // matrices here have entries bounded by the shift sigma, far from overflow.
@@ -181,67 +184,6 @@ void tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, double* Z
     }
 }
 
-// LU factorisation of T - lam I with partial pivoting (tridiagonal: U has
-// two super-diagonals); zero pivots replaced by +-tiny.  Stores reciprocal
-// pivots so each solve is division-free.
-struct TriLU {
-    std::vector<double> ip, u1, u2, mult;  // 1/u0, super-diagonals, multipliers
-    std::vector<char> swp;
-    void factor(const std::vector<double>& d, const std::vector<double>& e, double lam, double tiny) {
-        const int n = (int)d.size();
-        ip.resize(n);
-        u1.resize(n);
-        u2.resize(n);
-        mult.resize(n);
-        swp.resize(n);
-        double c0 = d[0] - lam, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;
-        for (int i = 0; i + 1 < n; ++i) {
-            const double s = e[i];
-            const double n1 = d[i + 1] - lam;
-            const double n2 = (i + 2 < n) ? e[i + 1] : 0.0;
-            double u0, r1, r2;
-            if (std::fabs(s) > std::fabs(c0)) {
-                swp[i] = 1;
-                u0 = s;
-                u1[i] = n1;
-                u2[i] = n2;
-                const double mlt = c0 / s;
-                mult[i] = mlt;
-                r1 = c1 - mlt * n1;
-                r2 = c2 - mlt * n2;
-            } else {
-                swp[i] = 0;
-                if (std::fabs(c0) < tiny) c0 = c0 < 0 ? -tiny : tiny;
-                u0 = c0;
-                u1[i] = c1;
-                u2[i] = c2;
-                const double mlt = s / c0;
-                mult[i] = mlt;
-                r1 = n1 - mlt * c1;
-                r2 = n2 - mlt * c2;
-            }
-            ip[i] = 1.0 / u0;
-            c0 = r1;
-            c1 = r2;
-            c2 = 0.0;
-        }
-        if (std::fabs(c0) < tiny) c0 = c0 < 0 ? -tiny : tiny;
-        ip[n - 1] = 1.0 / c0;
-        u1[n - 1] = 0.0;
-        u2[n - 1] = 0.0;
-    }
-    // b <- (T - lam I)^{-1} b
-    void solve(double* b, int n) const {
-        for (int i = 0; i + 1 < n; ++i) {
-            if (swp[i]) std::swap(b[i], b[i + 1]);
-            b[i + 1] -= mult[i] * b[i];
-        }
-        b[n - 1] *= ip[n - 1];
-        if (n >= 2) b[n - 2] = (b[n - 2] - u1[n - 2] * b[n - 1]) * ip[n - 2];
-        for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - u1[i] * b[i + 1] - u2[i] * b[i + 2]) * ip[i];
-    }
-};
-
 }  // namespace
 
 void sym_eig(int n, const double* A, double* w, double* Z) {
@@ -300,63 +242,209 @@ void SymEigSel::vectors(int m, double* Z) {
         if (m >= 1) Z[0] = 1.0;
         return;
     }
-    TriLU lu;
-    std::vector<std::vector<double>> Y;  // eigenvectors of T
-    Y.reserve(m);
     const double tiny = kEps * norm;
     const double cluster_gap = 1e-3 * norm;
-    double prev_shift = -INFINITY;
-    int cluster_start = 0;
-    std::vector<double> x(n);
-    for (int j = 0; j < m; ++j) {
-        double lam = w[j];
-        if (j > 0 && w[j] - w[j - 1] > cluster_gap) cluster_start = j;
-        if (lam <= prev_shift + 10 * tiny) lam = prev_shift + 10 * tiny;  // separate equal shifts
-        prev_shift = lam;
-        lu.factor(d, e, lam, tiny);
-        // start vector with no special alignment to any eigenvector
-        for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 17) / 17.0;
-        for (int it = 0; it < 3; ++it) {
-            lu.solve(x.data(), n);
-            for (int pass = 0; pass < 2; ++pass)
-                for (int q = cluster_start; q < j; ++q) {
-                    double dot = 0.0;
-                    for (int i = 0; i < n; ++i) dot += Y[q][i] * x[i];
-                    for (int i = 0; i < n; ++i) x[i] -= dot * Y[q][i];
-                }
-            double nrm = 0.0;
-            for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
-            nrm = std::sqrt(nrm);
-            if (!(nrm > 0.0) || !std::isfinite(nrm)) {
-                for (int i = 0; i < n; ++i) x[i] = (i == j % n) ? 1.0 : 0.0;
-                nrm = 1.0;
-            }
-            const double inv = 1.0 / nrm;
-            for (int i = 0; i < n; ++i) x[i] *= inv;
+    // shifts (equal ones pulled apart) and the first index of each one's
+    // cluster of close eigenvalues
+    std::vector<double> shift(m);
+    std::vector<int> cstart(m);
+    {
+        double prev = -INFINITY;
+        int c0 = 0;
+        for (int j = 0; j < m; ++j) {
+            double lam = w[j];
+            if (j > 0 && w[j] - w[j - 1] > cluster_gap) c0 = j;
+            if (lam <= prev + 10 * tiny) lam = prev + 10 * tiny;
+            prev = lam;
+            shift[j] = lam;
+            cstart[j] = c0;
         }
-        Y.push_back(x);
     }
-    // back-transform all m vectors at once: Z = Q Y with Z row-major n x m;
-    // each reflector is applied as w = v^T Z[k+1:, :], Z[k+1:, :] -= beta v w^T
-    for (int j = 0; j < m; ++j)
-        for (int i = 0; i < n; ++i) Z[(size_t)i * m + j] = Y[j][i];
-    std::vector<double> wv(m);
-    for (int k = n - 3; k >= 0; --k) {
-        const double bk = beta[k];
-        if (bk == 0.0) continue;
-        const int len = n - k - 1;
-        const double* v = &refl[(size_t)k * n];
-        std::fill(wv.begin(), wv.end(), 0.0);
-        for (int i = 0; i < len; ++i) {
-            const double vi = v[i];
-            const double* row = Z + (size_t)(k + 1 + i) * m;
-            for (int j = 0; j < m; ++j) wv[j] += vi * row[j];
+    // Inverse iteration on kLanes shifts at once: the factorisations and
+    // solves of the lanes are independent, so their division chains overlap
+    // (lane-interleaved arrays, element i of lane q at [i * kLanes + q]).
+    // The pivot choices differ per lane and are taken by selects.
+    constexpr int L = kLanes;
+    std::vector<double> Y((size_t)m * n);  // final eigenvectors of T, one per row
+    std::vector<double> ip((size_t)n * L), u1((size_t)n * L), u2((size_t)n * L), mlt((size_t)n * L), x((size_t)n * L),
+        xs((size_t)L * n);
+    std::vector<unsigned char> swp((size_t)n * L);
+    for (int j0 = 0; j0 < m; j0 += L) {
+        const int na = std::min(L, m - j0);
+        double lam[L];
+        for (int q = 0; q < L; ++q) lam[q] = shift[j0 + std::min(q, na - 1)];
+        // pivoted LU of T - lam I per lane (U has two super-diagonals)
+        {
+            double c0[L], c1[L];
+            for (int q = 0; q < L; ++q) {
+                c0[q] = d[0] - lam[q];
+                c1[q] = e[0];
+            }
+            for (int i = 0; i + 1 < n; ++i) {
+                const double sd = e[i];
+                const double n2 = (i + 2 < n) ? e[i + 1] : 0.0;
+#pragma omp simd
+                for (int q = 0; q < L; ++q) {
+                    const double n1 = d[i + 1] - lam[q];
+                    const bool sw = std::fabs(sd) > std::fabs(c0[q]);
+                    const double ct = std::fabs(c0[q]) < tiny ? (c0[q] < 0 ? -tiny : tiny) : c0[q];
+                    const double piv = sw ? sd : ct;
+                    const double inv = 1.0 / piv;
+                    const double m_ = (sw ? c0[q] : sd) * inv;
+                    const double v1 = sw ? n1 : c1[q];
+                    const double v2 = sw ? n2 : 0.0;
+                    swp[(size_t)i * L + q] = sw;
+                    ip[(size_t)i * L + q] = inv;
+                    mlt[(size_t)i * L + q] = m_;
+                    u1[(size_t)i * L + q] = v1;
+                    u2[(size_t)i * L + q] = v2;
+                    c0[q] = (sw ? c1[q] : n1) - m_ * v1;
+                    c1[q] = (sw ? 0.0 : n2) - m_ * v2;
+                }
+            }
+            for (int q = 0; q < L; ++q) {
+                const double ct = std::fabs(c0[q]) < tiny ? (c0[q] < 0 ? -tiny : tiny) : c0[q];
+                ip[(size_t)(n - 1) * L + q] = 1.0 / ct;
+                u1[(size_t)(n - 1) * L + q] = 0.0;
+                u2[(size_t)(n - 1) * L + q] = 0.0;
+            }
         }
-        for (int j = 0; j < m; ++j) wv[j] *= bk;
-        for (int i = 0; i < len; ++i) {
-            const double vi = v[i];
-            double* row = Z + (size_t)(k + 1 + i) * m;
-            for (int j = 0; j < m; ++j) row[j] -= vi * wv[j];
+        // start vectors with no special alignment to any eigenvector
+        for (int i = 0; i < n; ++i)
+            for (int q = 0; q < L; ++q)
+                x[(size_t)i * L + q] = 1.0 + 0.25 * (double)((i * 7 + (j0 + q) * 13) % 17) / 17.0;
+        for (int it = 0; it < 3; ++it) {
+            // x <- (T - lam I)^{-1} x, every lane
+            for (int i = 0; i + 1 < n; ++i) {
+#pragma omp simd
+                for (int q = 0; q < L; ++q) {
+                    const double a = x[(size_t)i * L + q], bq = x[(size_t)(i + 1) * L + q];
+                    const bool sw = swp[(size_t)i * L + q];
+                    const double lo = sw ? bq : a, hi = sw ? a : bq;
+                    x[(size_t)i * L + q] = lo;
+                    x[(size_t)(i + 1) * L + q] = hi - mlt[(size_t)i * L + q] * lo;
+                }
+            }
+            for (int q = 0; q < L; ++q) x[(size_t)(n - 1) * L + q] *= ip[(size_t)(n - 1) * L + q];
+            for (int q = 0; q < L; ++q)
+                x[(size_t)(n - 2) * L + q] =
+                    (x[(size_t)(n - 2) * L + q] - u1[(size_t)(n - 2) * L + q] * x[(size_t)(n - 1) * L + q]) *
+                    ip[(size_t)(n - 2) * L + q];
+            for (int i = n - 3; i >= 0; --i) {
+#pragma omp simd
+                for (int q = 0; q < L; ++q)
+                    x[(size_t)i * L + q] = (x[(size_t)i * L + q] - u1[(size_t)i * L + q] * x[(size_t)(i + 1) * L + q] -
+                                            u2[(size_t)i * L + q] * x[(size_t)(i + 2) * L + q]) *
+                                           ip[(size_t)i * L + q];
+            }
+            // lane by lane, on contiguous copies: orthogonalise against the
+            // earlier vectors of the same cluster (finished ones, then this
+            // group's earlier lanes), twice, and normalise
+            for (int i = 0; i < n; ++i)
+                for (int q = 0; q < L; ++q) xs[(size_t)q * n + i] = x[(size_t)i * L + q];
+            for (int q = 0; q < na; ++q) {
+                const int j = j0 + q;
+                double* __restrict__ xq = &xs[(size_t)q * n];
+                for (int pass = 0; pass < 2; ++pass) {
+                    for (int r = cstart[j]; r < j; ++r) {
+                        const double* __restrict__ y = r < j0 ? &Y[(size_t)r * n] : &xs[(size_t)(r - j0) * n];
+                        double dot = 0.0;
+#pragma omp simd reduction(+ : dot)
+                        for (int i = 0; i < n; ++i) dot += y[i] * xq[i];
+#pragma omp simd
+                        for (int i = 0; i < n; ++i) xq[i] -= dot * y[i];
+                    }
+                }
+                double nrm = 0.0;
+#pragma omp simd reduction(+ : nrm)
+                for (int i = 0; i < n; ++i) nrm += xq[i] * xq[i];
+                nrm = std::sqrt(nrm);
+                if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+                    for (int i = 0; i < n; ++i) xq[i] = (i == j % n) ? 1.0 : 0.0;
+                    nrm = 1.0;
+                }
+                const double inv = 1.0 / nrm;
+                for (int i = 0; i < n; ++i) xq[i] *= inv;
+            }
+            for (int i = 0; i < n; ++i)
+                for (int q = 0; q < L; ++q) x[(size_t)i * L + q] = xs[(size_t)q * n + i];
+        }
+        for (int q = 0; q < na; ++q)
+            for (int i = 0; i < n; ++i) Y[(size_t)(j0 + q) * n + i] = xs[(size_t)q * n + i];
+    }
+    // back-transform all m vectors at once: Z = Q Y with Z row-major n x m.
+    // Q = H_0 H_1 ... H_{n-3} is applied from the last reflector down, kWY
+    // reflectors at a time in compact WY form (Schreiber and Van Loan):
+    // H_kb ... H_{kb+nb-1} = I - V T V^T with V the block's reflectors as
+    // columns and T upper triangular, T[0:i, i] = -beta_i T[0:i, 0:i]
+    // V[:, 0:i]^T v_i, T[i, i] = beta_i; then Z <- Z - V (T (V^T Z)), two
+    // sweeps over Z per block instead of two per reflector.
+    for (int j = 0; j < m; ++j)
+        for (int i = 0; i < n; ++i) Z[(size_t)i * m + j] = Y[(size_t)j * n + i];
+    const int nref = n - 2;  // reflectors 0 .. n-3
+    if (nref <= 0) return;
+    constexpr int NB = kWY;
+    std::vector<double> V((size_t)n * NB), W((size_t)NB * m), W2((size_t)NB * m);
+    double T[NB][NB];
+    for (int kb = ((nref - 1) / NB) * NB; kb >= 0; kb -= NB) {
+        const int nb = std::min(NB, nref - kb);
+        const int r0 = kb + 1;      // first row the block touches
+        const int rows = n - r0;
+        // V[row][r]: reflector kb + r acts on rows r0 + r .. n - 1
+        for (int row = 0; row < rows; ++row)
+            for (int r = 0; r < NB; ++r)
+                V[(size_t)row * NB + r] =
+                    (r < nb && row >= r) ? refl[(size_t)(kb + r) * n + (row - r)] : 0.0;
+        for (int i = 0; i < NB; ++i)
+            for (int r = 0; r < NB; ++r) T[i][r] = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            const double tau = beta[kb + i];
+            double u[NB];
+            for (int r = 0; r < i; ++r) {
+                double acc = 0.0;
+                for (int row = i; row < rows; ++row) acc += V[(size_t)row * NB + r] * V[(size_t)row * NB + i];
+                u[r] = acc;
+            }
+            for (int r = 0; r < i; ++r) {
+                double acc = 0.0;
+                for (int q = r; q < i; ++q) acc += T[r][q] * u[q];
+                T[r][i] = -tau * acc;
+            }
+            T[i][i] = tau;
+        }
+        // W = V^T Z[r0:, :]
+        std::fill(W.begin(), W.begin() + (size_t)nb * m, 0.0);
+        for (int row = 0; row < rows; ++row) {
+            const double* __restrict__ zr = Z + (size_t)(r0 + row) * m;
+            const int rmax = std::min(nb, row + 1);
+            for (int r = 0; r < rmax; ++r) {
+                const double vr = V[(size_t)row * NB + r];
+                double* __restrict__ wr = &W[(size_t)r * m];
+#pragma omp simd
+                for (int j = 0; j < m; ++j) wr[j] += vr * zr[j];
+            }
+        }
+        // W2 = T W
+        for (int r = 0; r < nb; ++r) {
+            double* __restrict__ w2 = &W2[(size_t)r * m];
+            for (int j = 0; j < m; ++j) w2[j] = 0.0;
+            for (int q = r; q < nb; ++q) {
+                const double tq = T[r][q];
+                const double* __restrict__ wq = &W[(size_t)q * m];
+#pragma omp simd
+                for (int j = 0; j < m; ++j) w2[j] += tq * wq[j];
+            }
+        }
+        // Z[r0:, :] -= V W2
+        for (int row = 0; row < rows; ++row) {
+            double* __restrict__ zr = Z + (size_t)(r0 + row) * m;
+            const int rmax = std::min(nb, row + 1);
+            for (int r = 0; r < rmax; ++r) {
+                const double vr = V[(size_t)row * NB + r];
+                const double* __restrict__ w2 = &W2[(size_t)r * m];
+#pragma omp simd
+                for (int j = 0; j < m; ++j) zr[j] -= vr * w2[j];
+            }
         }
     }
 }
