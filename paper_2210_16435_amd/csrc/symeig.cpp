@@ -4,7 +4,8 @@
 // Methods (Golub and Van Loan, Matrix Computations, Sections 8.3 and 8.2.2;
 // Wilkinson, The Algebraic Eigenvalue Problem, Ch. 9):
 //   * Householder reduction to tridiagonal form Q^T A Q = T (reflectors kept);
-//   * all eigenvalues of T by implicitly shifted QL iterations;
+//   * all eigenvalues of T by implicitly shifted QL iterations (root-free
+//     for the selective solver, with rotations for the full one);
 //   * eigenvectors of T for the m wanted eigenvalues only, by inverse
 //     iteration with a pivoted tridiagonal LU (several shifts in lockstep),
 //     re-orthogonalised within clusters of close eigenvalues; then
@@ -184,6 +185,57 @@ void tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, double* Z
     }
 }
 
+// Eigenvalues only: root-free implicit QL (Pal, Walker and Kahan; Parlett,
+// The Symmetric Eigenvalue Problem, Section 8.15).  The sweep carries the
+// squares of the off-diagonal entries, E[i] = e[i]^2, and of the rotation
+// cosines and sines, so no rotation takes a square root: with the shift
+// sigma, gamma_i = C_i (d_i - sigma) - S_i gamma_{i+1} is the running
+// diagonal remainder and P = gamma^2 / C the square of the entry the next
+// rotation eliminates.  The shift is the eigenvalue of the leading 2 x 2
+// closer to its first entry (one square root per sweep).
+void tridiag_ql_values(int n, std::vector<double>& d, std::vector<double>& e) {
+    std::vector<double> E(n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) E[i] = e[i] * e[i];
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        while (true) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (E[m] <= kEps * kEps * dd * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 60) break;
+            const double el = std::sqrt(E[l]);
+            const double g0 = (d[l + 1] - d[l]) / (2.0 * el);
+            const double r0 = pyth(g0, 1.0);
+            const double sigma = d[l] - el / (g0 + std::copysign(r0, g0));
+            double C = 1.0, S = 0.0;
+            double gamma = d[m] - sigma;
+            double P = gamma * gamma;
+            for (int i = m - 1; i >= l; --i) {
+                const double bb = E[i];
+                const double R = P + bb;
+                // 1 / C = R / P: the reciprocal of P is taken beside R's, so
+                // the next P needs no division after gamma
+                const double ip = 1.0 / P;
+                if (i != m - 1) E[i + 1] = S * R;
+                const double cold = C;
+                const double ir = 1.0 / R;
+                C = P * ir;
+                S = bb * ir;
+                const double gold = gamma;
+                const double alpha = d[i];
+                gamma = C * (alpha - sigma) - S * gold;
+                d[i + 1] = gold + (alpha - gamma);
+                P = C != 0.0 ? gamma * gamma * (R * ip) : cold * bb;
+            }
+            E[l] = S * P;
+            d[l] = sigma + gamma;
+        }
+    }
+}
+
 }  // namespace
 
 void sym_eig(int n, const double* A, double* w, double* Z) {
@@ -228,7 +280,7 @@ void SymEigSel::reduce(int n_, const double* A) {
     d.swap(t.d);
     e.swap(t.e);
     std::vector<double> dd = d, ee = e;
-    tridiag_ql(n, dd, ee, nullptr);
+    tridiag_ql_values(n, dd, ee);
     std::sort(dd.begin(), dd.end());
     w = dd;
     norm = 0.0;
