@@ -1058,7 +1058,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     if (b != 4 && b != 8 && b != 16 && b != 32) return set_error(SFAIRSC_E_ARG, "block width must be 4, 8, 16 or 32");
     while (b > 4 && 3 * b + k > dim) b /= 2;
     int ncv = o.max_basis;
-    if (ncv == 0) ncv = std::max(k + 6 * b, 4 * k + 2 * b);
+    if (ncv == 0) ncv = std::max(k + 8 * b, 4 * k + 2 * b);
     ncv = ((ncv + b - 1) / b) * b;
     ncv = std::min(ncv, kMaxBasis);
     while (ncv + 2 * b > dim && ncv > b) ncv -= b;
