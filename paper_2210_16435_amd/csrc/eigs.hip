@@ -29,6 +29,13 @@
 
 namespace sfairsc {
 
+// The float phase of a mixed solve stops at this relative residual (or at
+// the requested tolerance if that is looser); FP64 takes it from there.
+#ifndef SF_MIXED_TOL1
+#define SF_MIXED_TOL1 5e-7
+#endif
+constexpr double kMixedTol1 = SF_MIXED_TOL1;
+
 constexpr int kTsThreads = 256;
 constexpr int kTsRows = 8;
 constexpr int kTsAcc = (kLdMax * kMaxBlock + kTsThreads - 1) / kTsThreads;  // 28
@@ -1091,7 +1098,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     if (precision == SFAIRSC_PREC_MIXED) {
         auto t0 = std::chrono::steady_clock::now();
         S.mixed = true;
-        const double tol1 = std::max(tol, 5e-7);
+        const double tol1 = std::max(tol, kMixedTol1);
         SF_TRY(run_ks(S, tol1, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
         SF_TRY(ritz_vectors(S, R, Xr, nullptr));
         std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
