@@ -82,36 +82,70 @@ __global__ __launch_bounds__(kKmThreads) void k_chunk_sums(const double* __restr
 }
 
 // D^2 sampling: index of the first row whose inclusive prefix sum exceeds
-// u * total (total = sum of chunk sums, accumulated in chunk order).
-__global__ void k_pp_pick(const double* __restrict__ d2, const double* __restrict__ csum, int nchunks, int64_t n,
-                          double u, int64_t* __restrict__ idxp) {
-    if (threadIdx.x != 0) return;
-    double total = 0.0;
-    for (int c = 0; c < nchunks; ++c) total += csum[c];
+// u * total.  One wavefront: lane l sums a contiguous segment of the chunk
+// sums (total = the lanes' inclusive scan), the ballot of "prefix > target"
+// names the segment, a short scan the chunk; inside the chunk every lane
+// sums 16 consecutive rows and the same steps name the row.  Every order is
+// fixed, so the pick is reproducible; where rounding leaves no prefix above
+// the target, the last row of the range is taken.
+__global__ __launch_bounds__(64) void k_pp_pick(const double* __restrict__ d2, const double* __restrict__ csum,
+                                                int nchunks, int64_t n, double u, int64_t* __restrict__ idxp) {
+    const int lane = threadIdx.x;
+    const int S = (nchunks + 63) / 64;
+    const int c0 = min(nchunks, lane * S), c1 = min(nchunks, c0 + S);
+    double seg = 0.0;
+    for (int c = c0; c < c1; ++c) seg += csum[c];
+    double incl = seg;
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    const double total = __shfl(incl, 63);
     int64_t pick = (int64_t)(u * (double)n);
     if (pick >= n) pick = n - 1;
     if (total > 0.0) {
         const double target = u * total;
-        double acc = 0.0;
-        int c = 0;
-        for (; c < nchunks; ++c) {
-            if (acc + csum[c] > target) break;
-            acc += csum[c];
-        }
-        if (c == nchunks) {
+        const unsigned long long mseg = __ballot(incl > target);
+        if (mseg == 0) {
             pick = n - 1;
         } else {
-            const int64_t base = (int64_t)c * kChunk;
-            int64_t i = base;
-            const int64_t end = min(n, base + kChunk);
-            for (; i < end; ++i) {
-                acc += d2[i];
-                if (acc > target) break;
+            const int L = __builtin_ctzll(mseg);
+            double acc = __shfl(incl - seg, L);
+            const int s0 = min(nchunks, L * S), s1 = min(nchunks, s0 + S);
+            int c = s0;
+            for (; c + 1 < s1; ++c) {
+                const double v = csum[c];
+                if (acc + v > target) break;
+                acc += v;
             }
-            pick = i < end ? i : end - 1;
+            // chunk c: rows [base, end), 16 per lane
+            const int64_t base = (int64_t)c * kChunk;
+            const int64_t end = min(n, base + kChunk);
+            const int64_t e0 = min(end, base + 16 * lane), e1 = min(end, e0 + 16);
+            double part = 0.0;
+            for (int64_t i = e0; i < e1; ++i) part += d2[i];
+            double in2 = part;
+            for (int off = 1; off < 64; off <<= 1) {
+                const double t = __shfl_up(in2, off);
+                if (lane >= off) in2 += t;
+            }
+            const unsigned long long mrow = __ballot(acc + in2 > target);
+            if (mrow == 0) {
+                pick = end - 1;
+            } else {
+                const int L2 = __builtin_ctzll(mrow);
+                double a2 = acc + __shfl(in2 - part, L2);
+                const int64_t r0 = min(end, base + 16 * L2), r1 = min(end, r0 + 16);
+                int64_t i = r0;
+                for (; i < r1; ++i) {
+                    a2 += d2[i];
+                    if (a2 > target) break;
+                }
+                pick = i < r1 ? i : r1 - 1;
+            }
         }
     }
-    *idxp = pick;
+    if (lane == 0) *idxp = pick;
 }
 
 // Assignment: label_i = argmin_j ||H_i - c_j||^2; per-block changed count.
@@ -199,35 +233,57 @@ __global__ __launch_bounds__(1024) void k_update(const double* __restrict__ H, i
                                                  const double* __restrict__ part, const int* __restrict__ cpart,
                                                  int nb_sum, const double* __restrict__ mind,
                                                  double* __restrict__ cent, int* __restrict__ state, int max_iter) {
-    __shared__ int changed;
+    __shared__ int changed, iters;
     __shared__ int cnt[kMaxK];
     __shared__ double bestv[1024];
     __shared__ int64_t besti[1024];
     __shared__ int64_t used[kMaxK];
     if (state[0]) return;
+    // the counts are integers: shared atomics give the exact sums
+    if (threadIdx.x == 0) changed = 0;
+    if (threadIdx.x < K) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb_assign; b += blockDim.x) atomicAdd(&changed, changed_part[b]);
+    for (int o = threadIdx.x; o < nb_sum * K; o += blockDim.x) atomicAdd(&cnt[o % K], cpart[o]);
+    // the assignment count, read and advanced by one thread, shared with all
     if (threadIdx.x == 0) {
-        int c = 0;
-        for (int b = 0; b < nb_assign; ++b) c += changed_part[b];
-        changed = c;
-        state[1] += 1;
+        iters = state[1] + 1;
+        state[1] = iters;
     }
     __syncthreads();
-    if (changed == 0 || state[1] >= max_iter) {
+    if (changed == 0 || iters >= max_iter) {
         if (threadIdx.x == 0) state[0] = 1;
         return;
     }
-    if (threadIdx.x < K) {
-        int c = 0;
-        for (int b = 0; b < nb_sum; ++b) c += cpart[(size_t)b * K + threadIdx.x];
-        cnt[threadIdx.x] = c;
-    }
-    __syncthreads();
-    for (int o = threadIdx.x; o < K * kdim; o += blockDim.x) {
-        const int j = o / kdim;
-        if (cnt[j] > 0) {
-            double s = 0.0;
-            for (int b = 0; b < nb_sum; ++b) s += part[(size_t)b * K * kdim + o];
-            cent[o] = s / (double)cnt[j];
+    // centroid sums in a fixed order: P interleaved slices of the blocks per
+    // output (bestv as scratch), then the slices in order
+    const int O = K * kdim;
+    if (O <= (int)blockDim.x) {
+        const int P = blockDim.x / O;
+        const int t = threadIdx.x;
+        if (t < P * O) {
+            const int o = t % O, sl = t / O;
+            double s0 = 0.0;
+            for (int b = sl; b < nb_sum; b += P) s0 += part[(size_t)b * O + o];
+            bestv[t] = s0;
+        }
+        __syncthreads();
+        if (t < O) {
+            const int j = t / kdim;
+            if (cnt[j] > 0) {
+                double s0 = 0.0;
+                for (int sl = 0; sl < P; ++sl) s0 += bestv[sl * O + t];
+                cent[t] = s0 / (double)cnt[j];
+            }
+        }
+    } else {
+        for (int o = threadIdx.x; o < O; o += blockDim.x) {
+            const int j = o / kdim;
+            if (cnt[j] > 0) {
+                double s0 = 0.0;
+                for (int b = 0; b < nb_sum; ++b) s0 += part[(size_t)b * O + o];
+                cent[o] = s0 / (double)cnt[j];
+            }
         }
     }
     __syncthreads();
