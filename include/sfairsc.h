@@ -58,7 +58,8 @@ enum {
     SFAIRSC_E_EMPTY_GROUP = -3,   /* some group has no vertex (eq. groupdef)     */
     SFAIRSC_E_ISOLATED = -4,      /* d_i = 0 with normalized = 1 (D must be p.d.) */
     SFAIRSC_E_NOT_CONVERGED = -5, /* outputs hold the best current pairs         */
-    SFAIRSC_E_DEGENERATE = -6,    /* reserved                                    */
+    SFAIRSC_E_DEGENERATE = -6,    /* theta_k ~ theta_{k+1}: outputs written, the
+                                     k-dimensional subspace is not determined   */
     SFAIRSC_E_HIP = -7,           /* a HIP runtime call failed                   */
     SFAIRSC_E_NOMEM = -8          /* device allocation failed                    */
 };
@@ -254,6 +255,9 @@ typedef struct sfairsc_eigs_info {
        their orthogonalisation (CGS2 + Cholesky-QR) and the restart
        rotations; 0 otherwise */
     double operator_ms, ortho_ms, restart_ms;
+    int32_t degenerate;        /* 1: gap_ratio <= 100 tol (the status is then
+                                  SFAIRSC_E_DEGENERATE unless not converged) */
+    int32_t reserved;
 } sfairsc_eigs_info;
 
 /* Fill *opts with the defaults (all automatic, seed 0, certify 1). */
@@ -277,7 +281,12 @@ void sfairsc_eigs_opts_init(sfairsc_eigs_opts* opts);
  *          index on ties).
  * info     may be NULL.
  * Synchronises `stream`.  Returns SFAIRSC_E_NOT_CONVERGED (outputs and info
- * still written: the best current pairs) if max_restarts is reached.  The
+ * still written: the best current pairs) if max_restarts is reached, else
+ * SFAIRSC_E_DEGENERATE (outputs and info written, info->degenerate = 1) when
+ * the relative gap (theta_{k+1} - theta_k) / sigma of the last Rayleigh-Ritz
+ * step is at most 100 tol: Proposition 3.3 and any subspace-angle bound need
+ * lambda_k < lambda_{k+1}, so the returned k vectors are one basis of a
+ * subspace that is not determined (a multiple eigenvalue split by k).  The
  * handle keeps its workspace for later calls (no allocation after the
  * first call of a given shape).  Errors also: E_ARG, E_NOMEM, E_HIP.
  */
@@ -291,7 +300,8 @@ int sfairsc_eigs(sfairsc_graph_t g, int32_t k, double tol, int precision,
  * Per-graph outcome of sfairsc_eigs_batched.
  */
 typedef struct sfairsc_batch_info {
-    int32_t status;        /* SFAIRSC_OK or SFAIRSC_E_NOT_CONVERGED          */
+    int32_t status;        /* SFAIRSC_OK, SFAIRSC_E_NOT_CONVERGED or
+                              SFAIRSC_E_DEGENERATE (gap_ratio <= 100 tol)   */
     int32_t path;          /* 0: solved in the batched launch;
                               1: solved by sfairsc_eigs (the launch could
                               not take the graph or did not finish it)      */
@@ -359,7 +369,8 @@ typedef struct sfairsc_batch_info {
  * their current Ritz vectors.  The library keeps a per-device
  * workspace between calls: calls on one device must not overlap.
  * Synchronises `stream`.  Returns SFAIRSC_OK, SFAIRSC_E_NOT_CONVERGED (some
- * graph's status), E_ARG, E_NOMEM or E_HIP.
+ * graph's status), else SFAIRSC_E_DEGENERATE (some graph's status; all
+ * outputs written), or E_ARG, E_NOMEM, E_HIP.
  */
 int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count,
                          const int32_t* k, double tol, int precision,

@@ -72,16 +72,17 @@ def validate_graph(W, groups, h, k=None, normalized=False):
     n = W.shape[0]
     if W.shape != (n, n):
         raise ValueError("W must be square")
-    if (W - W.T).count_nonzero() != 0 and abs(W - W.T).max() != 0:
-        raise ValueError("W is not symmetric")
-    if W.nnz and W.data.min() < 0:
-        raise ValueError("negative weight")
+    # finiteness first: a NaN makes every later comparison meaningless
     if not np.all(np.isfinite(W.data)):
         raise ValueError("non-finite weight")
+    if W.nnz and W.data.min() < 0:
+        raise ValueError("negative weight")
+    if abs(W - W.T).max() != 0:
+        raise ValueError("W is not symmetric")
     if np.any(W.diagonal() != 0):
         raise ValueError("non-zero diagonal")
     g = np.asarray(groups)
-    if g.shape != (n,) or g.min() < 0 or g.max() >= h:
+    if g.shape != (n,) or n == 0 or g.min() < 0 or g.max() >= h:
         raise ValueError("group labels out of range")
     if np.bincount(g, minlength=h).min() == 0:
         raise ValueError("empty group")

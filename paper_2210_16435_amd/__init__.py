@@ -14,6 +14,7 @@ raises ImportError when the library is missing; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import warnings
 from dataclasses import dataclass
 from typing import Optional
 
@@ -24,6 +25,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     E_ARG,
     E_ASYM,
+    E_DEGENERATE,
     E_EMPTY_GROUP,
     E_HIP,
     E_ISOLATED,
@@ -242,9 +244,15 @@ class Graph:
         x0: Optional[torch.Tensor] = None,
         H_out: Optional[torch.Tensor] = None,
         raise_not_converged: bool = True,
+        raise_degenerate: bool = False,
         stream=None,
     ) -> EigsResult:
-        """The k smallest fair eigenpairs (Alg. 3 step 3)."""
+        """The k smallest fair eigenpairs (Alg. 3 step 3).
+
+        A converged solve whose theta_k and theta_{k+1} coincide to the
+        tolerance returns with `code == E_DEGENERATE` and a warning (or raises
+        with raise_degenerate=True): the k-dimensional subspace is then not
+        determined."""
         opts = _lib.EigsOpts()
         _lib.lib().sfairsc_eigs_opts_init(ctypes.byref(opts))
         opts.block_width = block_width
@@ -269,8 +277,10 @@ class Graph:
             self._h, k, float(tol), _prec(precision), ctypes.byref(opts), ev, _ptr(buf), ctypes.byref(info),
             _stream(stream)
         )
-        allow = () if raise_not_converged else (E_NOT_CONVERGED,)
+        allow = _allowed(raise_not_converged, raise_degenerate)
         _lib.check(code, allow=allow)
+        if code == E_DEGENERATE:
+            warnings.warn(_lib.lib().sfairsc_last_error().decode(errors="replace"), RuntimeWarning, stacklevel=2)
         return EigsResult(np.array(ev[:]), buf.t(), info.as_dict(), code)
 
     # -- clustering ------------------------------------------------------
@@ -309,6 +319,15 @@ class Graph:
 
 
 # -- batched solves ---------------------------------------------------------
+def _allowed(raise_not_converged: bool, raise_degenerate: bool):
+    allow = ()
+    if not raise_not_converged:
+        allow += (E_NOT_CONVERGED,)
+    if not raise_degenerate:
+        allow += (E_DEGENERATE,)
+    return allow
+
+
 def _handles(graphs):
     arr = (ctypes.c_void_p * len(graphs))()
     for i, g in enumerate(graphs):
@@ -329,10 +348,12 @@ def eigs_batched(
     certify: bool = True,
     H_out=None,
     raise_not_converged: bool = True,
+    raise_degenerate: bool = False,
     stream=None,
 ):
     """The k[i] smallest fair eigenpairs of every graph in one persistent
-    launch -> list of EigsResult (info: the per-graph batch record)."""
+    launch -> list of EigsResult (info: the per-graph batch record; a graph
+    with theta_k ~ theta_{k+1} has status E_DEGENERATE)."""
     graphs = list(graphs)
     cnt = len(graphs)
     if isinstance(k, int):
@@ -359,8 +380,10 @@ def eigs_batched(
         _handles(graphs), cnt, karr, float(tol), _prec(precision), ctypes.byref(opts), evp, Hp, infos,
         _stream(stream)
     )
-    allow = () if raise_not_converged else (E_NOT_CONVERGED,)
+    allow = _allowed(raise_not_converged, raise_degenerate)
     _lib.check(code, allow=allow)
+    if code == E_DEGENERATE:
+        warnings.warn(_lib.lib().sfairsc_last_error().decode(errors="replace"), RuntimeWarning, stacklevel=2)
     return [
         EigsResult(np.array(evs[i][:]), H_out[i].t(), infos[i].as_dict(), infos[i].status) for i in range(cnt)
     ]

@@ -92,6 +92,8 @@ class EigsInfo(ctypes.Structure):
         ("operator_ms", ctypes.c_double),
         ("ortho_ms", ctypes.c_double),
         ("restart_ms", ctypes.c_double),
+        ("degenerate", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -111,6 +113,7 @@ class EigsInfo(ctypes.Structure):
             "operator_ms": self.operator_ms,
             "ortho_ms": self.ortho_ms,
             "restart_ms": self.restart_ms,
+            "degenerate": self.degenerate,
         }
 
 

@@ -1638,6 +1638,26 @@ struct BatchWork {
 std::mutex g_bw_mu;
 BatchWork g_bw[64];
 
+}  // namespace
+
+void batched_release_workspaces() {
+    std::lock_guard<std::mutex> lk(g_bw_mu);
+    for (BatchWork& w : g_bw) {
+        w.big.release();
+        w.meta.release();
+        w.x0.release();
+        if (w.pin) (void)hipHostFree(w.pin);
+        w.pin = nullptr;
+        w.pin_bytes = 0;
+        if (w.e0) (void)hipEventDestroy(w.e0);
+        if (w.e1) (void)hipEventDestroy(w.e1);
+        w.e0 = w.e1 = nullptr;
+        w.cus = 0;  // the next launch re-creates the events
+    }
+}
+
+namespace {
+
 struct RunItem {
     sfairsc_graph* g;
     int k;
@@ -2118,15 +2138,23 @@ extern "C" int sfairsc_eigs_batched(const sfairsc_graph_t* graphs, int32_t count
             inf.gap_ratio = si.gap_ratio;
             inf.sigma = si.sigma;
             inf.status = r;
-            if (r != SFAIRSC_OK && r != SFAIRSC_E_NOT_CONVERGED) {
+            if (r != SFAIRSC_OK && r != SFAIRSC_E_NOT_CONVERGED && r != SFAIRSC_E_DEGENERATE) {
                 if (infos) infos[i] = inf;
                 return r;
             }
             if (r == SFAIRSC_E_NOT_CONVERGED) ret = SFAIRSC_E_NOT_CONVERGED;
         }
+        // a graph converged in the launch whose theta_k and theta_{k+1}
+        // coincide to the tolerance: the k-dimensional subspace is not
+        // determined (the single-graph solver sets this status itself)
+        if (!need_single && inf.status == SFAIRSC_OK && inf.gap_ratio <= kDegenerateGap * tol)
+            inf.status = SFAIRSC_E_DEGENERATE;
+        if (inf.status == SFAIRSC_E_DEGENERATE && ret == SFAIRSC_OK) ret = SFAIRSC_E_DEGENERATE;
         if (infos) infos[i] = inf;
     }
-    if (ret != SFAIRSC_OK) set_error(ret, "some graphs did not converge (see their status)");
+    if (ret == SFAIRSC_E_NOT_CONVERGED) set_error(ret, "some graphs did not converge (see their status)");
+    if (ret == SFAIRSC_E_DEGENERATE)
+        set_error(ret, "some graphs have theta_k ~ theta_{k+1} to the tolerance (see their status)");
     return ret;
 }
 

@@ -1179,12 +1179,25 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     SF_HIP(hipGetLastError());
     SF_TRY(S.sync());
     for (int i = 0; i < k; ++i) eigvals[i] = th[i];
+    // The wanted subspace is well defined only with a gap after theta_k
+    // (Proposition 3.3 and the angle bound need lambda_k < lambda_{k+1}):
+    // a relative gap at the tolerance level is flagged, outputs still written.
+    const bool gap_known = R.c > k;
+    const double gap = gap_known ? (R.theta[k] - R.theta[k - 1]) / S.sigma : 0.0;
+    const bool degenerate = gap_known && gap <= kDegenerateGap * tol;
     if (info) {
         info->max_rel_residual = worst;
         info->converged = nconv;
+        info->gap_ratio = gap;
+        info->degenerate = degenerate ? 1 : 0;
     }
     if (nconv < k) return set_error(SFAIRSC_E_NOT_CONVERGED, "%d of %d pairs converged (worst rel. residual %.3e)",
                                     nconv, k, worst);
+    if (degenerate)
+        return set_error(SFAIRSC_E_DEGENERATE,
+                         "theta_k and theta_{k+1} coincide to the tolerance (relative gap %.3e <= %g tol): the "
+                         "k-dimensional subspace is not determined",
+                         gap, kDegenerateGap);
     return SFAIRSC_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 
+#include <atomic>
+
 #include "internal.h"
 
 namespace sfairsc {
@@ -209,6 +211,8 @@ static bool spd_inverse(int m, const std::vector<double>& A, std::vector<double>
     }
     return true;
 }
+
+static std::atomic<int> g_live_graphs{0};
 
 static void free_graph(sfairsc_graph* g) {
     if (!g) return;
@@ -461,6 +465,7 @@ extern "C" int sfairsc_graph_create(sfairsc_graph_t* out, int64_t n, int64_t nnz
         free_graph(g);
         return r;
     }
+    g_live_graphs.fetch_add(1);
     *out = g;
     return SFAIRSC_OK;
 }
@@ -469,6 +474,10 @@ extern "C" void sfairsc_graph_destroy(sfairsc_graph_t g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
     free_graph(g);
+    // The library's process-wide workspaces (batched launches) live while
+    // any handle does: freed with the last one, so nothing of the library
+    // is left for the runtime's own teardown at exit.
+    if (g_live_graphs.fetch_sub(1) == 1) batched_release_workspaces();
 }
 
 extern "C" int sfairsc_graph_query(sfairsc_graph_t g, sfairsc_graph_stats* out) {

@@ -20,6 +20,9 @@ constexpr int kMaxGroups = 32;    // h
 constexpr int kMaxBasis = 192;    // Krylov basis columns before a restart
 constexpr int kMaxK = 64;         // wanted eigenpairs / k-means dimension
 constexpr int kLdMax = kMaxBasis + kMaxBlock;  // basis leading dimension
+// A relative gap (theta_{k+1} - theta_k) / sigma at most this multiple of the
+// tolerance marks the k-dimensional eigenspace as not determined.
+constexpr double kDegenerateGap = 100.0;
 
 int set_error(int code, const char* fmt, ...);
 
@@ -191,6 +194,10 @@ int lsqr_correct(sfairsc_graph* g, const void* T, bool t_float, int BW, int b, d
                  hipStream_t s, const int* skip);
 int lsqr_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
 void free_memb(sfairsc_graph* g);
+
+// Free the per-device workspaces of batched launches (device buffers, pinned
+// host buffer, events).  Called when the last graph handle is destroyed.
+void batched_release_workspaces();
 
 // The operator up to (not including) the output deflation: projection, SpMM
 // with its C^T T epilogue and the deflation table.  Y = T - C R_out (row i:

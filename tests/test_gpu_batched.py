@@ -55,8 +55,10 @@ def _check(g, k, norm, r, sigma, tol, lam_ref, H_ref, rtol, atol_angle):
     assert np.abs(F.T @ H).max() <= 1e-10 * np.sqrt(g.n) * np.abs(H).max()
     M = H.T @ (d[:, None] * H) if norm else H.T @ H
     assert np.abs(M - np.eye(k)).max() <= 1e-9
+    # returned pairs meet tol on the library's FP64 residual, which for
+    # vectors in null(C^T) equals the oracle's: only rounding separates them
     res = oracle.residual_norms(W, g.groups, g.h, norm, lam, H)
-    assert res.max() <= 4 * tol * sigma + 1e-12 * sigma, res.max() / sigma
+    assert res.max() <= tol * sigma + 2e-12 * sigma, res.max() / sigma
     err = eig_parity(lam, lam_ref[:k], rtol)
     assert err <= rtol, err
     gap = (lam_ref[k] - lam_ref[k - 1]) / sigma
@@ -191,12 +193,30 @@ def test_batched_workload_256():
     rs = sf.eigs_batched(Gs, ks, tol=1e-6, precision="mixed")
     paths = [r.info["path"] for r in rs]
     log(f"  launch ms {rs[0].info['batch_ms']:.2f}, graphs solved in the launch {paths.count(0)}")
-    assert all(r.status == 0 for r in rs)
+    assert all(r.status in (sf.OK, sf.E_DEGENERATE) for r in rs), [r.status for r in rs]
+    log(f"  degenerate (theta_k ~ theta_k+1): {sum(r.status == sf.E_DEGENERATE for r in rs)}")
     # every graph finished in the launch except the last few, handed off
     # (batch_status 5) to the single-graph solver with a warm start
     off = [i for i, r in enumerate(rs) if r.info["path"] != 0]
     assert len(off) <= 3 and all(rs[i].info["batch_status"] == 5 for i in off), [(i, rs[i].info) for i in off]
-    assert max(r.info["max_rel_residual"] for r in rs) <= 1e-6
+    # every member against the oracle's residual and the fairness and
+    # orthonormality constraints (not the library's own residual figure)
+    worst = 0.0
+    for i, (g, k, r) in enumerate(zip(graphs, ks, rs)):
+        W = g.to_scipy()
+        H = to_np(r.H)
+        lam = r.eigenvalues
+        sigma = Gs[i].sigma
+        assert np.all(np.diff(lam) >= -1e-12 * sigma), i
+        F = oracle.fairness_matrix(g.groups, g.h)
+        assert np.abs(F.T @ H).max() <= 1e-10 * np.sqrt(g.n) * np.abs(H).max(), i
+        assert np.abs(H.T @ H - np.eye(k)).max() <= 1e-9, i
+        res = oracle.residual_norms(W, g.groups, g.h, False, lam, H)
+        worst = max(worst, res.max() / sigma)
+        assert res.max() <= 1e-6 * sigma + 2e-12 * sigma, (i, res.max() / sigma)
+    log(f"  all 256: worst oracle residual / sigma {worst:.2e}")
+    # eigenvalues against the implicit-nullspace oracle on a sample (the
+    # smallest and largest graphs, four at random and the handed-off ones)
     handed = set(off)
     order = np.argsort([g.n for g in graphs])
     rng = np.random.default_rng(3)
@@ -206,7 +226,5 @@ def test_batched_workload_256():
         g, k, r = graphs[i], ks[i], rs[i]
         lam_ref, _ = oracle.fair_eigs_implicit(g.to_scipy(), g.groups, g.h, k, False, tol=1e-12)
         err = eig_parity(r.eigenvalues, lam_ref, 1e-5)
-        res = oracle.residual_norms(g.to_scipy(), g.groups, g.h, False, r.eigenvalues, to_np(r.H))
-        log(f"  graph {i}: n={g.n} k={k} h={g.h} eig rel err {err:.2e} res/sigma {res.max() / Gs[i].sigma:.2e}")
+        log(f"  graph {i}: n={g.n} k={k} h={g.h} eig rel err {err:.2e}")
         assert err <= 1e-5
-        assert res.max() <= 4e-6 * Gs[i].sigma

@@ -106,3 +106,95 @@ def test_bad_solver_arguments():
     with pytest.raises(sf.SfairscError) as e:
         G.eigs(4, block_width=5)
     assert e.value.code == sf.E_ARG
+
+
+# --- the library rejects exactly the inputs the oracle's validation rejects ---
+
+
+def _scipy(rp, ci, va, n=200):
+    import scipy.sparse as sp
+
+    return sp.csr_matrix((np.asarray(va, np.float64), ci, rp), shape=(n, n))
+
+
+def _case(name):
+    rp, ci, va, gr = _base()
+    normalized = False
+    if name == "asym_value":
+        va[5] += 0.25
+    elif name == "asym_pattern":
+        # drop the mirror of one stored entry: (i, j) kept, (j, i) removed
+        i = 3
+        j = int(ci[rp[i]])
+        rows = np.repeat(np.arange(200), np.diff(rp))
+        pos = np.nonzero((rows == j) & (ci == i))[0][0]
+        keep = np.ones(ci.size, bool)
+        keep[pos] = False
+        ci, va, rows = ci[keep], va[keep], rows[keep]
+        rp = np.zeros(201, np.int32)
+        np.cumsum(np.bincount(rows, minlength=200), out=rp[1:])
+    elif name in ("negative", "nan", "inf"):
+        bad = {"negative": -1.0, "nan": np.nan, "inf": np.inf}[name]
+        i = 3
+        j = int(ci[rp[i]])
+        rows = np.repeat(np.arange(200), np.diff(rp))
+        va[rp[i]] = bad
+        va[np.nonzero((rows == j) & (ci == i))[0][0]] = bad  # both copies: symmetric
+    elif name == "diagonal":
+        # insert a stored w_77 = 1
+        rows = np.repeat(np.arange(200), np.diff(rp))
+        rows = np.append(rows, 7)
+        ci = np.append(ci, 7).astype(np.int32)
+        va = np.append(va, 1.0)
+        o = np.lexsort((ci, rows))
+        rows, ci, va = rows[o], ci[o], va[o]
+        rp = np.zeros(201, np.int32)
+        np.cumsum(np.bincount(rows, minlength=200), out=rp[1:])
+    elif name == "label":
+        gr[0] = 7
+    elif name == "empty_group":
+        gr[gr == 2] = 1
+    elif name == "isolated_normalized":
+        rows = np.repeat(np.arange(200), np.diff(rp))
+        keep = (rows != 0) & (ci != 0)
+        rows, ci, va = rows[keep], ci[keep], va[keep]
+        rp = np.zeros(201, np.int32)
+        np.cumsum(np.bincount(rows, minlength=200), out=rp[1:])
+        normalized = True
+    return rp, ci.astype(np.int32), va, gr, normalized
+
+
+@pytest.mark.parametrize("name", ["valid", "asym_value", "asym_pattern", "negative", "nan", "inf", "diagonal",
+                                  "label", "empty_group", "isolated_normalized"])
+def test_rejects_what_the_oracle_rejects(name):
+    import oracle
+
+    sf = lib()
+    rp, ci, va, gr, normalized = _case(name)
+    try:
+        oracle.validate_graph(_scipy(rp, ci, va), gr, 3, normalized=normalized)
+        oracle_ok = True
+    except ValueError:
+        oracle_ok = False
+    try:
+        G = _create(sf, rp, ci, va, gr, normalized=normalized)
+        G.close()
+        lib_ok = True
+    except sf.SfairscError:
+        lib_ok = False
+    assert oracle_ok == lib_ok == (name == "valid"), (name, oracle_ok, lib_ok)
+
+
+def test_k_bound_matches_the_oracle():
+    import oracle
+
+    sf = lib()
+    rp, ci, va, gr = _base()
+    W = _scipy(rp, ci, va)
+    G = _create(sf, rp, ci, va, gr)
+    for k in (0, 200 - 3 + 2):
+        with pytest.raises(ValueError, match="k out of range"):
+            oracle.validate_graph(W, gr, 3, k=k)
+        with pytest.raises(sf.SfairscError) as e:
+            G.eigs(k)
+        assert e.value.code == sf.E_ARG

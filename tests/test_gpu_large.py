@@ -40,7 +40,8 @@ def _fair_checks(g, lam, H, sigma, tol):
     assert np.abs(H.T @ H - np.eye(k)).max() <= 1e-9
     res = oracle.residual_norms(W, g.groups, g.h, False, lam, H)
     log(f"  max residual / sigma {res.max() / sigma:.2e}")
-    assert res.max() <= 4 * tol * sigma
+    # the library's FP64 residual of a vector in null(C^T) is the oracle's
+    assert res.max() <= tol * sigma + 2e-12 * sigma
 
 
 def test_msbm_2m_mixed_full_size():

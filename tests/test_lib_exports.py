@@ -20,9 +20,9 @@ def _declared():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_2210_16435_amd.build import build
+        import __graft_entry__
 
-        build()
+        __graft_entry__.build()
     return ctypes.CDLL(LIB)
 
 
