@@ -248,8 +248,11 @@ typedef struct sfairsc_eigs_info {
     double gap_ratio;          /* (theta_{k+1} - theta_k) / sigma, last RR */
     double phase1_ms;          /* mixed precision: host wall time of the
                                   FP32-SpMM phase; 0 otherwise             */
-    double rr_ms;              /* host time spent in Rayleigh-Ritz (small
-                                  dense eigensolves), all phases           */
+    double rr_ms;              /* time_kernels: GPU time of the Rayleigh-
+                                  Ritz kernels (small dense eigensolves on
+                                  a second stream, beside the look-ahead
+                                  operator application), all phases; 0
+                                  otherwise                                 */
     /* time_kernels: summed GPU time between event pairs around the block
        steps' operator applications (projections, sparse product, C^T T),
        their orthogonalisation (CGS2 + Cholesky-QR) and the restart
@@ -460,6 +463,24 @@ int sfairsc_eigsum_backward(sfairsc_graph_t g, const double* H, int32_t k,
                             hipStream_t stream);
 
 /* ---- diagnostics ------------------------------------------------------ */
+
+/*
+ * The small dense symmetric eigensolver of the Rayleigh-Ritz step that the
+ * eigensolver runs at every restart (Alg. 3 step 3: the eigenpairs of the
+ * projected matrix), exposed for validation: all eigenvalues of the
+ * symmetric c x c matrix T and the eigenvectors of its m smallest, in FP64
+ * on the device (one workgroup: Householder tridiagonalisation, Sturm-count
+ * multisection, inverse iteration, back-transformation).
+ * T   device double, row-major c x c with leading dimension ldt >= c; the
+ *     two triangles are averaged (T is meant to be symmetric).
+ * w   device double[c], ascending.
+ * Z   device double, row-major c x m: column j is the unit eigenvector of
+ *     w[j] (may be NULL when m = 0).
+ * 1 <= c <= 192, 0 <= m <= c.  Allocates its scratch and synchronises
+ * `stream`.  Errors: E_ARG, E_NOMEM, E_HIP.
+ */
+int sfairsc_symeig(const double* T, int32_t c, int32_t ldt, int32_t m,
+                   double* w, double* Z, hipStream_t stream);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char* sfairsc_last_error(void);

@@ -51,3 +51,4 @@ from .general_f import (  # noqa: F401
     apply_deflated_operator_general,
 )
 from .lsqr import lsqr, project_lsqr, membership_constraint_matrix  # noqa: F401
+from .ritz import ritz_pairs, krylov_schur_keep  # noqa: F401

@@ -48,6 +48,7 @@ __all__ = [
     "tuning_lookup",
     "EigsResult",
     "FairEigSum",
+    "symeig",
     "SfairscError",
     "version",
     "PREC_FP64",
@@ -319,6 +320,23 @@ class Graph:
 
 
 # -- batched solves ---------------------------------------------------------
+def symeig(T: torch.Tensor, m: Optional[int] = None, stream=None):
+    """Eigenvalues (ascending) and the eigenvectors of the m smallest of a
+    small symmetric matrix (order <= 192) with the Rayleigh-Ritz kernel of the
+    eigensolver (diagnostic) -> (w, Z), Z of shape (c, m)."""
+    if T.dim() != 2 or T.shape[0] != T.shape[1]:
+        raise ValueError("T must be square")
+    c = T.shape[0]
+    m = c if m is None else int(m)
+    Td = T.to(torch.float64).contiguous()
+    if not Td.is_cuda:
+        raise ValueError("T must be a device tensor")
+    w = torch.empty(c, dtype=torch.float64, device=Td.device)
+    Z = torch.empty((c, max(m, 1)), dtype=torch.float64, device=Td.device)
+    _lib.check(_lib.lib().sfairsc_symeig(_ptr(Td), c, c, m, _ptr(w), _ptr(Z), _stream(stream)))
+    return w, Z[:, :m]
+
+
 def _allowed(raise_not_converged: bool, raise_degenerate: bool):
     allow = ()
     if not raise_not_converged:

@@ -180,6 +180,7 @@ PROTOTYPES = {
     ),
     "sfairsc_labels": (_int, [_vp, _vp, _i32, _i32, _i32, ctypes.c_uint64, _i32, _vp, ctypes.POINTER(_dbl), _vp]),
     "sfairsc_eigsum_backward": (_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "sfairsc_symeig": (_int, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
     "sfairsc_last_error": (ctypes.c_char_p, []),
     "sfairsc_version": (ctypes.c_char_p, []),
 }

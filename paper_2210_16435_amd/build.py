@@ -19,9 +19,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsfairsc.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["graph.hip", "operator.hip", "general.hip", "lsqr.hip", "ortho.hip", "eigs.hip", "kmeans.hip", "backward.hip",
-               "batched.hip"]
-CXX_SOURCES = ["symeig.cpp"]
+HIP_SOURCES = ["graph.hip", "operator.hip", "general.hip", "lsqr.hip", "ortho.hip", "rr.hip", "eigs.hip", "kmeans.hip",
+               "backward.hip", "batched.hip"]
+CXX_SOURCES = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = [

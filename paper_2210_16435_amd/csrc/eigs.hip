@@ -14,7 +14,7 @@
 //     T[0:c+b, c:c+b] = H1 + H2 (and its mirror)
 //     Y = Q R via Cholesky-QR twice      (Gram Y^T Y -> R1, Y R1^{-1}, again)
 // Row-major storage lets every tall-skinny product read each basis row once,
-// contiguously.  After ncv columns: Rayleigh-Ritz on T_c (host, FP64), the
+// contiguously.  After ncv columns: Rayleigh-Ritz on T_c (GPU, FP64, rr.hip), the
 // residual of Ritz pair i is ||R Z[c-b:c, i]||, and the p smallest Ritz
 // vectors are kept (V <- V Z[:, 0:p]) with T_p = diag(theta).
 //
@@ -331,14 +331,6 @@ __global__ void k_zero_i32(int* __restrict__ X, int count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) X[i] = 0;
 }
 
-// Tc (c x c, contiguous) = T[0:c, 0:c] (leading dimension ldt).
-__global__ void k_pack(const double* __restrict__ T, int ldt, int c, double* __restrict__ Tc) {
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < c * c; idx += gridDim.x * blockDim.x) {
-        int i = idx / c, j = idx - i * c;
-        Tc[idx] = T[(size_t)i * ldt + j];
-    }
-}
-
 // T[0:p, 0:p] = diag(theta).
 __global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta) {
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * p; idx += gridDim.x * blockDim.x) {
@@ -446,13 +438,21 @@ struct Solver {
     std::vector<hipEvent_t> pev;
     std::vector<int> pkind;
     size_t pev_used = 0;
-    hipEvent_t ev_rr = nullptr;  // the Rayleigh-Ritz inputs have reached the host
+    // Rayleigh-Ritz kernel buffers, its stream and (timing mode) its events
+    RrBufs rb{};
+    hipStream_t s2 = nullptr;
+    std::vector<hipEvent_t> rr_evs;
+    size_t rr_ev_used = 0;
     sfairsc_eigs_info* info = nullptr;
     double thresh = 0.0;
 
     int setup() {
         EigWork& w = g->eig;
-        if (!ev_rr) SF_HIP(hipEventCreateWithFlags(&ev_rr, hipEventDisableTiming));
+        if (!w.s2) SF_HIP(hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking));
+        if (!w.ev_fork) SF_HIP(hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming));
+        if (!w.ev_join) SF_HIP(hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming));
+        s2 = w.s2;
+        SF_TRY(rr_buffers(g, &rb));
         ld = ncv + b;
         SF_TRY(w.V.ensure((size_t)n * ld * sizeof(double)));
         SF_TRY(w.V2.ensure((size_t)n * ld * sizeof(double)));
@@ -750,6 +750,12 @@ struct Solver {
         }
         info->spmm_ms[mixed ? 1 : 0] += tot;
         ev_used = 0;
+        for (size_t i = 0; i + 1 < rr_ev_used; i += 2) {
+            float ms = 0.f;
+            SF_HIP(hipEventElapsedTime(&ms, rr_evs[i], rr_evs[i + 1]));
+            info->rr_ms += ms;
+        }
+        rr_ev_used = 0;
         for (size_t i = 0; i + 1 < pev_used; i += 2) {
             float ms = 0.f;
             SF_HIP(hipEventElapsedTime(&ms, pev[i], pev[i + 1]));
@@ -760,10 +766,54 @@ struct Solver {
         return SFAIRSC_OK;
     }
 
+    // The Rayleigh-Ritz step on the projected matrix T[0:c, 0:c], enqueued on
+    // the second stream after everything on the solve's stream so far; the
+    // caller joins the streams (ev_join) before it reads the results.
+    int rayleigh_ritz(int c, double tol, int keep_opt) {
+        EigWork& w = g->eig;
+        SF_HIP(hipEventRecord(w.ev_fork, s));
+        SF_HIP(hipStreamWaitEvent(s2, w.ev_fork, 0));
+        if (timing) {
+            if (rr_ev_used + 2 > rr_evs.size()) {
+                for (int i = 0; i < 16; ++i) {
+                    hipEvent_t e;
+                    SF_HIP(hipEventCreate(&e));
+                    rr_evs.push_back(e);
+                }
+            }
+            SF_HIP(hipEventRecord(rr_evs[rr_ev_used], s2));
+        }
+        RrArgs a;
+        a.T = T;
+        a.ldt = ld;
+        a.c = c;
+        a.skip = flag;
+        a.work = rb.work;
+        a.mode = 0;
+        a.Rc = Rc;
+        a.b = b;
+        a.k = k;
+        a.ncv = ncv;
+        a.keep = keep_opt;
+        a.tol = tol;
+        a.sigma = sigma;
+        a.theta = rb.theta;
+        a.Qch = Q;
+        a.Zk = rb.zk;
+        a.rec = rb.rec;
+        SF_TRY(rr_launch(a, s2));
+        if (timing) {
+            SF_HIP(hipEventRecord(rr_evs[rr_ev_used + 1], s2));
+            rr_ev_used += 2;
+        }
+        SF_HIP(hipEventRecord(w.ev_join, s2));
+        return SFAIRSC_OK;
+    }
+
     ~Solver() {
         for (auto e : evs) (void)hipEventDestroy(e);
         for (auto e : pev) (void)hipEventDestroy(e);
-        if (ev_rr) (void)hipEventDestroy(ev_rr);
+        for (auto e : rr_evs) (void)hipEventDestroy(e);
     }
 };
 
@@ -795,6 +845,7 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int sta
         return S.sync();
     };
     std::vector<double> G, G2, U(b * b), w(b);
+    // the b x b Gram, still in S.H1 after gram(), diagonalised on the device
     if (stage == 2) {
         std::vector<double> R1(b * b);
         SF_TRY(S.download(R1.data(), ortho_r1(S.g->eig.osmall.as<double>()), b * b * sizeof(double)));
@@ -804,7 +855,7 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int sta
     } else {
         SF_TRY(gram(S.identity(), G));
     }
-    sym_eig(b, G.data(), w.data(), U.data());
+    SF_TRY(small_eig_host(S.g, S.H1, b, b, w.data(), U.data(), S.s));
     // W <- W U; the diagonal of the rotated block's Gram: column norms^2
     SF_TRY(S.upload(S.Q, U.data(), b * b * sizeof(double)));
     SF_TRY(gram(S.Q, G2));
@@ -867,15 +918,16 @@ static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int sta
 }
 
 struct KsResult {
-    std::vector<double> theta;  // Ritz values of the last Rayleigh-Ritz
-    std::vector<double> res;    // residual estimates
-    std::vector<double> Z;      // c x m Ritz vectors (row-major), m >= k
+    std::vector<double> theta;  // theta[0:k] of the last Rayleigh-Ritz step
+    std::vector<double> res;    // their residual estimates
+    double gap = 0.0;           // (theta_{k+1} - theta_k) / sigma (0 when c <= k)
     int c = 0, m = 0;
     bool converged = false;
 };
 
 // One Krylov-Schur run.  On return the basis V and KsResult describe the
-// final Rayleigh-Ritz: Ritz vectors = V[:, 0:c] Z[:, i].
+// final Rayleigh-Ritz step; its first k Ritz vectors' coefficients Z[:, 0:k]
+// (c x k) are in S.rb.zk on the device: Ritz vectors = V[:, 0:c] Z[:, i].
 static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const double* x0, int b0, uint64_t seed,
                   KsResult& out) {
     const int b = S.b, ncv = S.ncv, k = S.k;
@@ -897,8 +949,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         if (hflag[0]) return set_error(SFAIRSC_E_ARG, "start block is rank deficient");
     }
     int repairs = 0;
-    std::vector<double> hT, Z, w, Rc(b * b);
-    SymEigSel sel;
+    std::vector<double> rec(rr_rec_doubles(k));
     // operator output computed ahead, during the previous Rayleigh-Ritz step
     bool ahead = false;
     OpOut pre;
@@ -914,8 +965,18 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
             if (S.info) S.info->block_steps += 1;
             c += b;
         }
+        // Rayleigh-Ritz on the device (second stream).  Look-ahead: a restart
+        // keeps the next block V[:, c : c + b] (moved to the column after the
+        // kept Ritz vectors), so its operator application runs on the solve's
+        // stream meanwhile (wasted if this cycle converges).  Both skip their
+        // work if the last expansion broke down (flag).
+        SF_TRY(S.rayleigh_ritz(c, tol, keep_opt));
+        SF_TRY(S.op(c, &pre));
+        ahead = true;
+        SF_HIP(hipStreamWaitEvent(S.s, S.g->eig.ev_join, 0));
         int hflag[3];
         SF_TRY(S.download(hflag, S.flag, 3 * sizeof(int)));
+        SF_TRY(S.download(rec.data(), S.rb.rec, rec.size() * sizeof(double)));
         SF_TRY(S.sync());
         SF_TRY(S.harvest_timing());
         if (hflag[0]) {
@@ -924,90 +985,32 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
             if (++repairs > 64) return set_error(SFAIRSC_E_HIP, "too many Krylov breakdowns");
             SF_TRY(repair_block(S, cact, seed, repairs, hflag[2]));
             c = cact + b;
+            ahead = false;
             if (S.info) S.info->block_steps += 1;
             continue;
         }
-        // Rayleigh-Ritz on T_c
-        hT.resize((size_t)c * c);
-        k_pack<<<grid_for((int64_t)c * c, 256, 256), 256, 0, S.s>>>(S.T, S.ld, c, S.part);
-        SF_HIP(hipGetLastError());
-        SF_TRY(S.download(hT.data(), S.part, (size_t)c * c * sizeof(double)));
-        SF_TRY(S.download(Rc.data(), S.Rc, b * b * sizeof(double)));
-        SF_HIP(hipEventRecord(S.ev_rr, S.s));
-        // Look-ahead: a restart keeps the next block V[:, c : c + b] (moved
-        // to the column after the kept Ritz vectors), so its operator
-        // application runs on the GPU while the host solves the Rayleigh-Ritz
-        // eigenproblem (wasted if this cycle converges).
-        SF_TRY(S.op(c, &pre));
-        ahead = true;
-        SF_TRY(S.sync_to(S.ev_rr));
-        for (int i = 0; i < c; ++i)
-            for (int j = i + 1; j < c; ++j) {
-                double m = 0.5 * (hT[i * c + j] + hT[j * c + i]);
-                hT[i * c + j] = m;
-                hT[j * c + i] = m;
-            }
-        // Rayleigh-Ritz: all Ritz values, then Ritz vectors only for the
-        // wanted pairs and those kept at a restart
-        int p = 0, m = k;
-        {
-            auto t0 = std::chrono::steady_clock::now();
-            sel.reduce(c, hT.data());
-            w = sel.w;
-            p = keep_opt > 0 ? keep_opt : std::max(k + b, k + (c - k) / 2);
-            p = std::min(p, ncv - b);
-            p = std::max(p, std::min(k, ncv - b));
-            while (p < ncv - b && p < c && std::fabs(w[p] - w[p - 1]) <= 1e-10 * S.sigma) ++p;
-            p = std::min((p + 3) & ~3, ncv - b);  // keeps every later column offset a multiple of 4
-            m = std::min(c, std::max(p, k));
-            Z.resize((size_t)c * m);
-            sel.vectors(m, Z.data());
-            if (S.info)
-                S.info->rr_ms +=
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        }
-        std::vector<double> res(m);
-        for (int i = 0; i < m; ++i) {
-            double ss = 0.0;
-            for (int r = 0; r < b; ++r) {
-                double acc = 0.0;
-                for (int q = r; q < b; ++q) acc += Rc[r * b + q] * Z[(size_t)(c - b + q) * m + i];
-                ss += acc * acc;
-            }
-            res[i] = std::sqrt(ss);
-        }
-        int nconv = 0;
-        for (int i = 0; i < k; ++i)
-            if (res[i] <= tol * S.sigma) ++nconv;
+        const int nconv = (int)rec[0], p = (int)rec[1], m = (int)rec[2];
+        const double gap = rec[3];
         if (S.info) {
             S.info->restarts = restart + 1;
             S.info->converged = nconv;
-            S.info->gap_ratio = c > k ? (w[k] - w[k - 1]) / S.sigma : 0.0;
+            S.info->gap_ratio = gap;
         }
-        out.theta = w;
-        out.res = res;
-        out.Z = Z;
+        out.theta.assign(rec.begin() + kRrRecHead, rec.begin() + kRrRecHead + k);
+        out.res.assign(rec.begin() + kRrRecHead + k, rec.begin() + kRrRecHead + 2 * k);
+        out.gap = gap;
         out.c = c;
         out.m = m;
         out.converged = nconv == k;
         if (out.converged || restart + 1 >= max_restarts) return SFAIRSC_OK;
-        // Q[:, 0:p] in 32-column slices, then the b x b identity (V_next copy)
-        std::vector<double> Qp((size_t)c * p + (size_t)b * b, 0.0);
-        size_t off = 0;
-        for (int j0 = 0; j0 < p; j0 += 32) {
-            const int wt = std::min(32, p - j0);
-            for (int t = 0; t < c; ++t)
-                for (int q = 0; q < wt; ++q) Qp[off + (size_t)t * wt + q] = Z[(size_t)t * m + j0 + q];
-            off += (size_t)c * wt;
-        }
-        for (int i = 0; i < b; ++i) Qp[off + (size_t)i * b + i] = 1.0;
-        SF_TRY(S.upload(S.Q, Qp.data(), Qp.size() * sizeof(double)));
-        SF_TRY(S.upload(S.theta, w.data(), p * sizeof(double)));
+        if (p < 1 || p + b > S.ld || p > c) return set_error(SFAIRSC_E_HIP, "internal: restart keeps %d of %d", p, c);
+        // V <- [V Z[:, 0:p], V_next]; the kernel left Z[:, 0:p] in 32-column
+        // slices followed by the identity in S.Q, and all Ritz values in theta
         SF_TRY(S.phase_mark(2, true));
         SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
         SF_TRY(S.phase_mark(2, false));
         std::swap(S.V, S.V2);
-        k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.theta);
+        k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.rb.theta);
         SF_HIP(hipGetLastError());
         c = p;
     }
@@ -1016,12 +1019,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
 // Ritz vectors X = V[:, 0:c] Z[:, 0:k] (row-major n x k in Xo, ld k).
 static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* scale) {
     const int c = R.c, k = S.k;
-    std::vector<double> Qk((size_t)c * k);
-    for (int t = 0; t < c; ++t)
-        for (int q = 0; q < k; ++q) Qk[(size_t)t * k + q] = R.Z[(size_t)t * R.m + q];
-    SF_TRY(S.upload(S.Q, Qk.data(), Qk.size() * sizeof(double)));
     k_rotate<<<grid_for(S.n, kRotRows, 1024), 256, (size_t)kRotRows * (c + S.b) * sizeof(double), S.s>>>(
-        S.V, S.ld, S.n, c, k, S.b, S.Q, 1, Xo, k, scale);
+        S.V, S.ld, S.n, c, k, S.b, S.rb.zk, 1, Xo, k, scale);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }
@@ -1183,7 +1182,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     // (Proposition 3.3 and the angle bound need lambda_k < lambda_{k+1}):
     // a relative gap at the tolerance level is flagged, outputs still written.
     const bool gap_known = R.c > k;
-    const double gap = gap_known ? (R.theta[k] - R.theta[k - 1]) / S.sigma : 0.0;
+    const double gap = gap_known ? R.gap : 0.0;
     const bool degenerate = gap_known && gap <= kDegenerateGap * tol;
     if (info) {
         info->max_rel_residual = worst;

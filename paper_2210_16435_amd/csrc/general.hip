@@ -326,7 +326,7 @@ static int set_constraint_impl(sfairsc_graph* g, const double* F, int64_t ldf, i
                                         C);
     SF_HIP(hipGetLastError());
 
-    // Gram C^T C, diagonalised on the host
+    // Gram C^T C
     SF_TRY(qt_sums<double>(g, C, RP, m, RP, C, RP, m, sums, s, nullptr));
     std::vector<double> G(m * m), w(m), Z(m * m);
     SF_TRY(wait_download(G.data(), sums, (size_t)m * m, s));
@@ -334,7 +334,8 @@ static int set_constraint_impl(sfairsc_graph* g, const double* F, int64_t ldf, i
         for (int j = 0; j < i; ++j) G[i * m + j] = G[j * m + i] = 0.5 * (G[i * m + j] + G[j * m + i]);
     for (double v : G)
         if (!std::isfinite(v)) return set_error(SFAIRSC_E_ARG, "F has a non-finite entry");
-    sym_eig(m, G.data(), w.data(), Z.data());
+    // eigenpairs of the Gram matrix (still in `sums`) on the device
+    SF_TRY(small_eig_host(g, sums, m, m, w.data(), Z.data(), s));
     const double wmax = w[m - 1];
     if (!(wmax > 0.0)) return set_error(SFAIRSC_E_ARG, "the constraint matrix is zero");
     const double cut = rank_tol * rank_tol * wmax;

@@ -246,6 +246,10 @@ static void free_graph(sfairsc_graph* g) {
     w.X.release();
     w.opart.release();
     w.osmall.release();
+    w.rr.release();
+    if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
+    if (w.ev_join) (void)hipEventDestroy(w.ev_join);
+    if (w.s2) (void)hipStreamDestroy(w.s2);
     if (w.pin) (void)hipHostFree(w.pin);
     w.pin = nullptr;
     auto& k = g->km;

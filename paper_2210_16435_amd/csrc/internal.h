@@ -10,7 +10,7 @@
 
 #include "../../include/sfairsc.h"
 #include "ortho.h"
-#include "symeig.h"
+#include "rr.h"
 
 namespace sfairsc {
 
@@ -75,6 +75,11 @@ struct EigWork {
     DevBuf X;       // n x kMaxK output staging
     DevBuf opart;   // partial sums of the matrix-core passes
     DevBuf osmall;  // their reduced sums and coefficient matrices
+    DevBuf rr;      // Rayleigh-Ritz kernel: scratch, eigenvalues, Ritz vectors, record
+    // second stream: the Rayleigh-Ritz kernel runs beside the look-ahead
+    // operator application of the solve's stream
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // Pinned host staging for host-to-device uploads: a pageable source may
     // be read by the DMA engine after hipMemcpyAsync returns, so every
     // upload is first copied here and the region is only reused after the
@@ -194,6 +199,24 @@ int lsqr_correct(sfairsc_graph* g, const void* T, bool t_float, int BW, int b, d
                  hipStream_t s, const int* skip);
 int lsqr_project(sfairsc_graph* g, double* X, int ldx, int b, hipStream_t s);
 void free_memb(sfairsc_graph* g);
+
+// Layout of EigWork::rr (doubles): kernel scratch, then the eigenvalues,
+// the first k Ritz vectors (c x k), the host record and a c x c block for
+// the eigenvectors of the small-matrix calls.
+struct RrBufs {
+    double* work;
+    double* theta;
+    double* zk;
+    double* rec;
+    double* zout;
+};
+int rr_buffers(sfairsc_graph* g, RrBufs* out);
+
+// All eigenpairs of a small symmetric device matrix (order c <= kMaxBasis,
+// row-major, leading dimension ldt), copied to the host: w ascending, Z
+// row-major c x c with the eigenvector of w[j] in column j.  Runs the
+// Rayleigh-Ritz kernel on `s` and synchronises it (set-up and repair paths).
+int small_eig_host(sfairsc_graph* g, const double* dT, int c, int ldt, double* w, double* Z, hipStream_t s);
 
 // Free the per-device workspaces of batched launches (device buffers, pinned
 // host buffer, events).  Called when the last graph handle is destroyed.
