@@ -10,23 +10,31 @@
 //
 //  1. Householder reduction to tridiagonal form, T = Q Tri Q^T with
 //     Q = H_0 H_1 ... H_{c-3}, H_j = I - tau_j v_j v_j^T.  The matrix stays in
-//     registers: wavefront w holds rows w, w + 16, ..., lane l columns l,
-//     l + 64, l + 128, so every row sum of a product is a wavefront
-//     reduction.  Two workgroup barriers per column.
-//  2. every eigenvalue of Tri by multisection: a group of G lanes per
-//     eigenvalue evaluates G Sturm counts (signs of the leading principal
-//     minors of Tri - x I, by their three-term recurrence with power-of-two
-//     rescaling) and keeps the subinterval that holds the eigenvalue, until
-//     its width is a few ulps of ||T||.
+//     registers, lanes holding rows and wavefronts holding columns (lane l,
+//     wavefront w: rows l + 64 t, columns w + 16 q).  The product T v then
+//     needs no cross-lane reduction: each thread sums its columns, the
+//     sixteen wavefront partials meet in LDS.  Three workgroup barriers per
+//     column; the wavefront that owns the next column builds its reflector
+//     right after its own update.
+//  2. the eigenvalues that the restart needs, by Sturm counts (signs of the
+//     leading principal minors of Tri - x I, three-term recurrence with
+//     power-of-two rescaling every four steps): four lanes per eigenvalue
+//     split its interval in five until the interval holds it alone; then
+//     one lane finishes with Laguerre's method on the characteristic
+//     polynomial (value and two derivatives by the same recurrence), whose
+//     steps never pass the eigenvalue.
+//     Eigenvalues that multisection cannot separate from a neighbour are
+//     bisected to a few ulps of ||T||.
 //  3. eigenvectors of Tri for the m smallest eigenvalues by inverse
 //     iteration, one lane per vector: Gaussian elimination with partial
-//     pivoting of Tri - s I (tiny pivots replaced by eps ||T||), three solves
-//     from a pseudo-random start; after each solve the vectors whose
-//     eigenvalues lie within 1e-3 ||T|| of each other are orthonormalised
-//     together (modified Gram-Schmidt, one wavefront per such cluster), as in
-//     LAPACK's inverse iteration.
-//  4. back-transformation Z = Q Y, the reflectors applied in reverse order,
-//     one wavefront per set of columns (no barriers).
+//     pivoting of Tri - s I (tiny pivots replaced by eps ||T||) and solves
+//     from a pseudo-random start, the factors kept in rows shared by the
+//     lanes and read eight rows ahead.  Eigenvalues closer than the
+//     clustering distance are solved three times and orthonormalised
+//     together after each solve (modified Gram-Schmidt, one wavefront per
+//     cluster), as in LAPACK's inverse iteration; the others twice.
+//  4. back-transformation Z = Q Y, sixteen lanes per column, the reflectors
+//     applied in reverse order from LDS, sixteen staged at a time.
 //
 // The matrix is first scaled by a power of two (max |T_ij| in [1/2, 1)).
 // Every reduction has a fixed order, so results are bitwise reproducible.
@@ -40,8 +48,10 @@ namespace sfairsc {
 namespace {
 
 constexpr int kRrT = 1024;
+constexpr int kRrW = kRrT / 64;    // wavefronts
 constexpr int kRrMax = kMaxBasis;  // largest order
 constexpr int kRrLd = kRrMax;      // leading dimension of the per-vector scratch
+constexpr int kMsG = 4;            // lanes per eigenvalue in the multisection
 
 // scratch layout (doubles)
 constexpr size_t kOffHV = 0;                               // Householder vectors [j][kRrMax]
@@ -54,22 +64,45 @@ constexpr size_t kOffPV = kOffL + (size_t)kRrMax * kRrLd;   // 1: rows interchan
 constexpr size_t kOffZ = kOffPV + (size_t)kRrMax * kRrLd;   // Ritz vectors [row][kRrLd]
 constexpr size_t kWork = kOffZ + (size_t)kRrMax * kRrLd;
 
+// Lane permutation of a double by the data-parallel primitives (DPP).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Uniform copy of lane l's value.
+__device__ inline double rdl(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+// Sum over each row of 16 lanes, in every lane of the row: exchanges with
+// lane ^ 1, lane ^ 2 (quad permutations), then the mirrored lane within 8
+// and within 16.
+__device__ inline double sum16(double v) {
+    v += dpp_d<0xB1>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x140>(v);
+    return v;
+}
 __device__ inline double wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = sum16(v);
+    return (rdl(v, 0) + rdl(v, 16)) + (rdl(v, 32) + rdl(v, 48));
 }
-
 __device__ inline double wmin(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmin(v, dpp_d<0xB1>(v));
+    v = fmin(v, dpp_d<0x4E>(v));
+    v = fmin(v, dpp_d<0x141>(v));
+    v = fmin(v, dpp_d<0x140>(v));
+    return fmin(fmin(rdl(v, 0), rdl(v, 16)), fmin(rdl(v, 32), rdl(v, 48)));
 }
-
 __device__ inline double wmax(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    return fmax(fmax(rdl(v, 0), rdl(v, 16)), fmax(rdl(v, 32), rdl(v, 48)));
 }
 
 // Uniform(-1, 1) start entry (SplitMix64 output function of the counter).
@@ -81,45 +114,113 @@ __device__ inline double start_entry(int vec, int row) {
     return (double)(z >> 11) * 0x1p-52 - 1.0;
 }
 
-// Number of eigenvalues of the tridiagonal matrix (d, e) below x: the sign
-// changes of p_0 = 1, p_i = det of the leading i x i block of Tri - x I
-// (p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2}).  A zero p_i takes the sign
-// opposite to p_{i-1}; both terms are rescaled by 2^-400 or 2^400 when the
-// newest leaves [2^-400, 2^400].
-__device__ int sturm_count(const double* __restrict__ d, const double* __restrict__ e2, int c, double x) {
-    double pm = 1.0, p = d[0] - x;
-    if (p == 0.0) p = -0x1p-60;
-    int cnt = p < 0.0;
-    for (int i = 1; i < c; ++i) {
-        double pn = (d[i] - x) * p - e2[i - 1] * pm;
-        if (pn == 0.0) pn = -p * 0x1p-60;
-        cnt += (pn < 0.0) != (p < 0.0);
-        const double a = fabs(pn);
-        if (a > 0x1p400) {
-            pn *= 0x1p-400;
-            p *= 0x1p-400;
-        } else if (a < 0x1p-400) {
-            pn *= 0x1p400;
-            p *= 0x1p400;
-        }
-        pm = p;
-        p = pn;
+// One step of the leading-minor recurrence p_i = (d - x) p_{i-1} - e^2 p_{i-2}
+// with its sign-change count (sign bits compared).  Every e^2 is at least
+// 2^-600, so a zero minor is never followed by another; a zero then counts
+// one sign change across the pair whichever sign it carries, which is the
+// count of the usual rule (a zero takes the sign opposite to its
+// predecessor) without a test on the critical path.
+__device__ inline void sturm_step(double2 de, double x, double& p, double& pm, int& cnt) {
+    const double pn = (de.x - x) * p - de.y * pm;
+    cnt += (int)((unsigned)(__double2hiint(pn) ^ __double2hiint(p)) >> 31);
+    pm = p;
+    p = pn;
+}
+
+// The scale factor that brings max(|p|, |pm|) back into [2^-200, 2^200]
+// (a power of two, exact); within four steps the minors grow by at most a
+// factor 5^4.
+__device__ inline double sturm_scale(double p, double pm) {
+    const double a = fmax(fabs(p), fabs(pm));
+    return a > 0x1p200 ? 0x1p-200 : (a < 0x1p-200 ? 0x1p200 : 1.0);
+}
+
+// Number of eigenvalues of the tridiagonal matrix below x; de[i] = {d_i,
+// e_{i-1}^2} (de[0].y unused; readable up to index c + 3).  The next four
+// rows are read while the current four are used.
+__device__ int sturm_count(const double2* __restrict__ de, int c, double x) {
+    double pm = 1.0, p = de[0].x - x;
+    int cnt = (int)((unsigned)__double2hiint(p) >> 31);
+    int i = 1;
+    double2 n0 = de[1], n1 = de[2], n2 = de[3], n3 = de[4];
+    for (; i + 3 < c; i += 4) {
+        const double2 d0 = n0, d1 = n1, d2 = n2, d3 = n3;
+        n0 = de[i + 4];
+        n1 = de[i + 5];
+        n2 = de[i + 6];
+        n3 = de[i + 7];
+        sturm_step(d0, x, p, pm, cnt);
+        sturm_step(d1, x, p, pm, cnt);
+        sturm_step(d2, x, p, pm, cnt);
+        sturm_step(d3, x, p, pm, cnt);
+        const double sc = sturm_scale(p, pm);
+        p *= sc;
+        pm *= sc;
     }
+    for (; i < c; ++i) sturm_step(de[i], x, p, pm, cnt);
+    return cnt;
+}
+
+// The same count plus the characteristic polynomial f = p_c and its first
+// two derivatives (p'_i = (d - x) p'_{i-1} - p_{i-1} - e^2 p'_{i-2},
+// p''_i = (d - x) p''_{i-1} - 2 p'_{i-1} - e^2 p''_{i-2}), all scaled by the
+// same power of two.
+__device__ inline void lag_step(double2 de, double x, double& p, double& pm, double& q, double& qm, double& r,
+                                double& rm, int& cnt) {
+    const double t = de.x - x;
+    const double pn = t * p - de.y * pm;
+    const double qn = t * q - p - de.y * qm;
+    const double rn = t * r - 2.0 * q - de.y * rm;
+    cnt += (int)((unsigned)(__double2hiint(pn) ^ __double2hiint(p)) >> 31);
+    pm = p;
+    p = pn;
+    qm = q;
+    q = qn;
+    rm = r;
+    r = rn;
+}
+__device__ int sturm_laguerre(const double2* __restrict__ de, int c, double x, double& f, double& f1, double& f2) {
+    double pm = 1.0, p = de[0].x - x;
+    double qm = 0.0, q = -1.0, rm = 0.0, r = 0.0;
+    int cnt = (int)((unsigned)__double2hiint(p) >> 31);
+    int i = 1;
+    for (; i + 3 < c; i += 4) {
+        const double2 d0 = de[i], d1 = de[i + 1], d2 = de[i + 2], d3 = de[i + 3];
+        lag_step(d0, x, p, pm, q, qm, r, rm, cnt);
+        lag_step(d1, x, p, pm, q, qm, r, rm, cnt);
+        lag_step(d2, x, p, pm, q, qm, r, rm, cnt);
+        lag_step(d3, x, p, pm, q, qm, r, rm, cnt);
+        const double a = fmax(fmax(fmax(fabs(p), fabs(pm)), fmax(fabs(q), fabs(qm))), fmax(fabs(r), fabs(rm)));
+        const double sc = a > 0x1p200 ? 0x1p-200 : (a < 0x1p-200 ? 0x1p200 : 1.0);
+        p *= sc;
+        pm *= sc;
+        q *= sc;
+        qm *= sc;
+        r *= sc;
+        rm *= sc;
+    }
+    for (; i < c; ++i) lag_step(de[i], x, p, pm, q, qm, r, rm, cnt);
+    f = p;
+    f1 = q;
+    f2 = r;
     return cnt;
 }
 
 template <int NR, int NC>
 __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     if (a.skip && *a.skip) return;
+    constexpr int NT = 4 * NC;  // rows per lane in the back-transformation
     __shared__ double vs[2][kRrMax];
-    __shared__ double ps[2][kRrMax];
+    __shared__ double ps[kRrMax];
+    __shared__ double part[kRrW][kRrMax];
     __shared__ double tau_s[kRrMax];
-    __shared__ double dd[kRrMax], ee[kRrMax], ee2[kRrMax];
-    __shared__ double th[kRrMax], sh[kRrMax], res_s[kRrMax];
+    __shared__ double dd[kRrMax], ee[kRrMax];
+    __shared__ double2 de[kRrMax + 8];
+    __shared__ double th[kRrMax], sh[kRrMax], res_s[kRrMax], ysc[kRrMax];
     __shared__ int cl_start[kRrMax + 1];
-    __shared__ int s_ncl, s_p, s_m;
+    __shared__ int s_ncl, s_multi, s_p, s_m, s_nev, s_pcap;
     __shared__ double s_gl, s_gu;
-    __shared__ double red16[16];
+    __shared__ double red[kRrW];
 
     const int c = a.c;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -133,20 +234,23 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     double* Zs = a.work + kOffZ;
 
     // ---- stage 1: Householder tridiagonalisation --------------------------
+    // A[q][t] = T[lane + 64 t][w + 16 q] (symmetrised: both triangles averaged)
     double A[NR][NC];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        const int r = 16 * q + w;
+        const int col = w + 16 * q;
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
-            const int col = 64 * t + lane;
-            A[q][t] = (r < c && col < c) ? 0.5 * (a.T[(size_t)r * a.ldt + col] + a.T[(size_t)col * a.ldt + r]) : 0.0;
+            const int row = lane + 64 * t;
+            A[q][t] = (row < c && col < c) ? 0.5 * (a.T[(size_t)row * a.ldt + col] + a.T[(size_t)col * a.ldt + row])
+                                           : 0.0;
         }
     }
     for (int i = tid; i < kRrMax; i += kRrT) {
-        vs[0][i] = vs[1][i] = ps[0][i] = ps[1][i] = 0.0;
-        tau_s[i] = dd[i] = ee[i] = ee2[i] = 0.0;
+        vs[0][i] = vs[1][i] = ps[i] = 0.0;
+        tau_s[i] = dd[i] = ee[i] = 0.0;
     }
+    for (int i = tid; i < kRrMax + 8; i += kRrT) de[i] = make_double2(0.0, 0.0);
     // scale by a power of two (exact) so that max |T_ij| lies in [1/2, 1):
     // no overflow or underflow in the squares and Sturm recurrences below;
     // eigenvalues are scaled back on output, eigenvectors are unchanged
@@ -157,13 +261,13 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
 #pragma unroll
             for (int t = 0; t < NC; ++t) mx = fmax(mx, fabs(A[q][t]));
         mx = wmax(mx);
-        if (lane == 0) red16[w] = mx;
+        if (lane == 0) red[w] = mx;
     }
     __syncthreads();
     int sexp = 0;
     {
         double mx = 0.0;
-        for (int i = 0; i < 16; ++i) mx = fmax(mx, red16[i]);
+        for (int i = 0; i < kRrW; ++i) mx = fmax(mx, red[i]);
         if (mx > 0.0 && isfinite(mx)) frexp(mx, &sexp);
         const double sc = ldexp(1.0, -sexp);
 #pragma unroll
@@ -171,130 +275,141 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
 #pragma unroll
             for (int t = 0; t < NC; ++t) A[q][t] *= sc;
     }
-    for (int j = 0; j + 2 < c; ++j) {
-        const int buf = j & 1;
-        if (w == (j & 15)) {
-            // the wavefront holding row j builds the reflector that zeroes
-            // T[j, j+2:] (= T[j+2:, j])
-            const int qj = j >> 4;
-            double x[NC];
+    // The reflector H_j = I - tau v v^T that zeroes T[j+2:, j], built by the
+    // wavefront owning column j (w == j mod 16) from its registers.
+    auto reflector = [&](int j) {
+        const int qj = j >> 4;
+        double x[NC];
 #pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                double v = 0.0;
+        for (int t = 0; t < NC; ++t) {
+            double v = 0.0;
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
-                    if (q == qj) v = A[q][t];
-                x[t] = v;
-            }
-            double ss = 0.0, al = 0.0, dj = 0.0;
-#pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                const int col = 64 * t + lane;
-                if (col > j + 1 && col < c) ss += x[t] * x[t];
-                if (col == j + 1) al = x[t];
-                if (col == j) dj = x[t];
-            }
-            ss = wsum(ss);
-            al = wsum(al);
-            dj = wsum(dj);
-            double tau = 0.0, beta = al, scale = 0.0;
-            if (ss > 0.0) {
-                beta = -copysign(sqrt(al * al + ss), al);
-                tau = (beta - al) / beta;
-                scale = 1.0 / (al - beta);
-            }
-#pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                const int col = 64 * t + lane;
-                if (col < c) {
-                    const double v = col == j + 1 ? 1.0 : (col > j + 1 ? x[t] * scale : 0.0);
-                    vs[buf][col] = v;
-                    HV[(size_t)j * kRrMax + col] = v;
-                }
-            }
-            if (lane == 0) {
-                dd[j] = dj;
-                ee[j] = beta;
-                tau_s[j] = tau;
-            }
+            for (int q = 0; q < NR; ++q)
+                if (q == qj) v = A[q][t];
+            x[t] = v;
         }
-        __syncthreads();
+        double ss = 0.0, xa = 0.0, xd = 0.0;
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            const int row = lane + 64 * t;
+            if (row > j + 1 && row < c) ss += x[t] * x[t];
+            if (t == ((j + 1) >> 6)) xa = x[t];
+            if (t == (j >> 6)) xd = x[t];
+        }
+        ss = wsum(ss);
+        const double al = rdl(xa, (j + 1) & 63);
+        const double dj = rdl(xd, j & 63);
+        double tau = 0.0, beta = al, scale = 0.0;
+        if (ss > 0.0) {
+            // tau = (beta - al) / beta and 1 / (al - beta) from one division
+            beta = -copysign(sqrt(al * al + ss), al);
+            const double g = al - beta, r = 1.0 / (beta * g);
+            tau = -g * g * r;
+            scale = beta * r;
+        }
+        double* hv = HV + (size_t)j * kRrMax;
+#pragma unroll
+        for (int t = 0; t < NC; ++t) {
+            const int row = lane + 64 * t;
+            const double v = row == j + 1 ? 1.0 : (row > j + 1 && row < c ? x[t] * scale : 0.0);
+            vs[j & 1][row] = v;
+            if (row < c) hv[row] = v;
+        }
+        if (lane == 0) {
+            dd[j] = dj;
+            ee[j] = beta;
+            tau_s[j] = tau;
+        }
+    };
+    const int nwr = (c + 63) >> 6;  // wavefronts holding the rows in the reduction below
+    if (c >= 2 && w == 0) reflector(0);
+    for (int j = 0; j + 1 < c; ++j) {
+        __syncthreads();  // reflector j in vs[j & 1] and tau_s[j]
         const double tau = tau_s[j];
+        const double* v = vs[j & 1];
         if (tau != 0.0) {
-            // p = tau T v on the rows below j
-            double vc[NC];
+            // p = tau T v: this wavefront's columns, then the sum of the
+            // sixteen partials per row
+            // the largest order has no registers to spare: its column
+            // values of v are read again after the barriers
+            constexpr bool keep = NR <= 8;
+            double vc[keep ? NR : 1], vr[NC];
+            auto vcol = [&](int q) { return keep ? vc[keep ? q : 0] : v[w + 16 * q]; };
+            if (keep)
 #pragma unroll
-            for (int t = 0; t < NC; ++t) vc[t] = vs[buf][64 * t + lane];
+                for (int q = 0; q < NR; ++q) vc[keep ? q : 0] = v[w + 16 * q];
 #pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const int r = 16 * q + w;
-                if (16 * q < c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int t = 0; t < NC; ++t) s += A[q][t] * vc[t];
-                    s = wsum(s);
-                    if (lane == 0 && r < c) ps[buf][r] = r > j ? tau * s : 0.0;
-                }
-            }
-        }
-        __syncthreads();
-        if (tau != 0.0) {
-            // K = tau/2 v^T p, w = p - K v, T -= v w^T + w v^T
-            double part = 0.0;
-#pragma unroll
-            for (int t = 0; t < NC; ++t) part += vs[buf][64 * t + lane] * ps[buf][64 * t + lane];
-            const double K = 0.5 * tau * wsum(part);
-            double vc[NC], wc[NC];
+            for (int t = 0; t < NC; ++t) vr[t] = v[lane + 64 * t];
 #pragma unroll
             for (int t = 0; t < NC; ++t) {
-                vc[t] = vs[buf][64 * t + lane];
-                wc[t] = ps[buf][64 * t + lane] - K * vc[t];
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < NR; ++q) s += A[q][t] * vcol(q);
+                part[w][lane + 64 * t] = s;
             }
+            __syncthreads();
+            if (w < nwr) {
+                double pv = 0.0;
+                if (tid < c) {
+                    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+#pragma unroll
+                    for (int u = 0; u < kRrW; u += 4) {
+                        h0 += part[u][tid];
+                        h1 += part[u + 1][tid];
+                        h2 += part[u + 2][tid];
+                        h3 += part[u + 3][tid];
+                    }
+                    const double pr = tid > j ? tau * ((h0 + h1) + (h2 + h3)) : 0.0;
+                    ps[tid] = pr;
+                    pv = pr * v[tid];
+                }
+                pv = wsum(pv);
+                if (lane == 0) red[w] = pv;
+            }
+            __syncthreads();
+            // K = tau/2 v^T p, w = p - K v, T -= v w^T + w v^T (rows and
+            // columns above j are untouched: v and p vanish there)
+            double pr[NC];
+#pragma unroll
+            for (int t = 0; t < NC; ++t) pr[t] = ps[lane + 64 * t];
+            double K = 0.0;
+            for (int u = 0; u < nwr; ++u) K += red[u];
+            K *= 0.5 * tau;
+            double wr[NC];
+#pragma unroll
+            for (int t = 0; t < NC; ++t) wr[t] = pr[t] - K * vr[t];
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
-                const int r = 16 * q + w;
-                if (r > j && r < c) {
-                    const double vr = vs[buf][r];
-                    const double wr = ps[buf][r] - K * vr;
+                const double vq = vcol(q);
+                const double wq = ps[w + 16 * q] - K * vq;
 #pragma unroll
-                    for (int t = 0; t < NC; ++t) A[q][t] -= vr * wc[t] + wr * vc[t];
-                }
+                for (int t = 0; t < NC; ++t) A[q][t] -= vr[t] * wq + wr[t] * vq;
             }
         }
+        if (j + 2 < c && w == ((j + 1) & 15)) reflector(j + 1);
     }
-    // the trailing 2 x 2 (or 1 x 1) block
-    for (int r = (c >= 2 ? c - 2 : 0); r < c; ++r) {
-        if (w == (r & 15)) {
-            const int qr = r >> 4;
-            double dg = 0.0, of = 0.0;
+    // the last diagonal entry
+    if (w == ((c - 1) & 15)) {
+        const int ql = (c - 1) >> 4;
+        double xd = 0.0;
 #pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                double v = 0.0;
+        for (int t = 0; t < NC; ++t)
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
-                    if (q == qr) v = A[q][t];
-                const int col = 64 * t + lane;
-                if (col == r) dg = v;
-                if (col == r + 1 && col < c) of = v;
-            }
-            dg = wsum(dg);
-            of = wsum(of);
-            if (lane == 0) {
-                dd[r] = dg;
-                if (r + 1 < c) ee[r] = of;
-            }
-        }
+            for (int q = 0; q < NR; ++q)
+                if (q == ql && t == ((c - 1) >> 6)) xd = A[q][t];
+        const double dl = rdl(xd, (c - 1) & 63);
+        if (lane == 0) dd[c - 1] = dl;
     }
     __syncthreads();
 
-    // ---- stage 2: eigenvalues by multisection ------------------------------
+    // ---- stage 2: eigenvalues ------------------------------------------------------
     if (w == 0) {
         double lo = INFINITY, hi = -INFINITY;
         for (int i = lane; i < c; i += 64) {
             const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < c ? fabs(ee[i]) : 0.0);
             lo = fmin(lo, dd[i] - r);
             hi = fmax(hi, dd[i] + r);
-            if (i + 1 < c) ee2[i] = ee[i] * ee[i];
+            de[i] = make_double2(dd[i], i > 0 ? fmax(ee[i - 1] * ee[i - 1], 0x1p-600) : 0.0);
         }
         lo = wmin(lo);
         hi = wmax(hi);
@@ -302,32 +417,105 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
             s_gl = lo;
             s_gu = hi;
         }
+    } else if (tid == 64) {
+        // how many of the smallest eigenvalues the restart can use: the kept
+        // count p (before its extension over equal eigenvalues and its
+        // rounding to a multiple of 4) plus room for both, and theta_{k+1}
+        int nev = c, pcap = c;
+        if (a.mode == 0) {
+            const int k = a.k, b = a.b, ncv = a.ncv;
+            int p0 = a.keep > 0 ? a.keep : max(k + b, k + (c - k) / 2);
+            p0 = min(p0, ncv - b);
+            p0 = max(p0, min(k, ncv - b));
+            nev = min(c, max(k + 1, p0 + 12));
+            pcap = nev < c ? nev - 4 : c;
+        } else {
+            nev = c;
+        }
+        s_nev = nev;
+        s_pcap = pcap;
     }
     __syncthreads();
     const double tn = fmax(fmax(fabs(s_gl), fabs(s_gu)), DBL_MIN);
+    const double atol = 4.0 * DBL_EPSILON * tn;
+    const int nev = s_nev;
     {
-        const int G = c <= 64 ? 16 : (c <= 128 ? 8 : 4);
-        const int i = tid / G, u = tid % G;
-        const double atol = 4.0 * DBL_EPSILON * tn;
+        // multisection: four lanes per eigenvalue (lanes of one group in one
+        // quad of a wavefront), until the interval holds lambda_i alone
+        // (counts i at lo and i + 1 at hi) or is narrower than atol
+        const int i = tid / kMsG, u = tid % kMsG, base = lane & ~(kMsG - 1);
+        const bool act = i < nev;
         double lo = s_gl - 2.0 * atol, hi = s_gu + 2.0 * atol;
-        // iterations to shrink [lo, hi] to atol (uniform over the workgroup;
-        // bounded also for non-finite input)
-        const double nd = ceil(log2((hi - lo) / atol) / log2((double)(G + 1)));
-        const int nit = (nd >= 0.0 && nd <= 128.0) ? (int)nd + 1 : 129;
-        const int base = (lane / G) * G;
-        const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-        for (int it = 0; it < nit; ++it) {
-            const double x = lo + (hi - lo) * ((double)(u + 1) / (double)(G + 1));
-            const int cnt = i < c ? sturm_count(dd, ee2, c, x) : 0;
-            const uint64_t bal = __ballot(i < c && cnt > i);
-            const uint64_t gm = (bal >> base) & gmask;
-            const int first = gm ? (__ffsll((unsigned long long)gm) - 1) : G;
-            const double xl = __shfl(x, base + (first > 0 ? first - 1 : 0), 64);
-            const double xh = __shfl(x, base + (first < G ? first : G - 1), 64);
-            if (first > 0) lo = xl;
-            if (first < G) hi = xh;
+        int clo = 0, chi = c;
+        for (int it = 0; it < 64; ++it) {
+            const bool go = act && (clo != i || chi != i + 1) && hi - lo > atol;
+            if (!__syncthreads_or(go)) break;
+            if (go) {
+                const double x = lo + (hi - lo) * ((double)(u + 1) / (double)(kMsG + 1));
+                const int cnt = sturm_count(de, c, x);
+                // first point of the group whose count exceeds i
+                const uint64_t bal = __ballot(cnt > i);
+                const uint64_t gm = (bal >> base) & ((1ull << kMsG) - 1ull);
+                const int first = gm ? (__ffsll((unsigned long long)gm) - 1) : kMsG;
+                const int sl = base + (first > 0 ? first - 1 : 0), sh = base + (first < kMsG ? first : kMsG - 1);
+                const double xl = __shfl(x, sl, 64), xh = __shfl(x, sh, 64);
+                const int cl = __shfl(cnt, sl, 64), ch = __shfl(cnt, sh, 64);
+                if (first > 0) {
+                    lo = xl;
+                    clo = cl;
+                }
+                if (first < kMsG) {
+                    hi = xh;
+                    chi = ch;
+                }
+            }
         }
-        if (i < c && u == 0) th[i] = 0.5 * (lo + hi);
+        // Laguerre's method (one lane of the group) from the middle of the
+        // isolating interval.  The characteristic polynomial has only real
+        // roots; from x left of lambda_i with no root in between, the right
+        // Laguerre point x + n / (s - G) (G = f'/f, H = G^2 - f''/f,
+        // s = sqrt((n-1)(nH - G^2))) lies in (x, lambda_i], and from the right
+        // the left point x - n / (s + G) in [lambda_i, x): the iterates
+        // approach lambda_i monotonically, cubically near it.  The count at x
+        // says which side x is on; a step that crossed lambda_i (rounding)
+        // only moves the bracket, the next one starts from its middle.
+        if (act && u == 0) {
+            double x = 0.5 * (lo + hi);
+            if (clo == i && chi == i + 1 && hi - lo > atol) {
+                const double nn = (double)c;
+                for (int it = 0; it < 48; ++it) {
+                    double f, f1, f2;
+                    const int cnt = sturm_laguerre(de, c, x, f, f1, f2);
+                    const bool right = cnt > i;  // x above lambda_i
+                    if (right)
+                        hi = x;
+                    else
+                        lo = x;
+                    if (hi - lo <= atol) {
+                        x = 0.5 * (lo + hi);
+                        break;
+                    }
+                    // within atol / 4 of a root by the Newton distance
+                    if (fabs(f) <= 0.25 * atol * fabs(f1)) break;
+                    const double G = f1 / f, H = G * G - f2 / f;
+                    const double sq = sqrt(fmax(0.0, (nn - 1.0) * (nn * H - G * G)));
+                    // n / (s -+ G) in the form without cancellation:
+                    // (s - G)(s + G) = n ((n - 1) H - G^2)
+                    const double den = (nn - 1.0) * H - G * G;
+                    double step;
+                    if (!right)
+                        step = G <= 0.0 ? nn / (sq - G) : (sq + G) / den;
+                    else
+                        step = -(G >= 0.0 ? nn / (sq + G) : (sq - G) / den);
+                    double xn = x + step;
+                    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+                    const double d = fabs(xn - x);
+                    x = xn;
+                    if (d <= 0.25 * atol) break;
+                }
+            }
+            th[i] = x;
+        }
     }
     __syncthreads();
 
@@ -339,7 +527,8 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
             p = a.keep > 0 ? a.keep : max(k + b, k + (c - k) / 2);
             p = min(p, ncv - b);
             p = max(p, min(k, ncv - b));
-            while (p < ncv - b && p < c && fabs(ldexp(th[p], sexp) - ldexp(th[p - 1], sexp)) <= 1e-10 * a.sigma)
+            while (p < ncv - b && p < c && p < s_pcap &&
+                   fabs(ldexp(th[p], sexp) - ldexp(th[p - 1], sexp)) <= 1e-10 * a.sigma)
                 ++p;
             p = min((p + 3) & ~3, ncv - b);
             m = min(c, max(p, k));
@@ -349,24 +538,37 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
         }
         s_p = p;
         s_m = m;
-        const double ortol = 1e-3 * tn, pertol = 10.0 * DBL_EPSILON * tn;
-        int ncl = 0;
+        // Clustering distance: inverse iteration alone gives a vector whose
+        // angle to the eigenvector is about eps ||T|| / gap, so eigenvalues
+        // closer than 100 eps / tol ||T|| (at most LAPACK's 1e-3 ||T||) are
+        // orthogonalised together, which keeps the restarted Krylov
+        // relation accurate to a small fraction of the tolerance.
+        double rel = 1e-3;
+        if (a.mode == 0 && a.tol > 0.0) rel = fmin(rel, 100.0 * DBL_EPSILON / a.tol);
+        const double ortol = rel * tn, pertol = 10.0 * DBL_EPSILON * tn;
+        int ncl = 0, multi = 0;
         cl_start[0] = 0;
         double prev = 0.0;
         for (int i = 0; i < m; ++i) {
             double s = th[i];
             if (i > 0) {
-                if (th[i] - th[i - 1] > ortol) cl_start[++ncl] = i;
+                if (th[i] - th[i - 1] > ortol) {
+                    multi |= (i - cl_start[ncl]) > 1;
+                    cl_start[++ncl] = i;
+                }
                 if (s - prev < pertol) s = prev + pertol;
             }
             sh[i] = s;
             prev = s;
         }
+        if (m > 0) multi |= (m - cl_start[ncl]) > 1;
         cl_start[++ncl] = m;
         s_ncl = ncl;
+        s_multi = multi;
     }
     __syncthreads();
     const int m = s_m;
+    const int ncl = s_ncl;
 
     // ---- stage 3: inverse iteration --------------------------------------------
     const double pivmin = DBL_EPSILON * tn;
@@ -401,18 +603,50 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
                 ai = bi - l * an;
                 bi = -l * bn;
             }
+            Y[o] = start_entry(tid, i);
         }
         double piv = ai;
         if (fabs(piv) < pivmin) piv = piv < 0.0 ? -pivmin : pivmin;
         U1[(size_t)(c - 1) * kRrLd + tid] = 1.0 / piv;
-        for (int r = 0; r < c; ++r) Y[(size_t)r * kRrLd + tid] = start_entry(tid, r);
+        Y[(size_t)(c - 1) * kRrLd + tid] = start_entry(tid, c - 1);
     }
-    const int ncl = s_ncl;
-    for (int it = 0; it < 3; ++it) {
-        if (tid < m) {
-            // forward: the row interchanges and multipliers
+    // my cluster has more than one member?
+    bool clustered = false;
+    if (tid < m) {
+        int cl = 0;
+        while (cl_start[cl + 1] <= tid) ++cl;
+        clustered = cl_start[cl + 1] - cl_start[cl] > 1;
+    }
+    const int nsolve = s_multi ? 3 : 2;
+    for (int it = 0; it < nsolve; ++it) {
+        if (tid < m && (it < 2 || clustered)) {
+            // forward: the row interchanges and multipliers (rows read eight ahead)
             double cur = Y[tid];
-            for (int i = 0; i + 1 < c; ++i) {
+            int i = 0;
+            for (; i + 8 < c; i += 8) {
+                double ny[8], lm[8], pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const size_t o = (size_t)(i + u) * kRrLd + tid;
+                    ny[u] = Y[o + kRrLd];
+                    lm[u] = Lm[o];
+                    pv[u] = PV[o];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const size_t o = (size_t)(i + u) * kRrLd + tid;
+                    double nxt = ny[u];
+                    if (pv[u] != 0.0) {
+                        Y[o] = nxt;
+                        nxt = cur - lm[u] * nxt;
+                    } else {
+                        Y[o] = cur;
+                        nxt = nxt - lm[u] * cur;
+                    }
+                    cur = nxt;
+                }
+            }
+            for (; i + 1 < c; ++i) {
                 const size_t o = (size_t)i * kRrLd + tid;
                 double nxt = Y[o + kRrLd];
                 const double l = Lm[o];
@@ -426,20 +660,47 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
                 cur = nxt;
             }
             Y[(size_t)(c - 1) * kRrLd + tid] = cur;
-            // backward substitution with U
-            double y1 = 0.0, y2 = 0.0;
-            for (int i = c - 1; i >= 0; --i) {
-                const size_t o = (size_t)i * kRrLd + tid;
+            // backward substitution with U; the sum of squares of the result
+            double y1 = 0.0, y2 = 0.0, nn = 0.0;
+            int r = c - 1;
+            for (; r >= 7; r -= 8) {
+                double yv[8], u1[8], u2[8], u3[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const size_t o = (size_t)(r - u) * kRrLd + tid;
+                    yv[u] = Y[o];
+                    u1[u] = U1[o];
+                    u2[u] = U2[o];
+                    u3[u] = U3[o];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double yi = (yv[u] - u2[u] * y1 - u3[u] * y2) * u1[u];
+                    Y[(size_t)(r - u) * kRrLd + tid] = yi;
+                    nn += yi * yi;
+                    y2 = y1;
+                    y1 = yi;
+                }
+            }
+            for (; r >= 0; --r) {
+                const size_t o = (size_t)r * kRrLd + tid;
                 const double yi = (Y[o] - U2[o] * y1 - U3[o] * y2) * U1[o];
                 Y[o] = yi;
+                nn += yi * yi;
                 y2 = y1;
                 y1 = yi;
             }
+            // a vector alone in its cluster is normalised in the
+            // back-transformation (three solves stay far from overflow:
+            // each grows the vector by at most about 1 / (eps ||T||))
+            if (!clustered) ysc[tid] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
         }
+        if (!s_multi) continue;
         __syncthreads();
-        // orthonormalise each cluster (a singleton is only normalised)
-        for (int cl = w; cl < ncl; cl += 16) {
+        // orthonormalise each cluster with more than one member
+        for (int cl = w; cl < ncl; cl += kRrW) {
             const int s0 = cl_start[cl], s1 = cl_start[cl + 1];
+            if (s1 - s0 < 2) continue;
             for (int jv = s0; jv < s1; ++jv) {
                 double yv[NC];
 #pragma unroll
@@ -457,7 +718,7 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
 #pragma unroll
                     for (int t = 0; t < NC; ++t) yv[t] *= inv;
                 }
-                const int passes = it == 2 ? 2 : 1;
+                const int passes = it == nsolve - 1 ? 2 : 1;
                 for (int pass = 0; pass < passes; ++pass)
                     for (int qv = s0; qv < jv; ++qv) {
                         double yq[NC], dp = 0.0;
@@ -481,58 +742,80 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
                     const int r = 64 * t + lane;
                     if (r < c) Y[(size_t)r * kRrLd + jv] = yv[t] * inv;
                 }
+                if (lane == 0) ysc[jv] = 1.0;
             }
         }
         __syncthreads();
     }
+    __syncthreads();
 
     // ---- stage 4: back-transformation Z = Q Y ------------------------------------
+    // Sixteen lanes per column (rows sl + 16 t), two columns per group of
+    // sixteen lanes (c0 and c0 + 64; one for the largest orders, where the
+    // registers would not hold two), 64 CS columns per pass.  The
+    // reflectors are staged through LDS sixteen at a time, last first.
     {
-        double y[NR][NC];
+        constexpr int CS = NC == 3 ? 1 : 2;
+        const int sl = lane & 15, gi = 4 * w + (lane >> 4);
+        for (int pbase = 0; pbase < m; pbase += 64 * CS) {
+            const int c0 = pbase + gi, c1 = CS == 2 ? pbase + 64 + gi : m;
+            const bool any0 = pbase + 4 * w < m, any1 = CS == 2 && pbase + 64 + 4 * w < m;  // uniform per wavefront
+            const double sc0 = c0 < m ? ysc[c0] : 0.0, sc1 = c1 < m ? ysc[c1] : 0.0;
+            double y0[NT], y1[NT];
 #pragma unroll
-        for (int u = 0; u < NR; ++u) {
-            const int col = w + 16 * u;
-#pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                const int r = 64 * t + lane;
-                y[u][t] = (col < m && r < c) ? Y[(size_t)r * kRrLd + col] : 0.0;
+            for (int t = 0; t < NT; ++t) {
+                const int r = sl + 16 * t;
+                y0[t] = (c0 < m && r < c) ? Y[(size_t)r * kRrLd + c0] * sc0 : 0.0;
+                y1[t] = (c1 < m && r < c) ? Y[(size_t)r * kRrLd + c1] * sc1 : 0.0;
             }
-        }
-        for (int j = c - 3; j >= 0; --j) {
-            const double tau = tau_s[j];
-            if (tau == 0.0) continue;
-            double v[NC];
+            for (int jc = c - 3; jc >= 0; jc -= kRrW) {
+                const int nj = min(kRrW, jc + 1);
+                __syncthreads();
+                for (int idx = tid; idx < nj * c; idx += kRrT) {
+                    const int jj = idx / c, r = idx - jj * c;
+                    part[jj][r] = HV[(size_t)(jc - jj) * kRrMax + r];
+                }
+                __syncthreads();
+                if (!any0) continue;
+                for (int jj = 0; jj < nj; ++jj) {
+                    const double tau = tau_s[jc - jj];
+                    if (tau == 0.0) continue;
+                    double v[NT];
 #pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                const int r = 64 * t + lane;
-                v[t] = r < c ? HV[(size_t)j * kRrMax + r] : 0.0;
-            }
+                    for (int t = 0; t < NT; ++t) {
+                        const int r = sl + 16 * t;
+                        v[t] = r < c ? part[jj][r] : 0.0;
+                    }
+                    double s0 = 0.0;
 #pragma unroll
-            for (int u = 0; u < NR; ++u) {
-                if (w + 16 * u < m) {
-                    double s = 0.0;
+                    for (int t = 0; t < NT; ++t) s0 += v[t] * y0[t];
+                    if (any1) {
+                        double s1 = 0.0;
 #pragma unroll
-                    for (int t = 0; t < NC; ++t) s += v[t] * y[u][t];
-                    s = tau * wsum(s);
+                        for (int t = 0; t < NT; ++t) s1 += v[t] * y1[t];
+                        s1 = tau * sum16(s1);
 #pragma unroll
-                    for (int t = 0; t < NC; ++t) y[u][t] -= s * v[t];
+                        for (int t = 0; t < NT; ++t) y1[t] -= s1 * v[t];
+                    }
+                    s0 = tau * sum16(s0);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) y0[t] -= s0 * v[t];
                 }
             }
-        }
 #pragma unroll
-        for (int u = 0; u < NR; ++u) {
-            const int col = w + 16 * u;
-#pragma unroll
-            for (int t = 0; t < NC; ++t) {
-                const int r = 64 * t + lane;
-                if (col < m && r < c) Zs[(size_t)r * kRrLd + col] = y[u][t];
+            for (int t = 0; t < NT; ++t) {
+                const int r = sl + 16 * t;
+                if (r < c) {
+                    if (c0 < m) Zs[(size_t)r * kRrLd + c0] = y0[t];
+                    if (c1 < m) Zs[(size_t)r * kRrLd + c1] = y1[t];
+                }
             }
         }
     }
     __syncthreads();
 
     // ---- outputs ------------------------------------------------------------------
-    for (int i = tid; i < c; i += kRrT) a.theta[i] = ldexp(th[i], sexp);
+    for (int i = tid; i < nev; i += kRrT) a.theta[i] = ldexp(th[i], sexp);
     if (a.mode == 1) {
         for (int idx = tid; idx < c * m; idx += kRrT) {
             const int r = idx / m, col = idx - r * m;
@@ -631,6 +914,8 @@ int rr_launch(const RrArgs& a, hipStream_t s) {
     }
     if (a.c <= 64)
         k_rr<4, 1><<<1, kRrT, 0, s>>>(a);
+    else if (a.c <= 96)
+        k_rr<6, 2><<<1, kRrT, 0, s>>>(a);
     else if (a.c <= 128)
         k_rr<8, 2><<<1, kRrT, 0, s>>>(a);
     else
