@@ -989,6 +989,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
             if (S.info) S.info->block_steps += 1;
             continue;
         }
+        if (!(rec[1] >= 0.0))
+            return set_error(SFAIRSC_E_HIP, "the projected matrix is not finite (the operator produced NaN or Inf)");
         const int nconv = (int)rec[0], p = (int)rec[1], m = (int)rec[2];
         const double gap = rec[3];
         if (S.info) {

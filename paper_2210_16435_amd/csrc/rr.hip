@@ -254,16 +254,45 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     // scale by a power of two (exact) so that max |T_ij| lies in [1/2, 1):
     // no overflow or underflow in the squares and Sturm recurrences below;
     // eigenvalues are scaled back on output, eigenvectors are unchanged
+    bool finite;
     {
-        double mx = 0.0;
+        // fmax drops NaNs; a scaled sum keeps them (and infinities) without
+        // overflowing on finite entries
+        double mx = 0.0, sm = 0.0;
 #pragma unroll
         for (int q = 0; q < NR; ++q)
 #pragma unroll
-            for (int t = 0; t < NC; ++t) mx = fmax(mx, fabs(A[q][t]));
+            for (int t = 0; t < NC; ++t) {
+                mx = fmax(mx, fabs(A[q][t]));
+                sm += A[q][t] * 0x1p-1000;
+            }
+        finite = isfinite(sm);
         mx = wmax(mx);
         if (lane == 0) red[w] = mx;
     }
-    __syncthreads();
+    // a non-finite entry: every output is NaN (the residual estimates
+    // infinite, no pair converged, no vector kept)
+    if (!__syncthreads_and(finite)) {
+        const double nan = __builtin_nan("");
+        for (int i = tid; i < c; i += kRrT) a.theta[i] = nan;
+        if (a.mode == 1) {
+            for (int idx = tid; idx < c * a.mreq; idx += kRrT) a.Zout[idx] = nan;
+            return;
+        }
+        if (a.Zk)
+            for (int idx = tid; idx < c * a.k; idx += kRrT) a.Zk[idx] = nan;
+        if (tid == 0) {
+            a.rec[0] = 0.0;
+            a.rec[1] = -1.0;
+            a.rec[2] = 0.0;
+            a.rec[3] = nan;
+        }
+        for (int i = tid; i < a.k; i += kRrT) {
+            a.rec[kRrRecHead + i] = nan;
+            a.rec[kRrRecHead + a.k + i] = INFINITY;
+        }
+        return;
+    }
     int sexp = 0;
     {
         double mx = 0.0;
@@ -514,7 +543,8 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
                     if (d <= 0.25 * atol) break;
                 }
             }
-            th[i] = x;
+            // inside the Gershgorin interval (exactly 0 for a zero matrix)
+            th[i] = fmin(fmax(x, s_gl), s_gu);
         }
     }
     __syncthreads();
