@@ -206,6 +206,31 @@ int sfairsc_apply_operator(sfairsc_graph_t g, const double* X, double* Y,
                            hipStream_t stream);
 
 /*
+ * The same Y = L^sigma X as sfairsc_apply_operator, through the same
+ * kernels, for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc.  Its
+ * scratch (group-sum partials, the projected input and the sparse product,
+ * the small tables) lives in a 64 MiB device array inside the library, one
+ * copy per GPU, held until the process ends; nothing is allocated or freed
+ * (the graph handle must already exist).
+ *
+ * Limits: the group constraint only (a handle with
+ * sfairsc_graph_set_constraint or sfairsc_graph_set_memberships gives
+ * E_ARG), and 2 n BW s plus the partials within 64 MiB, with BW = b rounded
+ * up to 4, 8, 16 or 32 and s = 4 (mixed) or 8 (FP64) bytes: about n <= 2
+ * million at b = 4 mixed, 500,000 at b = 8 FP64, 125,000 at b = 32 FP64.
+ * A larger problem returns E_ARG and launches nothing.
+ * All calls on one GPU share the array: calls that overlap in time on one
+ * GPU (different streams or threads) race and must be serialised by the
+ * caller.  Every scratch element a call reads is written earlier in the same
+ * call, so nothing carries over from the previous call.
+ * Arguments, layout and the other errors as sfairsc_apply_operator.
+ */
+int sfairsc_apply_operator_noalloc(sfairsc_graph_t g, const double* X,
+                                   double* Y, int32_t b, int precision,
+                                   double sigma, hipStream_t stream);
+
+/*
  * T = L_n X (normalized) or T = L X (unnormalized) with no projection: the
  * sparse product alone (the matrix-vector product of Section 3.4 (i)).
  * X, T   device row-major n x b, 1 <= b <= 32, float for SFAIRSC_PREC_MIXED

@@ -220,6 +220,24 @@ class Graph:
         )
         return Y
 
+    def apply_operator_noalloc(self, X: torch.Tensor, Y: torch.Tensor, precision="fp64", sigma: float = 0.0,
+                               stream=None) -> torch.Tensor:
+        """Y = L^sigma X into the caller's Y through the no-allocation entry point.
+
+        X and Y: contiguous float64 (n, b) tensors on the graph's device; the
+        library allocates nothing (its scratch is a fixed device array).
+        """
+        if X.dim() != 2 or Y.shape != X.shape or X.dtype != torch.float64 or Y.dtype != torch.float64:
+            raise ValueError("X and Y must be float64 tensors of the same shape (n, b)")
+        if not (X.is_contiguous() and Y.is_contiguous()):
+            raise ValueError("X and Y must be contiguous")
+        _lib.check(
+            _lib.lib().sfairsc_apply_operator_noalloc(
+                self._h, _ptr(X), _ptr(Y), X.shape[1], _prec(precision), float(sigma), _stream(stream)
+            )
+        )
+        return Y
+
     def spmm(self, X: torch.Tensor, precision="fp64", stream=None) -> torch.Tensor:
         """T = L X (or L_n X): float32 in and out for 'mixed', float64 for 'fp64'."""
         dt = torch.float32 if _prec(precision) == PREC_MIXED else torch.float64

@@ -159,6 +159,7 @@ PROTOTYPES = {
     "sfairsc_graph_set_memberships": (_int, [_vp, _i32, _vp, _vp, _i32, _dbl, _i32, _vp]),
     "sfairsc_lsqr_stats": (_int, [_vp, ctypes.POINTER(_i64), _vp]),
     "sfairsc_apply_operator": (_int, [_vp, _vp, _vp, _i32, _int, _dbl, _vp]),
+    "sfairsc_apply_operator_noalloc": (_int, [_vp, _vp, _vp, _i32, _int, _dbl, _vp]),
     "sfairsc_spmm": (_int, [_vp, _vp, _vp, _i32, _int, _vp]),
     "sfairsc_eigs_opts_init": (None, [ctypes.POINTER(EigsOpts)]),
     "sfairsc_eigs": (

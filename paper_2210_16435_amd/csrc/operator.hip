@@ -13,6 +13,7 @@
 // Every reduction has a fixed order (per-block partials combined in block
 // order), so results are bitwise reproducible run to run.
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 #include "reduce.h"
@@ -453,6 +454,71 @@ static int gen_apply(sfairsc_graph* g, const double* X, int ldx, int b, int mixe
     return gen_correct(g, w.t.p, mixed != 0, BW, b, sigma, Y, ldy, s, skip);
 }
 
+// Device buffers of one operator application with the group constraint.
+struct OpBufs {
+    double* part_in;  // [nblk_proj][h][b]
+    int nblk_proj;
+    double* part_out;  // [nblk_spmm][h][b]
+    int nblk_spmm;
+    double* small;  // R_in, S, R_out tables: 3 x [kMaxGroups][32]
+    void* xp;       // projected input, n x BW (float or double)
+    void* t;        // sparse product output, n x BW (float or double)
+};
+
+// S = C^T X, X' = P X, T = L_n X' (with C^T T), R_out table: everything up
+// to the deflation of the output, in the buffers B.
+static int op_apply_core(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
+                         hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, const OpBufs& B, OpOut* out) {
+    const int BW = pad_width(b);
+    const int64_t n = g->n;
+    double* Rin = B.small;
+    double* Sx = Rin + kMaxGroups * 32;
+    double* Rout = Sx + kMaxGroups * 32;
+    const int h = g->h;
+
+    // S = C^T X, R_in table
+    launch_proj_partial(X, ldx, b, n, g->grp, g->cs, h, B.part_in, B.nblk_proj, skip, s);
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(B.part_in, B.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx, Rin, skip);
+    const int ga = grid_rows(n * BW, 256, 8192);
+    if (mixed) {
+        float* xp = static_cast<float*>(B.xp);
+        float* t = static_cast<float*>(B.t);
+        k_proj_apply<float><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<float>(g, BW, xp, t, g->val32, g->diag32, b, B.part_out, B.nblk_spmm, s, skip);
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+    } else {
+        double* xp = static_cast<double*>(B.xp);
+        double* t = static_cast<double*>(B.t);
+        k_proj_apply<double><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<double>(g, BW, xp, t, g->val64, g->diag64, b, B.part_out, B.nblk_spmm, s, skip);
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+    }
+    // U = G^{-1} (C^T T - sigma S), R_out table
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(B.part_out, B.nblk_spmm, h, b, g->gpar, Sx, sigma, nullptr, Rout,
+                                               skip);
+    SF_HIP(hipGetLastError());
+    out->t = B.t;
+    out->is_float = mixed != 0;
+    out->BW = BW;
+    out->rtab = Rout;
+    return SFAIRSC_OK;
+}
+
+// Y = T - C R_out (the deflation of the output) into Y (double, ldy).
+static int op_deflate(sfairsc_graph* g, const OpOut& o, int b, double* Y, int ldy, hipStream_t s, const int* skip) {
+    const int64_t n = g->n;
+    if (o.is_float)
+        k_defl_apply<float><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const float*)o.t, o.BW, b, n, g->grp, g->cs,
+                                                                         o.rtab, Y, ldy, skip);
+    else
+        k_defl_apply<double><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const double*)o.t, o.BW, b, n, g->grp,
+                                                                          g->cs, o.rtab, Y, ldy, skip);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
@@ -468,42 +534,9 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
         return SFAIRSC_OK;
     }
     OpWork& w = g->op;
-    const int BW = pad_width(b);
-    const int64_t n = g->n;
-    double* Rin = w.small.as<double>();
-    double* Sx = Rin + kMaxGroups * 32;
-    double* Rout = Sx + kMaxGroups * 32;
-    const int h = g->h;
-
-    // S = C^T X, R_in table
-    launch_proj_partial(X, ldx, b, n, g->grp, g->cs, h, w.part_in.as<double>(), w.nblk_proj, skip, s);
-    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, b, g->gpar, nullptr, 0.0, Sx,
-                                               Rin, skip);
-    const int ga = grid_rows(n * BW, 256, 8192);
-    if (mixed) {
-        float* xp = w.xp.as<float>();
-        float* t = w.t.as<float>();
-        k_proj_apply<float><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
-        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
-        launch_spmm<float>(g, BW, xp, t, g->val32, g->diag32, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
-        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
-    } else {
-        double* xp = w.xp.as<double>();
-        double* t = w.t.as<double>();
-        k_proj_apply<double><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, Rin, xp, skip);
-        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
-        launch_spmm<double>(g, BW, xp, t, g->val64, g->diag64, b, w.part_out.as<double>(), w.nblk_spmm, s, skip);
-        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
-    }
-    // U = G^{-1} (C^T T - sigma S), R_out table
-    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_out.as<double>(), w.nblk_spmm, h, b, g->gpar, Sx, sigma,
-                                               nullptr, Rout, skip);
-    SF_HIP(hipGetLastError());
-    out->t = w.t.p;
-    out->is_float = mixed != 0;
-    out->BW = BW;
-    out->rtab = Rout;
-    return SFAIRSC_OK;
+    const OpBufs B{w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(), w.nblk_spmm, w.small.as<double>(),
+                   w.xp.p, w.t.p};
+    return op_apply_core(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, B, out);
 }
 
 int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
@@ -515,15 +548,73 @@ int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int
     }
     OpOut o;
     SF_TRY(op_apply_t(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, &o));
-    const int64_t n = g->n;
-    if (o.is_float)
-        k_defl_apply<float><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const float*)o.t, o.BW, b, n, g->grp, g->cs,
-                                                                         o.rtab, Y, ldy, skip);
-    else
-        k_defl_apply<double><<<grid_rows(n * b, 256, 8192), 256, 0, s>>>((const double*)o.t, o.BW, b, n, g->grp,
-                                                                          g->cs, o.rtab, Y, ldy, skip);
-    SF_HIP(hipGetLastError());
+    return op_deflate(g, o, b, Y, ldy, s, skip);
+}
+
+// ---------------------------------------------------------------------------
+// The operator without allocation: its scratch is a file-scope device array
+// (one copy per GPU, held until the process ends), reached through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current.
+static int scratch_address(int dev, void** out) {
+    if (dev < 0 || dev >= kScratchDevices) return set_error(SFAIRSC_E_ARG, "device %d outside [0, %d)", dev, kScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        SF_HIP(hipGetDevice(&cur));
+        if (cur != dev) SF_HIP(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return set_error(SFAIRSC_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
     return SFAIRSC_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int op_apply_noalloc(sfairsc_graph* g, const double* X, double* Y, int b, int mixed, double sigma,
+                            hipStream_t s) {
+    if (g->qbas || g->memb)
+        return set_error(SFAIRSC_E_ARG, "the no-allocation operator takes the group constraint only");
+    const int64_t n = g->n;
+    const int h = g->h;
+    const int BW = pad_width(b);
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    const int nblk_spmm = grid_rows(n, kSpmmWaves, kSpmmMaxBlocks);
+    const int nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
+    const size_t o_in = 0;
+    const size_t o_out = o_in + align256((size_t)nblk_proj * h * b * sizeof(double));
+    const size_t o_small = o_out + align256((size_t)nblk_spmm * h * b * sizeof(double));
+    const size_t o_xp = o_small + align256((size_t)5 * kMaxGroups * 32 * sizeof(double));
+    const size_t o_t = o_xp + align256((size_t)n * BW * es);
+    const size_t need = o_t + align256((size_t)n * BW * es);
+    if (need > kNoAllocScratchBytes)
+        return set_error(SFAIRSC_E_ARG,
+                         "n = %lld with block width %d needs %zu bytes of scratch, more than the %zu of the "
+                         "no-allocation operator",
+                         (long long)n, b, need, kNoAllocScratchBytes);
+    void* base = nullptr;
+    SF_TRY(scratch_address(g->device, &base));
+    char* p = static_cast<char*>(base);
+    const OpBufs B{reinterpret_cast<double*>(p + o_in),  nblk_proj, reinterpret_cast<double*>(p + o_out), nblk_spmm,
+                   reinterpret_cast<double*>(p + o_small), p + o_xp, p + o_t};
+    OpOut o;
+    SF_TRY(op_apply_core(g, X, b, b, mixed, sigma, s, nullptr, nullptr, nullptr, B, &o));
+    return op_deflate(g, o, b, Y, b, s, nullptr);
 }
 
 // X_i -= c_i R_{g_i} in place (X double, leading dimension ldx, b columns).
@@ -622,6 +713,16 @@ extern "C" int sfairsc_apply_operator(sfairsc_graph_t g, const double* X, double
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
     if (sigma <= 0.0) sigma = g->sigma;
     return op_apply(g, X, b, Y, b, b, precision == SFAIRSC_PREC_MIXED, sigma, stream);
+}
+
+extern "C" int sfairsc_apply_operator_noalloc(sfairsc_graph_t g, const double* X, double* Y, int32_t b,
+                                              int precision, double sigma, hipStream_t stream) {
+    if (!g || !X || !Y) return set_error(SFAIRSC_E_ARG, "NULL argument");
+    if (precision != SFAIRSC_PREC_FP64 && precision != SFAIRSC_PREC_MIXED)
+        return set_error(SFAIRSC_E_ARG, "unknown precision %d", precision);
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    if (sigma <= 0.0) sigma = g->sigma;
+    return op_apply_noalloc(g, X, Y, b, precision == SFAIRSC_PREC_MIXED, sigma, stream);
 }
 
 extern "C" int sfairsc_spmm(sfairsc_graph_t g, const void* X, void* T, int32_t b, int precision,
