@@ -189,7 +189,7 @@ def main():
     phase_break = {}
     for prec in precs:
         tot_ms, launches = 0.0, 0
-        acc = {"spmm_ms": 0.0, "operator_ms": 0.0, "ortho_ms": 0.0, "restart_ms": 0.0, "rr_host_ms": 0.0}
+        acc = {"spmm_ms": 0.0, "operator_ms": 0.0, "ortho_ms": 0.0, "restart_ms": 0.0, "rr_ms": 0.0}
         for _ in range(3):
             r = solve(prec, timing=True)
             slot = 1 if prec == "mixed" else 0
@@ -199,17 +199,17 @@ def main():
             acc["operator_ms"] += r.info["operator_ms"]
             acc["ortho_ms"] += r.info["ortho_ms"]
             acc["restart_ms"] += r.info["restart_ms"]
-            acc["rr_host_ms"] += r.info["rr_ms"]
+            acc["rr_ms"] += r.info["rr_ms"]
         spmm[prec] = (tot_ms / max(launches, 1), launches / 3)
         # per solve: SpMM, the rest of the operator (projections, C^T T),
-        # CGS2 + Cholesky-QR, restart rotation (GPU event time), host RR
+        # CGS2 + Cholesky-QR, restart rotation, Rayleigh-Ritz (GPU event time)
         ph = {key: v / 3 for key, v in acc.items()}
         phase_break[prec] = {
             "spmm_ms": round(ph["spmm_ms"], 3),
             "projection_ms": round(max(ph["operator_ms"] - ph["spmm_ms"], 0.0), 3),
             "cgs2_cholqr_ms": round(ph["ortho_ms"], 3),
             "restart_ms": round(ph["restart_ms"], 3),
-            "rayleigh_ritz_host_ms": round(ph["rr_host_ms"], 3),
+            "rayleigh_ritz_ms": round(ph["rr_ms"], 3),
         }
 
     # labels (Alg. 3 step 4) once, for the record
@@ -271,6 +271,8 @@ def main():
             "batched_256": bench_batched(sf, torch),
             "backward_200k": bench_backward(sf, torch),
             "mixed_2m": bench_2m(sf, torch),
+            "config1_2k": bench_config1(sf, torch),
+            "h_sweep_10k": bench_h_sweep(sf, torch),
         }
 
     out = {
@@ -497,6 +499,12 @@ def bench_batched(sf, torch):
     ms = (time.perf_counter() - t0) * 1e3 / reps
     graph_ms = np.array([r.info["graph_ms"] for r in rs])
     phases = np.array([r.info["phase_ms"] for r in rs]).sum(0)
+    spmm_total = 0
+    for g, r in zip(graphs, rs):
+        if r.info["path"] != 0:
+            continue
+        sv = 8 if r.info["double_spmm"] else 4
+        spmm_total += r.info["block_steps"] * spmm_bytes(g.n, g.nnz, r.info["block_width"], sv, sv)
     # the same graphs one after another through the single-graph solver
     t0 = time.perf_counter()
     for G, k, h in zip(Gs, ks, H):
@@ -521,7 +529,14 @@ def bench_batched(sf, torch):
             )
         },
         "solved_in_launch": int(sum(1 for r in rs if r.info["path"] == 0)),
-        "all_converged": bool(all(r.status == 0 for r in rs)),
+        "all_converged": bool(all(r.status in (0, sf.E_DEGENERATE) for r in rs)),
+        "degenerate_graphs": int(sum(1 for r in rs if r.status == sf.E_DEGENERATE)),
+        # algorithmic bytes of every sparse product the launch ran (one per
+        # block step and graph, at the graph's block width and value size)
+        # over the whole launch: a lower bound on the sparse-product rate,
+        # since the launch also orthogonalises and solves Rayleigh-Ritz
+        "spmm_algorithmic_bytes": int(spmm_total),
+        "spmm_algorithmic_gbps_over_launch": round(spmm_total / (rs[0].info["batch_ms"] * 1e-3) / 1e9, 1),
         "max_rel_residual": float(max(r.info["max_rel_residual"] for r in rs)),
         "sequential_single_graph_ms": round(seq_ms, 1),
         "speedup_vs_sequential": round(seq_ms / ms, 2),
@@ -587,40 +602,164 @@ def bench_backward(sf, torch):
 
 def bench_2m(sf, torch):
     """n = 2,000,000 unnormalized modified SBM, k = 20, h = 8, degree 30,
-    weights U(0.5, 1.5), float sparse products, block width 32, tol 1e-6."""
+    weights U(0.5, 1.5), block width 32, tol 1e-6: the mixed solve (float
+    sparse products) and the FP64 solve at the same tolerance, with the
+    per-phase times of each (HIP events inside the library)."""
     from sfairsc_inputs import workload
 
     g = workload("msbm-2m-h8")
     G = sf.Graph.from_msbm(g, False)
     k, b = 20, 32
     H = torch.empty((k, g.n), dtype=torch.float64, device="cuda")
-    G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    rt = G.eigs(k, tol=1e-6, precision="mixed", block_width=b, H_out=H, time_kernels=True)
-    launches = rt.info["spmm_launches"][1]
-    spmm_ms = rt.info["spmm_ms"][1] / max(launches, 1)
-    by = spmm_bytes(g.n, g.nnz, b, 4, 4)
     out = {
-        "workload": "msbm-2m-h8 (n=2e6, k=20, h=8, degree 30, tol 1e-6, mixed, b=32)",
+        "workload": "msbm-2m-h8 (n=2e6, k=20, h=8, degree 30, tol 1e-6, b=32)",
         "n": g.n,
         "nnz": g.nnz,
-        "ms_per_solve": round(ms, 2),
-        "block_steps": r.info["block_steps"],
-        "restarts": r.info["restarts"],
-        "max_rel_residual": r.info["max_rel_residual"],
-        "spmm_launch_ms": round(spmm_ms, 4),
-        "spmm_bytes": by,
-        "spmm_gbps": round(by / (spmm_ms * 1e-3) / 1e9, 1) if spmm_ms > 0 else None,
-        "rr_ms": round(r.info["rr_ms"], 1),
     }
-    _log(f"2m: {out}")
+    for prec in ("mixed", "fp64"):
+        G.eigs(k, tol=1e-6, precision=prec, block_width=b, H_out=H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = G.eigs(k, tol=1e-6, precision=prec, block_width=b, H_out=H)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        rt = G.eigs(k, tol=1e-6, precision=prec, block_width=b, H_out=H, time_kernels=True)
+        slot = 1 if prec == "mixed" else 0
+        launches = rt.info["spmm_launches"][slot]
+        spmm_ms = rt.info["spmm_ms"][slot] / max(launches, 1)
+        sv = 4 if prec == "mixed" else 8
+        by = spmm_bytes(g.n, g.nnz, b, sv, sv)
+        spmm_tot = sum(rt.info["spmm_ms"])
+        out[prec] = {
+            "ms_per_solve": round(ms, 2),
+            "block_steps": r.info["block_steps"],
+            "restarts": r.info["restarts"],
+            "max_rel_residual": r.info["max_rel_residual"],
+            "spmm_launch_ms": round(spmm_ms, 4),
+            "spmm_bytes": by,
+            "spmm_gbps": round(by / (spmm_ms * 1e-3) / 1e9, 1) if spmm_ms > 0 else None,
+            "phase_breakdown": {
+                "spmm_ms": round(spmm_tot, 2),
+                "projection_ms": round(max(rt.info["operator_ms"] - spmm_tot, 0.0), 2),
+                "cgs2_cholqr_ms": round(rt.info["ortho_ms"], 2),
+                "restart_ms": round(rt.info["restart_ms"], 2),
+                "rayleigh_ritz_ms": round(rt.info["rr_ms"], 2),
+            },
+        }
+        _log(f"2m {prec}: {out[prec]}")
+    out["mixed_vs_fp64_speedup"] = round(out["fp64"]["ms_per_solve"] / out["mixed"]["ms_per_solve"], 3)
+    _log(f"2m: speedup {out['mixed_vs_fp64_speedup']}")
     del G, H
     torch.cuda.empty_cache()
     return out
+
+
+def misclustered_fraction(labels, truth):
+    """Fraction of vertices outside the best one-to-one match of found and
+    planted clusters (Hungarian assignment on the contingency table)."""
+    from scipy.optimize import linear_sum_assignment
+
+    labels = np.asarray(labels)
+    truth = np.asarray(truth)
+    kl, kt = labels.max() + 1, truth.max() + 1
+    cont = np.zeros((kl, kt), dtype=np.int64)
+    np.add.at(cont, (labels, truth), 1)
+    r, c = linear_sum_assignment(-cont)
+    return float(1.0 - cont[r, c].sum() / labels.size)
+
+
+def bench_config1(sf, torch):
+    """The 2,000-vertex unnormalized m-SBM (k = 5 clusters of 400, h = 2 with
+    200/200 per cluster), FP64, the 5 smallest fair eigenpairs to tol 1e-10,
+    then k-means (k = 5, 10 restarts, seed 0): time-to-tol (median of 10 after
+    2 warm-ups), k-means time and the misclustered fraction against the
+    planted clusters."""
+    from sfairsc_inputs import WORKLOADS, workload
+
+    p = WORKLOADS["msbm-2k-h2"][1]
+    g = workload("msbm-2k-h2", relabel_seed=2)
+    G = sf.Graph.from_msbm(g, p["normalized"])
+    k = p["k"]
+    H = torch.empty((k, g.n), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        G.eigs(k, tol=p["tol"], precision="fp64", block_width=p["block"], H_out=H)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(10):
+        t0 = time.perf_counter()
+        r = G.eigs(k, tol=p["tol"], precision="fp64", block_width=p["block"], H_out=H)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    G.labels(r.H, k, n_restarts=10, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lab, inertia = G.labels(r.H, k, n_restarts=10, seed=0)
+    torch.cuda.synchronize()
+    km_ms = (time.perf_counter() - t0) * 1e3
+    out = {
+        "workload": "msbm-2k-h2 (n=2000, k=5, h=2, unnormalized, FP64, tol 1e-10; k-means 10 restarts, seed 0)",
+        "nnz": g.nnz,
+        "time_to_tol_ms": round(float(np.median(ts)), 3),
+        "block_steps": r.info["block_steps"],
+        "restarts": r.info["restarts"],
+        "max_rel_residual": r.info["max_rel_residual"],
+        "eigenvalues": [float(x) for x in r.eigenvalues],
+        "kmeans_ms": round(km_ms, 3),
+        "misclustered_fraction": misclustered_fraction(lab.cpu().numpy(), g.clusters),
+    }
+    _log(f"config 1: {out}")
+    del G, H
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_h_sweep(sf, torch):
+    """The cost of fairness as the number of groups grows (the paper's
+    h-sweep): m-SBM with n = 10,000, k = 5 equal clusters, h in {2, 5, 10}
+    equal groups per cluster, probabilities (10, 7, 4, 1) x (ln n / n)^(2/3)
+    in the paper's meaning (same cluster and group, different cluster and same
+    group, same cluster and different group, neither); normalized, k = 5,
+    tol 1e-8, float sparse products.  Fair against plain SC (one group) on
+    the same graph, median of 5 solves each."""
+    import dataclasses
+
+    from sfairsc_inputs.msbm import fair_block_sizes, msbm_from_blocks, relabel
+
+    n, kc = 10000, 5
+    s = (np.log(n) / n) ** (2.0 / 3.0)
+    a, b_, c_, d_ = 10 * s, 7 * s, 4 * s, 1 * s
+    rows = []
+    for h in (2, 5, 10):
+        u = fair_block_sizes([n // kc] * kc, [1] * h)
+        g = relabel(msbm_from_blocks(u, (a, c_, b_, d_), seed=200 + h), 2)
+        gs = dataclasses.replace(g, groups=np.zeros(g.n, dtype=np.int32), h=1)
+        H = torch.empty((kc, g.n), dtype=torch.float64, device="cuda")
+        row = {"h": h, "nnz": g.nnz}
+        for name, gg in (("fair", g), ("sc", gs)):
+            G = sf.Graph.from_msbm(gg, True)
+            G.eigs(kc, tol=1e-8, precision="mixed", H_out=H)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                r = G.eigs(kc, tol=1e-8, precision="mixed", H_out=H)
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            row[f"{name}_ms"] = round(float(np.median(ts)), 3)
+            row[f"{name}_block_steps"] = r.info["block_steps"]
+            if name == "fair":
+                lab, _ = G.labels(r.H, kc, n_restarts=10, seed=0)
+                row["fair_misclustered"] = misclustered_fraction(lab.cpu().numpy(), g.clusters)
+            del G
+        row["fair_over_sc"] = round(row["fair_ms"] / row["sc_ms"], 3)
+        rows.append(row)
+        _log(f"h sweep: {row}")
+        del H
+        torch.cuda.empty_cache()
+    return {
+        "workload": "m-SBM n=10000, k=5, h in {2,5,10}, (10,7,4,1)(ln n/n)^(2/3), normalized, tol 1e-8, mixed",
+        "runs": rows,
+    }
 
 
 def _source_hash():
