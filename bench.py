@@ -64,6 +64,11 @@ def main():
         help="only run the n = 50,000 headline graph with one-hot memberships through LSQR twice (for profilers)",
     )
     ap.add_argument(
+        "--backward-profile",
+        action="store_true",
+        help="only run the n = 200,000 backward (after one FP64 forward solve) twenty times (for profilers)",
+    )
+    ap.add_argument(
         "--copy-calibration",
         action="store_true",
         help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
@@ -78,6 +83,13 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}))
+        return
+    if args.backward_profile:
+        import torch
+
+        import paper_2210_16435_amd as sf
+
+        print(json.dumps(bench_backward(sf, torch)))
         return
     if args.batched_profile:
         import torch
