@@ -40,7 +40,7 @@ constexpr int kTsThreads = 256;
 constexpr int kTsRows = 8;
 constexpr int kTsAcc = (kLdMax * kMaxBlock + kTsThreads - 1) / kTsThreads;  // 28
 constexpr int kTsMaxBlocks = 512;
-constexpr int kRotRows = 16;
+constexpr int kRotRows = 32;
 constexpr int kStatBlocks = 256;
 constexpr int kStatsDoubles = kStatBlocks * 2 * kMaxK;
 constexpr int kStatsIdx = kStatBlocks * kMaxK;
@@ -249,45 +249,39 @@ __global__ __launch_bounds__(1024) void k_chol(const double* __restrict__ part, 
     }
 }
 
-// Rows: out = V[:, 0:c] Q (Q: c x p row-major).  mode 0 (restart, in place):
-// V[:, 0:p] = out and V[:, p:p+b] = old V[:, c:c+b].  mode 1: out written to
-// Xo row-major with leading dimension ldo (optional row scale).
-__global__ __launch_bounds__(256) void k_rotate(double* __restrict__ V, int ldv, int64_t n, int c, int p, int b,
-                                                 const double* __restrict__ Q, int mode, double* __restrict__ Xo,
-                                                 int ldo, const double* __restrict__ scale) {
-    extern __shared__ double Vs[];  // [kRotRows][c + b]
-    const int W = c + b;
+// Ritz vectors: Xo[i, q] = scale_i sum_t V[i, t] Q[t, q] for q < p (Q: c x p
+// row-major; Xo row-major with leading dimension ldo; scale optional).  A
+// block stages kRotRows rows of V[:, 0:c] in LDS (coalesced), then every
+// thread computes whole outputs (row, q): all threads busy for any p.
+__global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ V, int ldv, int64_t n, int c, int p,
+                                                 const double* __restrict__ Q, double* __restrict__ Xo, int ldo,
+                                                 const double* __restrict__ scale) {
+    extern __shared__ double Vs[];  // [kRotRows][c]
     const int64_t ntiles = (n + kRotRows - 1) / kRotRows;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t r0 = tile * kRotRows;
         const int rows = (int)min<int64_t>(kRotRows, n - r0);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < rows * W; idx += blockDim.x) {
-            int r = idx / W, cc = idx - r * W;
-            Vs[r * W + cc] = V[(r0 + r) * ldv + cc];
+        for (int idx = threadIdx.x; idx < rows * c; idx += blockDim.x) {
+            const int r = idx / c, t = idx - r * c;
+            Vs[idx] = V[(r0 + r) * ldv + t];
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < p; q += blockDim.x) {
-            double acc[kRotRows];
-#pragma unroll
-            for (int r = 0; r < kRotRows; ++r) acc[r] = 0.0;
-            for (int t = 0; t < c; ++t) {
-                const double z = Q[t * p + q];
-#pragma unroll
-                for (int r = 0; r < kRotRows; ++r) acc[r] += Vs[r * W + t] * z;
+        for (int idx = threadIdx.x; idx < rows * p; idx += blockDim.x) {
+            const int r = idx / p, q = idx - r * p;
+            const double* vr = Vs + (size_t)r * c;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int t = 0;
+            for (; t + 3 < c; t += 4) {
+                a0 += vr[t] * Q[t * p + q];
+                a1 += vr[t + 1] * Q[(t + 1) * p + q];
+                a2 += vr[t + 2] * Q[(t + 2) * p + q];
+                a3 += vr[t + 3] * Q[(t + 3) * p + q];
             }
-            for (int r = 0; r < rows; ++r) {
-                if (mode == 0)
-                    V[(r0 + r) * ldv + q] = acc[r];
-                else
-                    Xo[(r0 + r) * ldo + q] = scale ? acc[r] * scale[r0 + r] : acc[r];
-            }
+            for (; t < c; ++t) a0 += vr[t] * Q[t * p + q];
+            const double acc = (a0 + a1) + (a2 + a3);
+            Xo[(r0 + r) * ldo + q] = scale ? acc * scale[r0 + r] : acc;
         }
-        if (mode == 0)
-            for (int idx = threadIdx.x; idx < rows * b; idx += blockDim.x) {
-                int r = idx / b, j = idx - r * b;
-                V[(r0 + r) * ldv + p + j] = Vs[r * W + c + j];
-            }
     }
 }
 
@@ -1021,8 +1015,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
 // Ritz vectors X = V[:, 0:c] Z[:, 0:k] (row-major n x k in Xo, ld k).
 static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* scale) {
     const int c = R.c, k = S.k;
-    k_rotate<<<grid_for(S.n, kRotRows, 1024), 256, (size_t)kRotRows * (c + S.b) * sizeof(double), S.s>>>(
-        S.V, S.ld, S.n, c, k, S.b, S.rb.zk, 1, Xo, k, scale);
+    k_rotate<<<grid_for(S.n, kRotRows, 2048), 256, (size_t)kRotRows * c * sizeof(double), S.s>>>(
+        S.V, S.ld, S.n, c, k, S.rb.zk, Xo, k, scale);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }

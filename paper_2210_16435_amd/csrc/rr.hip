@@ -34,7 +34,8 @@
 //     together after each solve (modified Gram-Schmidt, one wavefront per
 //     cluster), as in LAPACK's inverse iteration; the others twice.
 //  4. back-transformation Z = Q Y, sixteen lanes per column, the reflectors
-//     applied in reverse order from LDS, sixteen staged at a time.
+//     applied in reverse order from LDS (kept there from stage 1 up to order
+//     96, else staged sixteen at a time).
 //
 // The matrix is first scaled by a power of two (max |T_ij| in [1/2, 1)).
 // Every reduction has a fixed order, so results are bitwise reproducible.
@@ -51,7 +52,6 @@ constexpr int kRrT = 1024;
 constexpr int kRrW = kRrT / 64;    // wavefronts
 constexpr int kRrMax = kMaxBasis;  // largest order
 constexpr int kRrLd = kRrMax;      // leading dimension of the per-vector scratch
-constexpr int kMsG = 4;            // lanes per eigenvalue in the multisection
 
 // scratch layout (doubles)
 constexpr size_t kOffHV = 0;                               // Householder vectors [j][kRrMax]
@@ -221,6 +221,11 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     __shared__ int s_ncl, s_multi, s_p, s_m, s_nev, s_pcap;
     __shared__ double s_gl, s_gu;
     __shared__ double red[kRrW];
+    // orders up to 96: the reflectors stay in LDS (the back-transformation
+    // reads them there); larger orders keep them in the global scratch
+    constexpr bool kHvLds = NR <= 6;
+    constexpr int kHvLd = 96;
+    __shared__ double hvs[kHvLds ? kHvLd * kHvLd : 1];
 
     const int c = a.c;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -336,7 +341,7 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
             tau = -g * g * r;
             scale = beta * r;
         }
-        double* hv = HV + (size_t)j * kRrMax;
+        double* hv = kHvLds ? hvs + (size_t)j * kHvLd : HV + (size_t)j * kRrMax;
 #pragma unroll
         for (int t = 0; t < NC; ++t) {
             const int row = lane + 64 * t;
@@ -469,10 +474,13 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     const double atol = 4.0 * DBL_EPSILON * tn;
     const int nev = s_nev;
     {
-        // multisection: four lanes per eigenvalue (lanes of one group in one
-        // quad of a wavefront), until the interval holds lambda_i alone
-        // (counts i at lo and i + 1 at hi) or is narrower than atol
-        const int i = tid / kMsG, u = tid % kMsG, base = lane & ~(kMsG - 1);
+        // multisection: G lanes per eigenvalue (a group inside one
+        // wavefront), until the interval holds lambda_i alone
+        // (counts i at lo and i + 1 at hi) or is narrower than atol.  Wider
+        // groups take fewer steps but keep more wavefronts busy on the FP64
+        // units; four is as fast as eight or sixteen here.
+        const int G = 4;
+        const int i = tid / G, u = tid % G, base = lane & ~(G - 1);
         const bool act = i < nev;
         double lo = s_gl - 2.0 * atol, hi = s_gu + 2.0 * atol;
         int clo = 0, chi = c;
@@ -480,20 +488,20 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
             const bool go = act && (clo != i || chi != i + 1) && hi - lo > atol;
             if (!__syncthreads_or(go)) break;
             if (go) {
-                const double x = lo + (hi - lo) * ((double)(u + 1) / (double)(kMsG + 1));
+                const double x = lo + (hi - lo) * ((double)(u + 1) / (double)(G + 1));
                 const int cnt = sturm_count(de, c, x);
                 // first point of the group whose count exceeds i
                 const uint64_t bal = __ballot(cnt > i);
-                const uint64_t gm = (bal >> base) & ((1ull << kMsG) - 1ull);
-                const int first = gm ? (__ffsll((unsigned long long)gm) - 1) : kMsG;
-                const int sl = base + (first > 0 ? first - 1 : 0), sh = base + (first < kMsG ? first : kMsG - 1);
+                const uint64_t gm = (bal >> base) & ((1ull << G) - 1ull);
+                const int first = gm ? (__ffsll((unsigned long long)gm) - 1) : G;
+                const int sl = base + (first > 0 ? first - 1 : 0), sh = base + (first < G ? first : G - 1);
                 const double xl = __shfl(x, sl, 64), xh = __shfl(x, sh, 64);
                 const int cl = __shfl(cnt, sl, 64), ch = __shfl(cnt, sh, 64);
                 if (first > 0) {
                     lo = xl;
                     clo = cl;
                 }
-                if (first < kMsG) {
+                if (first < G) {
                     hi = xh;
                     chi = ch;
                 }
@@ -610,29 +618,21 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
             const double an = dd[i + 1] - s;
             const double bn = i + 2 < c ? ee[i + 1] : 0.0;
             const size_t o = (size_t)i * kRrLd + tid;
-            if (fabs(ai) >= fabs(ci)) {
-                double piv = ai;
-                if (fabs(piv) < pivmin) piv = piv < 0.0 ? -pivmin : pivmin;
-                const double l = ci / piv;
-                U1[o] = 1.0 / piv;
-                U2[o] = bi;
-                U3[o] = 0.0;
-                Lm[o] = l;
-                PV[o] = 0.0;
-                ai = an - l * bi;
-                bi = bn;
-            } else {
-                double piv = ci;
-                if (fabs(piv) < pivmin) piv = piv < 0.0 ? -pivmin : pivmin;
-                const double l = ai / piv;
-                U1[o] = 1.0 / piv;
-                U2[o] = an;
-                U3[o] = bn;
-                Lm[o] = l;
-                PV[o] = 1.0;
-                ai = bi - l * an;
-                bi = -l * bn;
-            }
+            // partial pivoting: rows i and i+1 swap when |ci| > |ai|
+            // (selects, one reciprocal per row)
+            const bool sw = fabs(ai) < fabs(ci);
+            double piv = sw ? ci : ai;
+            if (fabs(piv) < pivmin) piv = piv < 0.0 ? -pivmin : pivmin;
+            const double rp = 1.0 / piv;
+            const double l = (sw ? ai : ci) * rp;
+            U1[o] = rp;
+            U2[o] = sw ? an : bi;
+            U3[o] = sw ? bn : 0.0;
+            Lm[o] = l;
+            PV[o] = sw ? 1.0 : 0.0;
+            const double na = sw ? bi - l * an : an - l * bi;
+            bi = sw ? -l * bn : bn;
+            ai = na;
             Y[o] = start_entry(tid, i);
         }
         double piv = ai;
@@ -665,29 +665,19 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const size_t o = (size_t)(i + u) * kRrLd + tid;
-                    double nxt = ny[u];
-                    if (pv[u] != 0.0) {
-                        Y[o] = nxt;
-                        nxt = cur - lm[u] * nxt;
-                    } else {
-                        Y[o] = cur;
-                        nxt = nxt - lm[u] * cur;
-                    }
-                    cur = nxt;
+                    const bool sw = pv[u] != 0.0;
+                    const double nxt = ny[u];
+                    Y[o] = sw ? nxt : cur;
+                    cur = sw ? cur - lm[u] * nxt : nxt - lm[u] * cur;
                 }
             }
             for (; i + 1 < c; ++i) {
                 const size_t o = (size_t)i * kRrLd + tid;
-                double nxt = Y[o + kRrLd];
+                const double nxt = Y[o + kRrLd];
                 const double l = Lm[o];
-                if (PV[o] != 0.0) {
-                    Y[o] = nxt;
-                    nxt = cur - l * nxt;
-                } else {
-                    Y[o] = cur;
-                    nxt = nxt - l * cur;
-                }
-                cur = nxt;
+                const bool sw = PV[o] != 0.0;
+                Y[o] = sw ? nxt : cur;
+                cur = sw ? cur - l * nxt : nxt - l * cur;
             }
             Y[(size_t)(c - 1) * kRrLd + tid] = cur;
             // backward substitution with U; the sum of squares of the result
@@ -798,23 +788,29 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
                 y0[t] = (c0 < m && r < c) ? Y[(size_t)r * kRrLd + c0] * sc0 : 0.0;
                 y1[t] = (c1 < m && r < c) ? Y[(size_t)r * kRrLd + c1] * sc1 : 0.0;
             }
-            for (int jc = c - 3; jc >= 0; jc -= kRrW) {
-                const int nj = min(kRrW, jc + 1);
-                __syncthreads();
-                for (int idx = tid; idx < nj * c; idx += kRrT) {
-                    const int jj = idx / c, r = idx - jj * c;
-                    part[jj][r] = HV[(size_t)(jc - jj) * kRrMax + r];
+            // reflectors from LDS: all of them (orders up to 96) or sixteen
+            // at a time staged from the global scratch
+            const int chunk = kHvLds ? c : kRrW;
+            for (int jc = c - 3; jc >= 0; jc -= chunk) {
+                const int nj = min(chunk, jc + 1);
+                if (!kHvLds) {
+                    __syncthreads();
+                    for (int idx = tid; idx < nj * c; idx += kRrT) {
+                        const int jj = idx / c, r = idx - jj * c;
+                        part[jj][r] = HV[(size_t)(jc - jj) * kRrMax + r];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
                 if (!any0) continue;
                 for (int jj = 0; jj < nj; ++jj) {
                     const double tau = tau_s[jc - jj];
                     if (tau == 0.0) continue;
+                    const double* hr = kHvLds ? hvs + (size_t)(jc - jj) * kHvLd : &part[jj][0];
                     double v[NT];
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
                         const int r = sl + 16 * t;
-                        v[t] = r < c ? part[jj][r] : 0.0;
+                        v[t] = r < c ? hr[r] : 0.0;
                     }
                     double s0 = 0.0;
 #pragma unroll
