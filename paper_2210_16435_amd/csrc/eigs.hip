@@ -682,6 +682,10 @@ struct Solver {
         a.grp = g->grp;
         a.cs = g->cs;
         a.rtab = o.rtab;
+        a.lc = o.lc;
+        a.lcw = o.lcw;
+        a.m = o.m;
+        a.utab = o.utab;
         a.T = T;
         a.ldt = ld;
         a.thresh = thresh;

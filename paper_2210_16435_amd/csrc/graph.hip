@@ -234,6 +234,9 @@ static void free_graph(sfairsc_graph* g) {
     o.t.release();
     o.xpad.release();
     o.ypad.release();
+    o.part_x.release();
+    o.lc.release();
+    o.ctlc.release();
     if (o.ev0) (void)hipEventDestroy(o.ev0);
     if (o.ev1) (void)hipEventDestroy(o.ev1);
     auto& w = g->eig;
@@ -440,6 +443,7 @@ static int create_impl(sfairsc_graph* g, int64_t n, int64_t nnz, const int32_t* 
     for (int t = 0; t < h; ++t) gp[t] = g->p[t];
     for (int t = 0; t < m * m; ++t) gp[h + t] = g->ginv[t];
     SF_HIP(hipMemcpyAsync(g->gpar, gp.data(), gp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    SF_TRY(op_prepare_lc(g, s));
     SF_HIP(hipStreamSynchronize(s));
     return SFAIRSC_OK;
 }

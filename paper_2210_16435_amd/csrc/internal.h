@@ -61,6 +61,10 @@ struct OpWork {
     DevBuf xp;          // projected input, n x BW (float or double)
     DevBuf t;           // sparse product output, n x BW (float or double)
     DevBuf xpad, ypad;  // padding copies for b not in {4, 8, 16, 32}
+    DevBuf part_x;      // [nblk_spmm][h][b] double: the SpMM's sums of c_i X_i
+    DevBuf lc;          // L C (n x lcw, row-major, double): the constraint's image
+    DevBuf ctlc;        // C^T L C ([h-1][32], double)
+    int lcw = 0;        // row stride of lc; 0 until formed
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -222,15 +226,22 @@ int small_eig_host(sfairsc_graph* g, const double* dT, int c, int ldt, double* w
 // host buffer, events).  Called when the last graph handle is destroyed.
 void batched_release_workspaces();
 
-// The operator up to (not including) the output deflation: projection, SpMM
-// with its C^T T epilogue and the deflation table.  Y = T - C R_out (row i:
-// T_i - c_i rtab[g_i]) is left to the caller (fused into its next pass).
+// The operator up to (not including) the output deflation: SpMM with its
+// C^T epilogue sums and the deflation tables.  The caller forms
+// Y_i = T_i - c_i rtab[g_i] - sum_{s < m} lc[i][s] utab[s] (fused into its
+// next pass); with lc == nullptr the last term is absent.
 struct OpOut {
     const void* t;       // n x BW compact, float if is_float else double
     bool is_float;
     int BW;
     const double* rtab;  // [h][32]; nullptr: t already holds Y (general constraint)
+    const double* lc = nullptr;    // L C, n x lcw (double); nullptr: T = L P X already
+    int lcw = 0, m = 0;            // its row stride and columns (h - 1)
+    const double* utab = nullptr;  // U_in = G^{-1} C^T X, [m][32]
 };
+// L C and C^T L C for the operator's reassociated form (group constraint,
+// h >= 2); a no-op otherwise or when already formed.
+int op_prepare_lc(sfairsc_graph* g, hipStream_t s);
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out);
 

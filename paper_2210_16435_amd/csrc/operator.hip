@@ -10,6 +10,14 @@
 //   q           = sum_{s<h-1} p_s U_s,
 // with c_i = d_i^{-1/2} (normalized) or 1, p_s = |V_s| / n.
 //
+// The solver applies the same operator reassociated (op_apply_t):
+//   T = L_n P X = T0 - (L_n C) U_in,  T0 = L_n X,  U_in = G^{-1} C^T X,
+//   C^T T = C^T T0 - (C^T L_n C) U_in,
+// with L_n C and C^T L_n C formed once per graph.  The sparse product then
+// reads the block itself, its epilogue sums both C^T X and C^T T0, and one
+// single-workgroup kernel turns them into the tables of both corrections:
+// three launches instead of five, and no pass between the two reductions.
+//
 // Every reduction has a fixed order (per-block partials combined in block
 // order), so results are bitwise reproducible run to run.
 #include <cmath>
@@ -226,7 +234,104 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     }
 }
 
-// X'_i = X_i - c_i R_{g_i}, written compact (stride BW) in type OT.
+// Both tables of the reassociated operator from the sparse product's two
+// epilogue sums (per block: sums of c_i X_i in partx, of c_i T0_i in partt,
+// T0 = L_n X; output-major, sum s of column j at (s b + j) nblk):
+//   S = C^T X,  U_in = G^{-1} S                         -> Utab [h-1][32]
+//   C^T T = C^T T0 - (C^T L_n C) U_in                   (ctlc [h-1][32])
+//   U_out = G^{-1} (C^T T - sigma S), R table of U_out  -> Rtab [h][32]
+// (C^T Z as in the file header).  Nothing here mixes the block's columns:
+// one workgroup per column j (32 of them, those past b write zeros), one
+// wavefront per sum with its lanes over the blocks.
+constexpr int kFin2Threads = 256;
+__global__ __launch_bounds__(kFin2Threads) void k_group_finalize2(const double* __restrict__ partx,
+                                                                   const double* __restrict__ partt, int nblk, int h,
+                                                                   int b, const double* __restrict__ gpar,
+                                                                   const double* __restrict__ ctlc, double sigma,
+                                                                   double* __restrict__ Rtab,
+                                                                   double* __restrict__ Utab, const int* skip) {
+    if (skip && *skip) return;
+    __shared__ double A[2][kMaxGroups];
+    __shared__ double gp[kMaxGroups + kMaxGroups * kMaxGroups];
+    __shared__ double cl[kMaxGroups * kMaxGroups];
+    __shared__ double Z[kMaxGroups], U[kMaxGroups], W[kMaxGroups];
+    const int j = blockIdx.x, m = h - 1;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (j >= b) {
+        for (int s = t; s < h; s += kFin2Threads) Rtab[s * 32 + j] = 0.0;
+        for (int s = t; s < m; s += kFin2Threads) Utab[s * 32 + j] = 0.0;
+        return;
+    }
+    for (int e = t; e < h + m * m; e += kFin2Threads) gp[e] = gpar[e];
+    for (int e = t; e < m * m; e += kFin2Threads) cl[e] = ctlc[(e / m) * 32 + e % m];
+    for (int r = w; r < 2 * h; r += kFin2Threads / 64) {
+        const double* src = r < h ? partx + ((size_t)r * b + j) * nblk : partt + ((size_t)(r - h) * b + j) * nblk;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int blk = lane;
+        for (; blk + 192 < nblk; blk += 256) {
+            s0 += src[blk];
+            s1 += src[blk + 64];
+            s2 += src[blk + 128];
+            s3 += src[blk + 192];
+        }
+        for (; blk < nblk; blk += 64) s0 += src[blk];
+        double v = (s0 + s1) + (s2 + s3);
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) A[r < h ? 0 : 1][r < h ? r : r - h] = v;
+    }
+    __syncthreads();
+    const double* p = gp;
+    const double* Ginv = gp + h;
+    double tx = 0.0, tt = 0.0;
+    for (int s = 0; s < h; ++s) {
+        tx += A[0][s];
+        tt += A[1][s];
+    }
+    if (t < m) Z[t] = A[0][t] - p[t] * tx;  // S
+    __syncthreads();
+    if (t < m) {
+        double u = 0.0;
+        for (int r = 0; r < m; ++r) u += Ginv[t * m + r] * Z[r];
+        U[t] = u;
+        Utab[t * 32 + j] = u;
+    }
+    __syncthreads();
+    if (t < m) {  // C^T T - sigma S
+        double z = A[1][t] - p[t] * tt;
+        for (int r = 0; r < m; ++r) z -= cl[t * m + r] * U[r];
+        W[t] = z - sigma * Z[t];
+    }
+    __syncthreads();
+    if (t < m) {  // U_out
+        double u = 0.0;
+        for (int r = 0; r < m; ++r) u += Ginv[t * m + r] * W[r];
+        Z[t] = u;
+    }
+    __syncthreads();
+    if (t < h) {
+        double q = 0.0;
+        for (int s = 0; s < m; ++s) q += p[s] * Z[s];
+        Rtab[t * 32 + j] = (t < m ? Z[t] : 0.0) - q;
+    }
+}
+
+// C compact (n x lcw, double): C[i][s] = c_i (1[g_i = s] - p_s) for s < h-1,
+// zero in the padding columns.
+__global__ __launch_bounds__(256) void k_build_c(int64_t n, int m, int lcw, const int32_t* __restrict__ grp,
+                                                  const double* __restrict__ cs, const double* __restrict__ gpar,
+                                                  double* __restrict__ Cm) {
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n * lcw;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / lcw;
+        const int s = (int)(idx - i * lcw);
+        double v = 0.0;
+        if (s < m) v = (cs ? cs[i] : 1.0) * ((grp[i] == s ? 1.0 : 0.0) - gpar[s]);
+        Cm[idx] = v;
+    }
+}
+
+// X'_i = X_i - c_i R_{g_i}, written compact (stride BW) in type OT; without
+// a table (Rtab == nullptr) X itself.
 template <class OT>
 __global__ __launch_bounds__(256) void k_proj_apply(const double* __restrict__ X, int ldx, int b, int BW, int64_t n,
                                                      const int32_t* __restrict__ grp, const double* __restrict__ cs,
@@ -240,16 +345,18 @@ __global__ __launch_bounds__(256) void k_proj_apply(const double* __restrict__ X
         int j = (int)(idx - i * BW);
         double v = 0.0;
         if (j < b) {
-            double c = cs ? cs[i] : 1.0;
-            v = X[i * ldx + j] - c * Rtab[grp[i] * 32 + j];
+            v = X[i * ldx + j];
+            if (Rtab) v -= (cs ? cs[i] : 1.0) * Rtab[grp[i] * 32 + j];
         }
         Xp[idx] = (OT)v;
     }
 }
 
 // T = diag * X' - W X' (CSR), epilogue: per-group sums of c_i T_i into
-// part[block][h][b].  X', T compact n x BW in type VT; the products
-// accumulate in VT (float in mixed precision).
+// part[block][h][b]; with partx also those of c_i X'_i, and then both
+// output-major ([h][b][block]) for the column-parallel finalisation.  X', T
+// compact n x BW in type VT; the products accumulate in VT (float in mixed
+// precision).
 //
 // A wavefront takes RPW rows at once, G = 64 / RPW lanes each.  A row's
 // nonzeros go in chunks of G: one coalesced load of their columns and
@@ -266,7 +373,8 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
                                                         const VT* __restrict__ X, VT* __restrict__ T, int64_t n,
                                                         const int32_t* __restrict__ grp,
                                                         const double* __restrict__ cs, int h, int b,
-                                                        double* __restrict__ part, const int* skip) {
+                                                        double* __restrict__ part, double* __restrict__ partx,
+                                                        const int* skip) {
     if (skip && *skip) return;
     using V = Vec16<VT>;
     constexpr int VEC = V::N;
@@ -275,18 +383,20 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
     constexpr int NS = G / LPR;     // nonzeros per gather instruction
     constexpr int IT = G / NS;      // gathers per lane per chunk (= LPR)
     static_assert(NS >= 1, "row group narrower than a row vector");
-    extern __shared__ double gacc[];  // [kSpmmWaves][h][BW]
+    extern __shared__ double gacc[];  // [kSpmmWaves][h][BW] (T), then the same for X'
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int sub = lane / G, sl = lane - sub * G;
     const int slot = sl / LPR;
     const int cl = sl - slot * LPR;
     const bool epi = part != nullptr;
+    const bool epx = epi && partx != nullptr;
     if (epi) {
-        for (int o = threadIdx.x; o < kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
+        for (int o = threadIdx.x; o < (epx ? 2 : 1) * kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
         __syncthreads();
     }
     double* wacc = gacc + wave * h * BW;
+    double* xacc = gacc + (kSpmmWaves + wave) * h * BW;
     const int64_t rstride = (int64_t)gridDim.x * kSpmmWaves * RPW;
     for (int64_t row0 = ((int64_t)blockIdx.x * kSpmmWaves + wave) * RPW; row0 < n; row0 += rstride) {
         const int64_t row = row0 + sub;
@@ -326,9 +436,9 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
         for (int off = LPR; off < G; off <<= 1)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off);
-        V t;
+        V t, xi;
         if (rv && slot == 0) {
-            V xi = V::load(X + row * BW + cl * VEC);
+            xi = V::load(X + row * BW + cl * VEC);
             const VT dg = diag[row];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) t.v[v] = dg * xi.v[v] - acc[v];
@@ -344,6 +454,11 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
                     double* dst = wacc + gi * BW + cl * VEC;
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) dst[v] += c * (double)t.v[v];
+                    if (epx) {
+                        double* dx = xacc + gi * BW + cl * VEC;
+#pragma unroll
+                        for (int v = 0; v < VEC; ++v) dx[v] += c * (double)xi.v[v];
+                    }
                 }
             }
         }
@@ -354,7 +469,14 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
             const int s = o / b, jj = o - s * b;
             double tot = 0.0;
             for (int w = 0; w < kSpmmWaves; ++w) tot += gacc[w * h * BW + s * BW + jj];
-            part[(size_t)blockIdx.x * h * b + o] = tot;
+            if (epx) {
+                double tx = 0.0;
+                for (int w = 0; w < kSpmmWaves; ++w) tx += gacc[(kSpmmWaves + w) * h * BW + s * BW + jj];
+                part[(size_t)o * gridDim.x + blockIdx.x] = tot;
+                partx[(size_t)o * gridDim.x + blockIdx.x] = tx;
+            } else {
+                part[(size_t)blockIdx.x * h * b + o] = tot;
+            }
         }
     }
 }
@@ -401,14 +523,14 @@ static int ensure_op(sfairsc_graph* g) {
 
 template <class VT>
 static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* val, const VT* diag, int b,
-                        double* part, int nblk, hipStream_t s, const int* skip) {
-    size_t lds = part ? (size_t)kSpmmWaves * g->h * BW * sizeof(double) : 0;
+                        double* part, int nblk, hipStream_t s, const int* skip, double* partx = nullptr) {
+    size_t lds = part ? (size_t)(partx ? 2 : 1) * kSpmmWaves * g->h * BW * sizeof(double) : 0;
     // rows per wavefront: short rows share a wavefront (at most 4)
     const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
     const int rpw = avg <= 24.0 ? 4 : (avg <= 96.0 ? 2 : 1);
 #define SF_SPMM_CASE(W, R)                                                                                     \
     k_spmm<VT, W, R><<<nblk, kSpmmThreads, lds, s>>>(g->rowptr, g->col, val, diag, X, T, g->n, g->grp, g->cs, \
-                                                     g->h, b, part, skip)
+                                                     g->h, b, part, partx, skip)
 #define SF_SPMM_RPW(W)                 \
     case W:                            \
         if (rpw == 4)                  \
@@ -519,6 +641,76 @@ static int op_deflate(sfairsc_graph* g, const OpOut& o, int b, double* Y, int ld
     return SFAIRSC_OK;
 }
 
+// The operator fits the reassociated form: both epilogue sums in the SpMM's
+// LDS (as the single-sum form's LDS at twice the groups).
+static bool fused_fits(const sfairsc_graph* g, int BW) {
+    return g->h >= 2 && g->op.lcw > 0 && 2 * g->h * BW <= 1024;
+}
+
+int op_prepare_lc(sfairsc_graph* g, hipStream_t s) {
+    const int h = g->h, m = h - 1;
+    if (m < 1 || g->qbas || g->memb || g->op.lcw > 0) return SFAIRSC_OK;
+    SF_TRY(ensure_op(g));
+    OpWork& w = g->op;
+    const int64_t n = g->n;
+    const int lcw = pad_width(m);
+    SF_TRY(w.lc.ensure((size_t)n * lcw * sizeof(double)));
+    SF_TRY(w.ctlc.ensure((size_t)kMaxGroups * 32 * sizeof(double)));
+    // C in the operator's input buffer, then L_n C by the FP64 sparse product
+    double* Cm = w.xp.as<double>();
+    k_build_c<<<grid_rows(n * lcw, 256, 8192), 256, 0, s>>>(n, m, lcw, g->grp, g->cs, g->gpar, Cm);
+    launch_spmm<double>(g, lcw, Cm, w.lc.as<double>(), g->val64, g->diag64, m, nullptr, w.nblk_spmm, s, nullptr);
+    // C^T (L_n C): the group sums of its columns combined as C^T Z (S_out);
+    // the R table it also writes goes to a spare slot
+    launch_proj_partial(w.lc.as<double>(), lcw, m, n, g->grp, g->cs, h, w.part_in.as<double>(), w.nblk_proj,
+                        nullptr, s);
+    double* spare = w.small.as<double>() + 4 * kMaxGroups * 32;
+    k_group_finalize<<<1, kFinThreads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, h, m, g->gpar, nullptr, 0.0,
+                                               w.ctlc.as<double>(), spare, nullptr);
+    SF_HIP(hipGetLastError());
+    w.lcw = lcw;
+    return SFAIRSC_OK;
+}
+
+// The reassociated operator: X compacted (no projection), T0 = L_n X with
+// both epilogue sums, then the two tables (R_out for C, U_in for L_n C).
+static int op_apply_fused(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma,
+                          hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
+    OpWork& w = g->op;
+    const int BW = pad_width(b);
+    const int64_t n = g->n;
+    const int h = g->h;
+    SF_TRY(w.part_x.ensure((size_t)w.nblk_spmm * h * 32 * sizeof(double)));
+    double* Rout = w.small.as<double>() + 2 * kMaxGroups * 32;
+    double* Uin = w.small.as<double>() + 3 * kMaxGroups * 32;
+    const int ga = grid_rows(n * BW, 256, 8192);
+    if (mixed) {
+        k_proj_apply<float><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, nullptr, w.xp.as<float>(), skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<float>(g, BW, w.xp.as<float>(), w.t.as<float>(), g->val32, g->diag32, b,
+                           w.part_out.as<double>(), w.nblk_spmm, s, skip, w.part_x.as<double>());
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+    } else {
+        k_proj_apply<double><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, nullptr, w.xp.as<double>(), skip);
+        if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
+        launch_spmm<double>(g, BW, w.xp.as<double>(), w.t.as<double>(), g->val64, g->diag64, b,
+                            w.part_out.as<double>(), w.nblk_spmm, s, skip, w.part_x.as<double>());
+        if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
+    }
+    k_group_finalize2<<<32, kFin2Threads, 0, s>>>(w.part_x.as<double>(), w.part_out.as<double>(), w.nblk_spmm, h,
+                                                  b, g->gpar, w.ctlc.as<double>(), sigma, Rout, Uin, skip);
+    SF_HIP(hipGetLastError());
+    out->t = w.t.p;
+    out->is_float = mixed != 0;
+    out->BW = BW;
+    out->rtab = Rout;
+    out->lc = w.lc.as<double>();
+    out->lcw = w.lcw;
+    out->m = h - 1;
+    out->utab = Uin;
+    return SFAIRSC_OK;
+}
+
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
                hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
@@ -533,21 +725,24 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
         out->rtab = nullptr;
         return SFAIRSC_OK;
     }
+    if (fused_fits(g, pad_width(b))) return op_apply_fused(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, out);
     OpWork& w = g->op;
     const OpBufs B{w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(), w.nblk_spmm, w.small.as<double>(),
                    w.xp.p, w.t.p};
     return op_apply_core(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, B, out);
 }
 
+// The public operator keeps the paper's order: X' = P X first.
 int op_apply(sfairsc_graph* g, const double* X, int ldx, double* Y, int ldy, int b, int mixed, double sigma,
              hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip) {
-    if (g->qbas || g->memb) {
-        if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
-        SF_TRY(ensure_op(g));
-        return gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, Y, ldy);
-    }
+    if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
+    SF_TRY(ensure_op(g));
+    if (g->qbas || g->memb) return gen_apply(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, Y, ldy);
+    OpWork& w = g->op;
+    const OpBufs B{w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(), w.nblk_spmm, w.small.as<double>(),
+                   w.xp.p, w.t.p};
     OpOut o;
-    SF_TRY(op_apply_t(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, &o));
+    SF_TRY(op_apply_core(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, B, &o));
     return op_deflate(g, o, b, Y, ldy, s, skip);
 }
 

@@ -19,6 +19,9 @@ struct OrthoArgs {
     const int32_t* grp;
     const double* cs;   // d^{-1/2} or nullptr
     const double* rtab; // deflation table [h][32]; nullptr: t already holds Y
+    const double* lc = nullptr;    // L C (n x lcw): Y_i also loses LC_i utab
+    int lcw = 0, m = 0;            // its row stride (>= 4) and columns
+    const double* utab = nullptr;  // [m][32]
     double* T;          // projected matrix (device, ldt x ldt)
     int ldt;
     double thresh;      // Cholesky pivot threshold (rank deficiency)

@@ -122,6 +122,36 @@ def test_small_random_graphs(case):
     check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, G.sigma, lam_ref, H_ref, 1e-8, 1e-6, gap)
 
 
+# The solver's operator is the reassociated form T = L X - (L C) U_in (one
+# L C term in the first orthogonalisation pass).  These cases drive each of its
+# kernel variants: up to four constraint columns from quad broadcasts, more
+# (h > 5) with the extended tail, block widths 4 and 16 (one column tile) and
+# 32 (two tiles), FP64 and mixed, both Laplacians.
+REASSOC = [
+    (900, 10, 21, 7, True, 4, 8, "fp64"),
+    (900, 10, 22, 6, False, 5, 16, "fp64"),
+    (1400, 12, 23, 9, True, 3, 4, "mixed"),
+    (1400, 12, 24, 5, False, 6, 32, "fp64"),
+    (1100, 8, 25, 3, True, 4, 16, "mixed"),
+    (1600, 10, 26, 5, True, 5, 4, "fp64"),
+]
+
+
+@pytest.mark.parametrize("case", REASSOC, ids=[f"h{c[3]}-b{c[6]}-{c[7]}-{'norm' if c[4] else 'unnorm'}" for c in REASSOC])
+def test_reassociated_operator_paths(case):
+    sf = lib()
+    n, deg, seed, h, normalized, k, b, prec = case
+    g = random_sparse_graph(n, deg, seed=seed, h=h, weights=("uniform", 0.5, 1.5))
+    log(f"reassociated operator {case}")
+    lam_ref, H_ref = oracle.fair_eigs_dense(g.to_scipy(), g.groups, h, k + 1, normalized)
+    G = sf.Graph.from_msbm(g, normalized)
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    r = G.eigs(k, tol=tol, precision=prec, block_width=b)
+    gap = (lam_ref[k] - lam_ref[k - 1]) / G.sigma
+    rtol, ang = (1e-8, 1e-6) if prec == "fp64" else (1e-5, 1e-4)
+    check_solution(g, r.eigenvalues, to_np(r.H), k, normalized, tol, G.sigma, lam_ref, H_ref, rtol, ang, gap)
+
+
 @pytest.mark.parametrize("normalized", [False, True])
 def test_plain_sc_h1_on_the_same_kernels(normalized):
     # plain spectral clustering = the fair problem with one group (F has no
