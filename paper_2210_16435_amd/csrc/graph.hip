@@ -234,7 +234,6 @@ static void free_graph(sfairsc_graph* g) {
     o.t.release();
     o.xpad.release();
     o.ypad.release();
-    o.part_x.release();
     o.lc.release();
     o.ctlc.release();
     if (o.ev0) (void)hipEventDestroy(o.ev0);

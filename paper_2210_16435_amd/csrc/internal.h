@@ -61,7 +61,6 @@ struct OpWork {
     DevBuf xp;          // projected input, n x BW (float or double)
     DevBuf t;           // sparse product output, n x BW (float or double)
     DevBuf xpad, ypad;  // padding copies for b not in {4, 8, 16, 32}
-    DevBuf part_x;      // [nblk_spmm][h][b] double: the SpMM's sums of c_i X_i
     DevBuf lc;          // L C (n x lcw, row-major, double): the constraint's image
     DevBuf ctlc;        // C^T L C ([h-1][32], double)
     int lcw = 0;        // row stride of lc; 0 until formed

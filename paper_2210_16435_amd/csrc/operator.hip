@@ -13,9 +13,9 @@
 // The solver applies the same operator reassociated (op_apply_t):
 //   T = L_n P X = T0 - (L_n C) U_in,  T0 = L_n X,  U_in = G^{-1} C^T X,
 //   C^T T = C^T T0 - (C^T L_n C) U_in,
-// with L_n C and C^T L_n C formed once per graph.  The sparse product then
-// reads the block itself, its epilogue sums both C^T X and C^T T0, and one
-// single-workgroup kernel turns them into the tables of both corrections:
+// with L_n C and C^T L_n C formed once per graph.  The block's compaction
+// then also sums C^T X, the sparse product reads the block itself and sums
+// C^T T0, and one kernel turns both into the tables of both corrections:
 // three launches instead of five, and no pass between the two reductions.
 //
 // Every reduction has a fixed order (per-block partials combined in block
@@ -152,6 +152,86 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_partial_p2(const double* 
     }
 }
 
+// Output-major partial sums by XCD: consecutive workgroups run on different
+// XCDs (round robin over 8), so block blk's slot is (blk mod 8) per + blk / 8
+// with per = ceil(nblk / 8): each XCD's blocks fill whole lines of a row
+// (its L2 writes them back whole) and a row of 8 per slots is read
+// contiguously.  Slots past nblk are never written and never read.
+__host__ __device__ inline int xcd_row(int nblk) { return 8 * ((nblk + 7) >> 3); }
+__host__ __device__ inline int xcd_slot(int blk, int nblk) { return (blk & 7) * ((nblk + 7) >> 3) + (blk >> 3); }
+__device__ inline bool xcd_valid(int slot, int nblk) {
+    const int per = (nblk + 7) >> 3;
+    const int x = slot / per;
+    return (slot - x * per) * 8 + x < nblk;
+}
+
+// X compacted (row stride b) in type OT and the per-block sums of c_i X~_i
+// per group, X~ the compacted value (so that they are the sums of what the
+// sparse product reads), output-major by XCD slot.  Power-of-two b (4..32),
+// laid out as k_proj_partial_p2.
+template <class OT>
+__global__ __launch_bounds__(kProjThreads) void k_compact_sums(const double* __restrict__ X, int ldx, int b,
+                                                               int64_t n, const int32_t* __restrict__ grp,
+                                                               const double* __restrict__ cs, int h,
+                                                               OT* __restrict__ Xp, double* __restrict__ part,
+                                                               const int* skip) {
+    if (skip && *skip) return;
+    constexpr int NWV = kProjThreads / 64;
+    __shared__ double wsum[NWV][kMaxGroups * 32];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lb = 31 - __clz(b);
+    const int col = lane & (b - 1), rl = lane >> lb, rpw = 64 >> lb;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
+    const int64_t step = (int64_t)NWV * rpw;
+    for (int g0 = 0; g0 < h; g0 += 8) {
+        const bool wr = g0 == 0;  // the compacted block is written on the first pass
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        int64_t i = r0 + (int64_t)wave * rpw + rl;
+        for (; i + 3 * step < r1; i += 4 * step) {
+            int gi[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t r = i + u * step;
+                gi[u] = grp[r] - g0;
+                const OT xv = (OT)X[r * ldx + col];
+                if (wr) Xp[r * b + col] = xv;
+                v[u] = (cs ? cs[r] : 1.0) * (double)xv;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc[q] += (gi[u] == q) ? v[u] : 0.0;
+        }
+        for (; i < r1; i += step) {
+            const int gi = grp[i] - g0;
+            const OT xv = (OT)X[i * ldx + col];
+            if (wr) Xp[i * b + col] = xv;
+            const double v = (cs ? cs[i] : 1.0) * (double)xv;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += (gi == q) ? v : 0.0;
+        }
+        for (int off = b; off < 64; off <<= 1)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += __shfl_xor(acc[q], off);
+        if (rl == 0)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (g0 + q < h) wsum[wave][(g0 + q) * b + col] = acc[q];
+    }
+    __syncthreads();
+    const int rowlen = xcd_row(gridDim.x), sl = xcd_slot(blockIdx.x, gridDim.x);
+    for (int o = threadIdx.x; o < h * b; o += kProjThreads) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) sum += wsum[w][o];
+        part[(size_t)o * rowlen + sl] = sum;
+    }
+}
+
 static void launch_proj_partial(const double* X, int ldx, int b, int64_t n, const int32_t* grp, const double* cs,
                                 int h, double* part, int nblk, const int* skip, hipStream_t s) {
     if (b >= 4 && b <= 32 && (b & (b - 1)) == 0)
@@ -234,9 +314,10 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
     }
 }
 
-// Both tables of the reassociated operator from the sparse product's two
-// epilogue sums (per block: sums of c_i X_i in partx, of c_i T0_i in partt,
-// T0 = L_n X; output-major, sum s of column j at (s b + j) nblk):
+// Both tables of the reassociated operator from the per-block sums of c_i X_i
+// (partx, nbx blocks: the compaction) and of c_i T0_i (partt, nbt blocks: the
+// sparse product's epilogue), T0 = L_n X, both output-major by XCD slot (sum
+// s of column j in row s b + j):
 //   S = C^T X,  U_in = G^{-1} S                         -> Utab [h-1][32]
 //   C^T T = C^T T0 - (C^T L_n C) U_in                   (ctlc [h-1][32])
 //   U_out = G^{-1} (C^T T - sigma S), R table of U_out  -> Rtab [h][32]
@@ -244,8 +325,8 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
 // one workgroup per column j (32 of them, those past b write zeros), one
 // wavefront per sum with its lanes over the blocks.
 constexpr int kFin2Threads = 256;
-__global__ __launch_bounds__(kFin2Threads) void k_group_finalize2(const double* __restrict__ partx,
-                                                                   const double* __restrict__ partt, int nblk, int h,
+__global__ __launch_bounds__(kFin2Threads) void k_group_finalize2(const double* __restrict__ partx, int nbx,
+                                                                   const double* __restrict__ partt, int nbt, int h,
                                                                    int b, const double* __restrict__ gpar,
                                                                    const double* __restrict__ ctlc, double sigma,
                                                                    double* __restrict__ Rtab,
@@ -265,17 +346,22 @@ __global__ __launch_bounds__(kFin2Threads) void k_group_finalize2(const double* 
     for (int e = t; e < h + m * m; e += kFin2Threads) gp[e] = gpar[e];
     for (int e = t; e < m * m; e += kFin2Threads) cl[e] = ctlc[(e / m) * 32 + e % m];
     for (int r = w; r < 2 * h; r += kFin2Threads / 64) {
-        const double* src = r < h ? partx + ((size_t)r * b + j) * nblk : partt + ((size_t)(r - h) * b + j) * nblk;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int blk = lane;
-        for (; blk + 192 < nblk; blk += 256) {
-            s0 += src[blk];
-            s1 += src[blk + 64];
-            s2 += src[blk + 128];
-            s3 += src[blk + 192];
+        const int nb = r < h ? nbx : nbt, rowlen = xcd_row(nb);
+        const double* src = r < h ? partx + ((size_t)r * b + j) * rowlen : partt + ((size_t)(r - h) * b + j) * rowlen;
+        // eight loads per lane in flight at once
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int sl = lane;
+        if (rowlen == nb) {  // every slot written
+            for (; sl + 7 * 64 < rowlen; sl += 8 * 64)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += src[sl + u * 64];
         }
-        for (; blk < nblk; blk += 64) s0 += src[blk];
-        double v = (s0 + s1) + (s2 + s3);
+#pragma unroll 4
+        for (; sl < rowlen; sl += 64) {
+            const double v = src[sl];
+            if (xcd_valid(sl, nb)) a[0] += v;
+        }
+        double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
         if (lane == 0) A[r < h ? 0 : 1][r < h ? r : r - h] = v;
     }
@@ -353,10 +439,9 @@ __global__ __launch_bounds__(256) void k_proj_apply(const double* __restrict__ X
 }
 
 // T = diag * X' - W X' (CSR), epilogue: per-group sums of c_i T_i into
-// part[block][h][b]; with partx also those of c_i X'_i, and then both
-// output-major ([h][b][block]) for the column-parallel finalisation.  X', T
-// compact n x BW in type VT; the products accumulate in VT (float in mixed
-// precision).
+// part[block][h][b], or (om) output-major by XCD slot (xcd_slot) for the
+// column-parallel finalisation.  X', T compact n x BW in type VT; the
+// products accumulate in VT (float in mixed precision).
 //
 // A wavefront takes RPW rows at once, G = 64 / RPW lanes each.  A row's
 // nonzeros go in chunks of G: one coalesced load of their columns and
@@ -373,8 +458,7 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
                                                         const VT* __restrict__ X, VT* __restrict__ T, int64_t n,
                                                         const int32_t* __restrict__ grp,
                                                         const double* __restrict__ cs, int h, int b,
-                                                        double* __restrict__ part, double* __restrict__ partx,
-                                                        const int* skip) {
+                                                        double* __restrict__ part, int om, const int* skip) {
     if (skip && *skip) return;
     using V = Vec16<VT>;
     constexpr int VEC = V::N;
@@ -383,20 +467,18 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
     constexpr int NS = G / LPR;     // nonzeros per gather instruction
     constexpr int IT = G / NS;      // gathers per lane per chunk (= LPR)
     static_assert(NS >= 1, "row group narrower than a row vector");
-    extern __shared__ double gacc[];  // [kSpmmWaves][h][BW] (T), then the same for X'
+    extern __shared__ double gacc[];  // [kSpmmWaves][h][BW]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int sub = lane / G, sl = lane - sub * G;
     const int slot = sl / LPR;
     const int cl = sl - slot * LPR;
     const bool epi = part != nullptr;
-    const bool epx = epi && partx != nullptr;
     if (epi) {
-        for (int o = threadIdx.x; o < (epx ? 2 : 1) * kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
+        for (int o = threadIdx.x; o < kSpmmWaves * h * BW; o += kSpmmThreads) gacc[o] = 0.0;
         __syncthreads();
     }
     double* wacc = gacc + wave * h * BW;
-    double* xacc = gacc + (kSpmmWaves + wave) * h * BW;
     const int64_t rstride = (int64_t)gridDim.x * kSpmmWaves * RPW;
     for (int64_t row0 = ((int64_t)blockIdx.x * kSpmmWaves + wave) * RPW; row0 < n; row0 += rstride) {
         const int64_t row = row0 + sub;
@@ -436,9 +518,9 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
         for (int off = LPR; off < G; off <<= 1)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off);
-        V t, xi;
+        V t;
         if (rv && slot == 0) {
-            xi = V::load(X + row * BW + cl * VEC);
+            V xi = V::load(X + row * BW + cl * VEC);
             const VT dg = diag[row];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) t.v[v] = dg * xi.v[v] - acc[v];
@@ -454,11 +536,6 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
                     double* dst = wacc + gi * BW + cl * VEC;
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) dst[v] += c * (double)t.v[v];
-                    if (epx) {
-                        double* dx = xacc + gi * BW + cl * VEC;
-#pragma unroll
-                        for (int v = 0; v < VEC; ++v) dx[v] += c * (double)xi.v[v];
-                    }
                 }
             }
         }
@@ -469,14 +546,10 @@ __global__ __launch_bounds__(kSpmmThreads) void k_spmm(const int32_t* __restrict
             const int s = o / b, jj = o - s * b;
             double tot = 0.0;
             for (int w = 0; w < kSpmmWaves; ++w) tot += gacc[w * h * BW + s * BW + jj];
-            if (epx) {
-                double tx = 0.0;
-                for (int w = 0; w < kSpmmWaves; ++w) tx += gacc[(kSpmmWaves + w) * h * BW + s * BW + jj];
-                part[(size_t)o * gridDim.x + blockIdx.x] = tot;
-                partx[(size_t)o * gridDim.x + blockIdx.x] = tx;
-            } else {
+            if (om)
+                part[(size_t)o * xcd_row(gridDim.x) + xcd_slot(blockIdx.x, gridDim.x)] = tot;
+            else
                 part[(size_t)blockIdx.x * h * b + o] = tot;
-            }
         }
     }
 }
@@ -513,8 +586,9 @@ static int ensure_op(sfairsc_graph* g) {
     const int64_t n = g->n;
     w.nblk_spmm = grid_rows(n, kSpmmWaves, kSpmmMaxBlocks);
     w.nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
-    SF_TRY(w.part_in.ensure((size_t)w.nblk_proj * g->h * 32 * sizeof(double)));
-    SF_TRY(w.part_out.ensure((size_t)w.nblk_spmm * g->h * 32 * sizeof(double)));
+    // (rows of the output-major layouts round the block count up to 8)
+    SF_TRY(w.part_in.ensure((size_t)xcd_row(w.nblk_proj) * g->h * 32 * sizeof(double)));
+    SF_TRY(w.part_out.ensure((size_t)xcd_row(w.nblk_spmm) * g->h * 32 * sizeof(double)));
     SF_TRY(w.small.ensure((size_t)5 * kMaxGroups * 32 * sizeof(double)));
     SF_TRY(w.xp.ensure((size_t)n * 32 * sizeof(double)));
     SF_TRY(w.t.ensure((size_t)n * 32 * sizeof(double)));
@@ -523,14 +597,14 @@ static int ensure_op(sfairsc_graph* g) {
 
 template <class VT>
 static void launch_spmm(sfairsc_graph* g, int BW, const VT* X, VT* T, const VT* val, const VT* diag, int b,
-                        double* part, int nblk, hipStream_t s, const int* skip, double* partx = nullptr) {
-    size_t lds = part ? (size_t)(partx ? 2 : 1) * kSpmmWaves * g->h * BW * sizeof(double) : 0;
+                        double* part, int nblk, hipStream_t s, const int* skip, int om = 0) {
+    size_t lds = part ? (size_t)kSpmmWaves * g->h * BW * sizeof(double) : 0;
     // rows per wavefront: short rows share a wavefront (at most 4)
     const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 0.0;
     const int rpw = avg <= 24.0 ? 4 : (avg <= 96.0 ? 2 : 1);
 #define SF_SPMM_CASE(W, R)                                                                                     \
     k_spmm<VT, W, R><<<nblk, kSpmmThreads, lds, s>>>(g->rowptr, g->col, val, diag, X, T, g->n, g->grp, g->cs, \
-                                                     g->h, b, part, partx, skip)
+                                                     g->h, b, part, om, skip)
 #define SF_SPMM_RPW(W)                 \
     case W:                            \
         if (rpw == 4)                  \
@@ -641,10 +715,10 @@ static int op_deflate(sfairsc_graph* g, const OpOut& o, int b, double* Y, int ld
     return SFAIRSC_OK;
 }
 
-// The operator fits the reassociated form: both epilogue sums in the SpMM's
-// LDS (as the single-sum form's LDS at twice the groups).
-static bool fused_fits(const sfairsc_graph* g, int BW) {
-    return g->h >= 2 && g->op.lcw > 0 && 2 * g->h * BW <= 1024;
+// The reassociated form: group constraint, L C formed, and a power-of-two
+// block width of at least 4 (the compaction's layout).
+static bool fused_fits(const sfairsc_graph* g, int b) {
+    return g->h >= 2 && g->op.lcw > 0 && b >= 4 && (b & (b - 1)) == 0;
 }
 
 int op_prepare_lc(sfairsc_graph* g, hipStream_t s) {
@@ -680,25 +754,26 @@ static int op_apply_fused(sfairsc_graph* g, const double* X, int ldx, int b, int
     const int BW = pad_width(b);
     const int64_t n = g->n;
     const int h = g->h;
-    SF_TRY(w.part_x.ensure((size_t)w.nblk_spmm * h * 32 * sizeof(double)));
     double* Rout = w.small.as<double>() + 2 * kMaxGroups * 32;
     double* Uin = w.small.as<double>() + 3 * kMaxGroups * 32;
-    const int ga = grid_rows(n * BW, 256, 8192);
     if (mixed) {
-        k_proj_apply<float><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, nullptr, w.xp.as<float>(), skip);
+        k_compact_sums<float><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h, w.xp.as<float>(),
+                                                                 w.part_in.as<double>(), skip);
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<float>(g, BW, w.xp.as<float>(), w.t.as<float>(), g->val32, g->diag32, b,
-                           w.part_out.as<double>(), w.nblk_spmm, s, skip, w.part_x.as<double>());
+                           w.part_out.as<double>(), w.nblk_spmm, s, skip, 1);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
     } else {
-        k_proj_apply<double><<<ga, 256, 0, s>>>(X, ldx, b, BW, n, g->grp, g->cs, nullptr, w.xp.as<double>(), skip);
+        k_compact_sums<double><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h,
+                                                                  w.xp.as<double>(), w.part_in.as<double>(), skip);
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<double>(g, BW, w.xp.as<double>(), w.t.as<double>(), g->val64, g->diag64, b,
-                            w.part_out.as<double>(), w.nblk_spmm, s, skip, w.part_x.as<double>());
+                            w.part_out.as<double>(), w.nblk_spmm, s, skip, 1);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
     }
-    k_group_finalize2<<<32, kFin2Threads, 0, s>>>(w.part_x.as<double>(), w.part_out.as<double>(), w.nblk_spmm, h,
-                                                  b, g->gpar, w.ctlc.as<double>(), sigma, Rout, Uin, skip);
+    k_group_finalize2<<<32, kFin2Threads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(),
+                                                  w.nblk_spmm, h, b, g->gpar, w.ctlc.as<double>(), sigma, Rout, Uin,
+                                                  skip);
     SF_HIP(hipGetLastError());
     out->t = w.t.p;
     out->is_float = mixed != 0;
@@ -725,7 +800,7 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
         out->rtab = nullptr;
         return SFAIRSC_OK;
     }
-    if (fused_fits(g, pad_width(b))) return op_apply_fused(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, out);
+    if (fused_fits(g, b)) return op_apply_fused(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, out);
     OpWork& w = g->op;
     const OpBufs B{w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(), w.nblk_spmm, w.small.as<double>(),
                    w.xp.p, w.t.p};
