@@ -232,7 +232,9 @@ def main():
     kmeans_ms = (time.perf_counter() - t0) * 1e3
     from sfairsc_inputs.msbm import MSBMGraph  # noqa: F401
 
-    head = "mixed" if "mixed" in results else precs[0]
+    # the headline is the faster of the solves (both FP64-certified to the
+    # same tolerance); the other is reported beside it
+    head = min(results, key=lambda prec: results[prec][0])
     ms_head, r_head = results[head]
     s_val = 4 if head == "mixed" else 8
     per_launch_ms, _ = spmm[head]

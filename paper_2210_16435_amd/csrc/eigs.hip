@@ -1019,6 +1019,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
 // Ritz vectors X = V[:, 0:c] Z[:, 0:k] (row-major n x k in Xo, ld k).
 static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* scale) {
     const int c = R.c, k = S.k;
+    // up to 32 vectors: the matrix-core product of the orthogonalisation
+    if (k <= 32 && c % 4 == 0) return ortho_product(S.V, S.ld, S.n, c, S.rb.zk, k, Xo, k, scale, S.s);
     k_rotate<<<grid_for(S.n, kRotRows, 2048), 256, (size_t)kRotRows * c * sizeof(double), S.s>>>(
         S.V, S.ld, S.n, c, k, S.rb.zk, Xo, k, scale);
     SF_HIP(hipGetLastError());

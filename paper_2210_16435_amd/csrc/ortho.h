@@ -47,6 +47,12 @@ int ortho_expand(const OrthoArgs& a);
 int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double thresh, double* part, double* small,
                 double* gsave, double* rc, int* flag, hipStream_t s);
 
+// Out[i, 0:b] = rscale_i (V[i, 0:kin] M) on the matrix cores (M kin x b
+// row-major, b <= 32, kin a multiple of 4; Out row-major with leading
+// dimension ldo; rscale optional).
+int ortho_product(double* V, int ld, int64_t n, int kin, const double* M, int b, double* Out, int ldo,
+                  const double* rscale, hipStream_t s);
+
 // Thick-restart rotation into a second basis buffer (see ortho.hip).
 int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
                  hipStream_t s);

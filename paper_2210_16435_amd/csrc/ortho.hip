@@ -299,7 +299,8 @@ template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
-                                                          int ldo, const double* __restrict__ Htiles) {
+                                                          int ldo, const double* __restrict__ Htiles,
+                                                          const double* __restrict__ rscale) {
     if (skip && *skip) return;
     extern __shared__ double lds[];
     double* Ms = lds;                                   // [kin][BJ * 16]
@@ -364,15 +365,17 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
             }
         }
         // store Ynew: lane holds rows row0 + 4q + lk, column jt*16 + li
+        // (optionally scaled by row: Ritz vectors in the D^{-1/2} basis)
         const int col_in_tile = li;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int64_t row = row0 + 4 * q + lk;
             if (row < n) {
+                const double rs = rscale ? rscale[row] : 1.0;
 #pragma unroll
                 for (int jt = 0; jt < BJ; ++jt) {
                     const int col = jt * 16 + col_in_tile;
-                    if (col < b) Vout[row * ldo + yoff + col] = D[jt][q];
+                    if (col < b) Vout[row * ldo + yoff + col] = rscale ? D[jt][q] * rs : D[jt][q];
                 }
             }
         }
@@ -636,14 +639,15 @@ static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int l
 template <bool GRAM, bool SYRK>
 static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
                        int yoff, int b, int cv, const double* M, double* part, const int* skip,
-                       double* Vout = nullptr, int ldo = 0, const double* Htiles = nullptr) {
+                       double* Vout = nullptr, int ldo = 0, const double* Htiles = nullptr,
+                       const double* rscale = nullptr) {
     if (!Vout) {
         Vout = V;
         ldo = ld;
     }
 #define SF_PASS_U(BJV, RTV)                                                                                 \
     k_pass_upd<BJV, GRAM, SYRK, RTV>                                                                        \
-        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles)
+        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles, rscale)
     // the row-tile bound matters only for the Gram product
     const int rt = GRAM ? rt_bound(cv) : kMaxRT;
     if (BJ == 1) {
@@ -791,6 +795,20 @@ int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b
     const int BJ = b > 16 ? 2 : 1;
     launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, c, b, p, b, c, q, nullptr,
                              nullptr, Vout, ld);
+    SF_HIP(hipGetLastError());
+    return SFAIRSC_OK;
+}
+
+int ortho_product(double* V, int ld, int64_t n, int kin, const double* M, int b, double* Out, int ldo,
+                  const double* rscale, hipStream_t s) {
+    if (kin % 4 != 0 || ld % 4 != 0 || kin > kLdMax || b < 1 || b > 32)
+        return set_error(SFAIRSC_E_ARG, "internal: bad product shape kin=%d b=%d", kin, b);
+    const int BJ = b > 16 ? 2 : 1;
+    // no partial sums here: one 16-row tile per wavefront, for latency
+    const int64_t g = ((n + 15) / 16 + kOrWaves - 1) / kOrWaves;
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+    launch_upd<false, false>(BJ, nblk, (size_t)kin * BJ * 16 * sizeof(double), s, V, ld, n, 0, kin, 0, b, kin, M,
+                             nullptr, nullptr, Out, ldo, nullptr, rscale);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }
