@@ -295,17 +295,121 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
 // same wavefront).
 //   GRAM: partial [V[:, 0:cv]^T Ynew (nrt x BJ tiles); Ynew^T Ynew (BJ x BJ)]
 //   SYRK: partial Ynew^T Ynew
-template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT>
+//
+// With CB > 0 the pass first does the small finalisation that precedes it
+// (F.mode 1: the one before pass C, 2: before pass D), every workgroup
+// alike, instead of a single-workgroup kernel between the two: one
+// wavefront factors the CB x CB Gram block (R = chol(G), R^{-1}) from the
+// reduced tiles, M is built in LDS from them, and workgroup 0 also writes
+// what the solver keeps (the projected matrix's new column block and R1 in
+// mode 1, the coupling R2 R1 in mode 2, the Gram of the block and the
+// failure flag).  A failed factorisation fails alike in every workgroup:
+// all return, workgroup 0 raises the flag.
+struct FoldArgs {
+    int mode;
+    const double* sumA;  // mode 1: pass A's reduced tiles (H1)
+    const double* sumB;  // mode 1: pass B's (H2, then G); mode 2: pass C's (G2)
+    int BJ, cv, cact, ldt;
+    double thresh;
+    double* R1g;  // mode 1: written; mode 2: read
+    double* Gsave;
+    double* T;
+    double* Rc;
+    int* flag;
+};
+
+template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT, int CB = 0>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
                                                           int ldo, const double* __restrict__ Htiles,
-                                                          const double* __restrict__ rscale) {
+                                                          const double* __restrict__ rscale, FoldArgs F) {
     if (skip && *skip) return;
     extern __shared__ double lds[];
     double* Ms = lds;                                   // [kin][BJ * 16]
     const int mld = BJ * 16;
-    if (Htiles) {
+    if constexpr (CB > 0) {
+        constexpr int B = CB;
+        __shared__ double Rs[B * B], Ris[B * B];
+        __shared__ int bad;
+        const int nrtf = (F.cv + 15) >> 4;
+        const double* H2 = F.sumB;
+        const double* gt = F.mode == 1 ? F.sumB + (size_t)nrtf * F.BJ * 256 : F.sumB;
+        const bool w0 = blockIdx.x == 0;
+        if (threadIdx.x < 64) {
+            const int j = threadIdx.x;
+            double g[B], ri[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                g[i] = j < B ? tile_at(gt, F.BJ, i, j) : 0.0;
+                ri[i] = 0.0;
+                if (w0 && j < B) F.Gsave[i * B + j] = g[i];
+            }
+            const bool ok = wave_chol_inv<B>(g, ri, F.thresh);
+            if (j < B) {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    Rs[i * B + j] = g[i];
+                    Ris[i * B + j] = ri[i];
+                    if (w0 && F.mode == 1) F.R1g[i * B + j] = g[i];
+                }
+            }
+            if (j == 0) {
+                bad = ok ? 0 : 1;
+                if (!ok && w0) {
+                    F.flag[0] = 1;
+                    F.flag[1] = F.cact;
+                    F.flag[2] = F.mode;
+                }
+            }
+        } else if (F.mode == 1 && w0) {
+            // the projected matrix's new column block H1 + H2 (and its mirror
+            // row block)
+            for (int e = threadIdx.x - 64; e < F.cv * B; e += kOrThreads - 64) {
+                const int q = e / B, j = e - q * B;
+                const double h = tile_at(F.sumA, F.BJ, q, j) + tile_at(H2, F.BJ, q, j);
+                F.T[(size_t)q * F.ldt + F.cact + j] = h;
+                if (q < F.cact) F.T[(size_t)(F.cact + j) * F.ldt + q] = h;
+            }
+        }
+        __syncthreads();
+        if (F.mode == 1 && w0) {
+            // symmetrise the diagonal block (its two triangles came from two
+            // different sums)
+            for (int e = threadIdx.x; e < B * B; e += kOrThreads) {
+                const int i = e / B, j = e - i * B;
+                if (j > i) {
+                    double* x = F.T + (size_t)(F.cact + i) * F.ldt + F.cact + j;
+                    double* y = F.T + (size_t)(F.cact + j) * F.ldt + F.cact + i;
+                    const double mm = 0.5 * (*x + *y);
+                    *x = mm;
+                    *y = mm;
+                }
+            }
+        }
+        if (bad) return;
+        if (F.mode == 2 && w0)
+            for (int e = threadIdx.x; e < B * B; e += kOrThreads) {
+                const int i = e / B, j = e - i * B;
+                double acc = 0.0;
+                for (int q = i; q <= j; ++q) acc += Rs[i * B + q] * F.R1g[q * B + j];
+                F.Rc[e] = acc;
+            }
+        // M: mode 1 [-H2 R^{-1}; R^{-1}] (kin = cv + B rows), mode 2 R^{-1}
+        for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
+            const int q = e / mld, j = e - q * mld;
+            double acc = 0.0;
+            if (j < B) {
+                if (F.mode == 1 && q < F.cv) {
+                    for (int t = 0; t <= j; ++t) acc -= tile_at(H2, F.BJ, q, t) * Ris[t * B + j];
+                } else {
+                    const int r = F.mode == 1 ? q - F.cv : q;
+                    acc = Ris[r * B + j];
+                }
+            }
+            Ms[e] = acc;
+        }
+    } else if (Htiles) {
         // M = [-H1; I] straight from pass A's reduced tiles (rows < cv)
         for (int e = threadIdx.x; e < kin * mld; e += kOrThreads) {
             const int r = e / mld, j = e - r * mld;
@@ -647,7 +751,8 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
     }
 #define SF_PASS_U(BJV, RTV)                                                                                 \
     k_pass_upd<BJV, GRAM, SYRK, RTV>                                                                        \
-        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles, rscale)
+        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles, rscale, \
+                                    FoldArgs{})
     // the row-tile bound matters only for the Gram product
     const int rt = GRAM ? rt_bound(cv) : kMaxRT;
     if (BJ == 1) {
@@ -666,6 +771,21 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
             SF_PASS_U(2, kMaxRT);
     }
 #undef SF_PASS_U
+}
+
+// Pass C (SYRK) or D with the finalisation before it folded in (CB = b <= 8).
+template <bool SYRK>
+static void launch_fold(int b, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
+                        int yoff, int cv, double* part, const int* skip, const FoldArgs& F) {
+#define SF_FOLD(BJV, CBV)                                                                                    \
+    k_pass_upd<BJV, false, SYRK, kMaxRT, CBV><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv,     \
+                                                                         nullptr, part, skip, V, ld, nullptr, \
+                                                                         nullptr, F)
+    if (b == 4)
+        SF_FOLD(1, 4);
+    else
+        SF_FOLD(1, 8);
+#undef SF_FOLD
 }
 
 int ortho_expand(const OrthoArgs& a) {
@@ -705,30 +825,40 @@ int ortho_expand(const OrthoArgs& a) {
     launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, nullptr, a.part, a.flag, nullptr, 0,
                            sumA);
     k_reduce_partials<<<reduce_grid(OB), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
+
+    const int OC = BJ * BJ * 256;
+    size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
+    size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
+    if (b <= 8) {
+        // pass C: R1 = chol(G) and M2 = [-H2 R1^{-1}; R1^{-1}] (folded in),
+        // then Y1 = [V | Y'] M2 and its Syrk
+        FoldArgs F{1, sumA, sumB, BJ, cv, cact, a.ldt, a.thresh, R1, a.gsave, a.T, a.rc, a.flag};
+        launch_fold<true>(b, nblk, ldsC, s, a.V, a.ld, n, 0, kin, cv, cv, a.part, a.flag, F);
+        k_reduce_partials<<<reduce_grid(OC), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OC, sumA, a.flag);
+        // pass D: R2 = chol(G2), the coupling R2 R1 (folded in), Y2 = Y1 R2^{-1}
+        F.mode = 2;
+        F.sumB = sumA;
+        F.thresh = 0.25;
+        launch_fold<false>(b, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, cv, nullptr, a.flag, F);
+        SF_HIP(hipGetLastError());
+        return SFAIRSC_OK;
+    }
+    // wider blocks: the factorisations in single-workgroup kernels (one
+    // wavefront per SIMD; folded into a pass their registers would spill)
 #define SF_FINB(BB) \
     k_fin_b<BB><<<1, 256, 0, s>>>(sumA, sumB, BJ, cv, a.thresh, M2, R1, a.gsave, a.T, a.ldt, cact, a.flag, a.flag)
-    switch (b) {
-        case 4: SF_FINB(4); break;
-        case 8: SF_FINB(8); break;
-        case 16: SF_FINB(16); break;
-        default: SF_FINB(32); break;
-    }
+    if (b == 16)
+        SF_FINB(16);
+    else
+        SF_FINB(32);
 #undef SF_FINB
-
-    // pass C: Y1 = [V | Y'] M2, Syrk
-    size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
     launch_upd<false, true>(BJ, nblk, ldsC, s, a.V, a.ld, n, 0, kin, cv, b, cv, M2, a.part, a.flag);
-    const int OC = BJ * BJ * 256;
     k_reduce_partials<<<reduce_grid(OC), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OC, sumA, a.flag);
-    switch (b) {
-        case 4: k_fin_c<4><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
-        case 8: k_fin_c<8><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
-        case 16: k_fin_c<16><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
-        default: k_fin_c<32><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25); break;
-    }
-
+    if (b == 16)
+        k_fin_c<16><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25);
+    else
+        k_fin_c<32><<<1, 256, 0, s>>>(sumA, BJ, R1, M3, a.rc, a.gsave, cact, a.flag, a.flag, 0.25);
     // pass D: Y2 = Y1 R2^{-1}
-    size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
     launch_upd<false, false>(BJ, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, b, cv, M3, nullptr, a.flag);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
