@@ -406,6 +406,23 @@ int grid_for(int64_t work, int per, int cap) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+// Wait for an event by polling it: the solve's restarts wait for a few
+// hundred microseconds at a time, and a polling wait returns within a
+// microsecond or two of the GPU's completion where a blocking one can take
+// tens.  Past a few milliseconds it blocks instead.
+static int poll_wait(hipEvent_t e) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipSuccess) return SFAIRSC_OK;
+        if (q != hipErrorNotReady) return set_error(SFAIRSC_E_HIP, "hipEventQuery failed: %s", hipGetErrorString(q));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(4)) {
+            SF_HIP(hipEventSynchronize(e));
+            return SFAIRSC_OK;
+        }
+    }
+}
+
 struct Solver {
     sfairsc_graph* g;
     hipStream_t s;
@@ -445,6 +462,7 @@ struct Solver {
         if (!w.s2) SF_HIP(hipStreamCreateWithFlags(&w.s2, hipStreamNonBlocking));
         if (!w.ev_fork) SF_HIP(hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming));
         if (!w.ev_join) SF_HIP(hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming));
+        if (!w.ev_wait) SF_HIP(hipEventCreateWithFlags(&w.ev_wait, hipEventDisableTiming));
         s2 = w.s2;
         SF_TRY(rr_buffers(g, &rb));
         ld = ncv + b;
@@ -546,7 +564,8 @@ struct Solver {
     // Synchronise the stream; staged uploads are complete and staged
     // downloads are delivered afterwards.
     int sync() {
-        SF_HIP(hipStreamSynchronize(s));
+        SF_HIP(hipEventRecord(g->eig.ev_wait, s));
+        SF_TRY(poll_wait(g->eig.ev_wait));
         for (const Pending& p : pending) std::memcpy(p.dst, p.slot, p.bytes);
         pending.clear();
         g->eig.pin_off = 0;
@@ -709,7 +728,7 @@ struct Solver {
     // Deliver the staged downloads once the stream has reached event e
     // (work enqueued after e keeps running; it must not stage transfers).
     int sync_to(hipEvent_t e) {
-        SF_HIP(hipEventSynchronize(e));
+        SF_TRY(poll_wait(e));
         for (const Pending& p : pending) std::memcpy(p.dst, p.slot, p.bytes);
         pending.clear();
         g->eig.pin_off = 0;
@@ -972,11 +991,11 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         SF_TRY(S.op(c, &pre));
         ahead = true;
         SF_HIP(hipStreamWaitEvent(S.s, S.g->eig.ev_join, 0));
-        int hflag[3];
-        SF_TRY(S.download(hflag, S.flag, 3 * sizeof(int)));
+        // the record carries the expansion's flag words too: one download
         SF_TRY(S.download(rec.data(), S.rb.rec, rec.size() * sizeof(double)));
         SF_TRY(S.sync());
         SF_TRY(S.harvest_timing());
+        const int hflag[3] = {(int)rec[kRrRecFlag], (int)rec[kRrRecFlag + 1], (int)rec[kRrRecFlag + 2]};
         if (hflag[0]) {
             // everything after the failed expansion at hflag[1] was skipped
             const int cact = hflag[1];

@@ -251,6 +251,7 @@ static void free_graph(sfairsc_graph* g) {
     w.rr.release();
     if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
     if (w.ev_join) (void)hipEventDestroy(w.ev_join);
+    if (w.ev_wait) (void)hipEventDestroy(w.ev_wait);
     if (w.s2) (void)hipStreamDestroy(w.s2);
     if (w.pin) (void)hipHostFree(w.pin);
     w.pin = nullptr;

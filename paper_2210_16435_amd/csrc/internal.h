@@ -82,7 +82,7 @@ struct EigWork {
     // second stream: the Rayleigh-Ritz kernel runs beside the look-ahead
     // operator application of the solve's stream
     hipStream_t s2 = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_wait = nullptr;
     // Pinned host staging for host-to-device uploads: a pageable source may
     // be read by the DMA engine after hipMemcpyAsync returns, so every
     // upload is first copied here and the region is only reused after the

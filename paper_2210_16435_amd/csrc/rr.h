@@ -10,8 +10,11 @@ namespace sfairsc {
 // Record the kernel leaves for the host after a restart-mode call (doubles):
 // [0] pairs among the k wanted meeting tol, [1] p (Ritz vectors kept),
 // [2] m (Ritz vectors formed), [3] (theta_{k+1} - theta_k) / sigma (0 when
-// c <= k), then theta[0:k] and the residual estimates res[0:k].
-constexpr int kRrRecHead = 4;
+// c <= k), [4..6] the three words of the skip flag as the kernel found them
+// (written also when it skipped, so that one download carries both), then
+// theta[0:k] and the residual estimates res[0:k].
+constexpr int kRrRecFlag = 4;
+constexpr int kRrRecHead = 7;
 inline size_t rr_rec_doubles(int k) { return (size_t)kRrRecHead + 2 * (size_t)k; }
 
 struct RrArgs {
@@ -20,7 +23,8 @@ struct RrArgs {
     const double* T = nullptr;
     int ldt = 0;
     int c = 0;
-    const int* skip = nullptr;  // device flag: nonzero = leave every output untouched
+    const int* skip = nullptr;  // device flag (3 words): nonzero = leave every output but
+                                // the record's flag words untouched
     double* work = nullptr;     // rr_work_doubles() of scratch
     // mode 0 (restart): the Ritz vectors kept by the thick restart, chosen by
     // the rule of the solver, their residual estimates ||Rc Z[c-b:c, i]||

@@ -208,6 +208,7 @@ __device__ int sturm_laguerre(const double2* __restrict__ de, int c, double x, d
 
 template <int NR, int NC>
 __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
+    if (a.mode == 0 && a.rec && threadIdx.x < 3) a.rec[kRrRecFlag + threadIdx.x] = a.skip ? (double)a.skip[threadIdx.x] : 0.0;
     if (a.skip && *a.skip) return;
     constexpr int NT = 4 * NC;  // rows per lane in the back-transformation
     __shared__ double vs[2][kRrMax];
