@@ -716,9 +716,12 @@ static int op_deflate(sfairsc_graph* g, const OpOut& o, int b, double* Y, int ld
 }
 
 // The reassociated form: group constraint, L C formed, and a power-of-two
-// block width of at least 4 (the compaction's layout).
+// block width from 4 to 16 (the compaction's layout).  At 32 the launches it
+// saves are a rounding error against millisecond kernels, and the L C term
+// would land in the first orthogonalisation pass's widest variant, whose
+// registers are already short.
 static bool fused_fits(const sfairsc_graph* g, int b) {
-    return g->h >= 2 && g->op.lcw > 0 && b >= 4 && (b & (b - 1)) == 0;
+    return g->h >= 2 && g->op.lcw > 0 && b >= 4 && b <= 16 && (b & (b - 1)) == 0;
 }
 
 int op_prepare_lc(sfairsc_graph* g, hipStream_t s) {

@@ -80,15 +80,6 @@ __device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, doub
     for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
 }
 
-// Every lane of a quad takes the double of the quad's lane given by the
-// quad permutation CTRL (0x00, 0x55, 0xAA, 0xFF: lane 0, 1, 2, 3).
-template <int CTRL>
-__device__ __forceinline__ double quad_bcast(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
 __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
     const int tile = (i >> 4) * BJ + (j >> 4);
@@ -101,12 +92,13 @@ __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, 
 // (the last term only with LC, the reassociated operator); partial
 // V[:, 0:cv]^T Y0 (nrt x BJ tiles).  RT bounds nrt (4, 8 or kMaxRT): the
 // accumulators and the loads in flight are sized by it, so the common small
-// bases keep their registers for loads.  Of the LC row each lane loads the
-// value s = li mod 4 with the other loads (lcw >= 4 keeps it in bounds; the
-// table rows from m to 4 are zero) and takes the other three from its quad
-// by DPP broadcasts; values past the fourth (m > 4, the LCX variant) are read
-// where used.
-template <int BJ, class TT, int RT, bool LCX>
+// bases keep their registers for loads.  The L C term of a 16-row tile,
+// LC[16 x m] Utab[m x b], is a matrix-core product whose output registers
+// are already laid out as the tile's Y0 values (row 4q + lk of the tile in
+// register q of lane li + 16 lk): each lane loads one LC value per 4 of the
+// m columns (lcw, a multiple of 4, keeps the loads in bounds; LC's padding
+// columns and the table's rows from m on are zero).
+template <int BJ, class TT, int RT>
 __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, int ld, int64_t n, int cv, int b,
                                                         const TT* __restrict__ T, int BW,
                                                         const int32_t* __restrict__ grp,
@@ -119,8 +111,12 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
     extern __shared__ double lds[];
     // the deflation tables (kMaxGroups x 32 doubles; the rows past h are read
     // but never used), so that their lookups wait for no global load
+    // (the L C term is compiled for one column tile of the block only: the
+    // reassociated operator serves widths up to 16, and the two-tile
+    // variants have no registers to spare)
+    constexpr bool kLC = BJ == 1;
     __shared__ double rtab_s[BJ == 1 ? kMaxGroups * 32 : 1];
-    __shared__ double utab_s[BJ == 1 ? kMaxGroups * 32 : 1];
+    __shared__ double utab_s[kLC ? kMaxGroups * 32 : 1];
     if constexpr (BJ == 1) {
         if (Rtab)
             for (int e = threadIdx.x; e < kMaxGroups * 32; e += kOrThreads) rtab_s[e] = Rtab[e];
@@ -128,14 +124,6 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
             for (int e = threadIdx.x; e < kMaxGroups * 32; e += kOrThreads) utab_s[e] = e < m * 32 ? Utab[e] : 0.0;
         __syncthreads();
     }
-    // sum_{s<m} LC[row][s] Utab[s][col], from lv = LC[row][li mod 4]
-    auto lc_term = [&](double lv, int64_t row, int col) {
-        double r = (quad_bcast<0x00>(lv) * utab_s[col] + quad_bcast<0x55>(lv) * utab_s[32 + col]) +
-                   (quad_bcast<0xAA>(lv) * utab_s[64 + col] + quad_bcast<0xFF>(lv) * utab_s[96 + col]);
-        if constexpr (LCX)
-            for (int s2 = 4; s2 < m; ++s2) r += LC[row * lcw + s2] * utab_s[s2 * 32 + col];
-        return r;
-    };
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int nrt = (cv + 15) >> 4;
@@ -145,20 +133,31 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
     const int64_t ntiles = (n + 15) >> 4;
     const int64_t wstride = (int64_t)gridDim.x * kOrWaves;
     for (int64_t tile = (int64_t)blockIdx.x * kOrWaves + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
+        // the tile's L C term (see above): corr[jt][q] for row 4q + lk,
+        // column jt * 16 + li
+        d4 corr[1] = {d4{0, 0, 0, 0}};
+        if constexpr (kLC) {
+            if (LC) {
+                const int64_t ra = tile * 16 + li;
+                const int64_t rsa = ra < n ? ra : 0;
+                for (int k0 = 0; k0 < m; k0 += 4) {
+                    const double av = LC[rsa * lcw + k0 + lk];
+                    corr[0] = mfma(av, utab_s[(k0 + lk) * 32 + li], corr[0]);
+                }
+            }
+        }
         if constexpr (BJ == 1 && RT <= 8) {
             // a small basis: every load of the tile (4 steps) first
             double yraw[4];
             double araw[4][RT];
             double cq[4];
             int gq[4];
-            double lq[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t row = tile * 16 + q * 4 + lk;
                 const int64_t rs = row < n ? row : 0;
                 cq[q] = (cs && Rtab) ? cs[rs] : 1.0;
                 gq[q] = Rtab ? grp[rs] : 0;
-                lq[q] = LC ? LC[rs * lcw + (li & 3)] : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -176,12 +175,10 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                 const int64_t row = tile * 16 + q * 4 + lk;
                 const bool rv = row < n;
                 double y = 0.0;
-                // the broadcasts with every lane of the quad active
-                const double lct = LC ? lc_term(lq[q], rv ? row : 0, li) : 0.0;
                 if (rv && li < b) {
                     y = yraw[q];
                     if (Rtab) y -= cq[q] * rtab_s[gq[q] * 32 + li];
-                    y -= lct;
+                    if (LC) y -= corr[0][q];
                     V[row * ld + cv + li] = y;
                 }
 #pragma unroll
@@ -209,7 +206,6 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                 // for them only
                 const double c = (cs && Rtab) ? cs[rs] : 1.0;
                 const int gi = Rtab ? grp[rs] : 0;
-                const double l4 = LC ? LC[rs * lcw + (li & 3)] : 0.0;
 #pragma unroll
                 for (int jt = 0; jt < BJ; ++jt) {
                     const int col = jt * 16 + li;
@@ -225,8 +221,6 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                 // Y0 = T - c_i Rtab[g_i] (Rtab == nullptr: T already holds Y, a
                 // general constraint) into the new block's columns
                 double y[BJ];
-                // BJ == 1: the column is li; the broadcasts with every lane active
-                const double lct = LC ? lc_term(l4, rs, li) : 0.0;
 #pragma unroll
                 for (int jt = 0; jt < BJ; ++jt) {
                     const int col = jt * 16 + li;
@@ -234,7 +228,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                     if (rv && col < b) {
                         v = yraw[jt];
                         if (Rtab) v -= c * rtab_s[gi * 32 + col];
-                        v -= lct;
+                        if (LC) v -= corr[0][q];
                         V[row * ld + cv + col] = v;
                     }
                     y[jt] = v;
@@ -267,8 +261,6 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
                     if (rv && col < b) {
                         v = (double)T[row * BW + col];
                         if (Rtab) v -= c * Rtab[gi * 32 + col];
-                        if (LC)
-                            for (int s2 = 0; s2 < m; ++s2) v -= LC[row * lcw + s2] * Utab[s2 * 32 + col];
                         V[row * ld + cv + col] = v;
                     }
                     y[jt] = v;
@@ -318,7 +310,7 @@ struct FoldArgs {
     int* flag;
 };
 
-template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT, int CB = 0>
+template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT, int CB = 0, bool SCALE = false>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
@@ -475,11 +467,13 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
         for (int q = 0; q < 4; ++q) {
             const int64_t row = row0 + 4 * q + lk;
             if (row < n) {
-                const double rs = rscale ? rscale[row] : 1.0;
+                // (SCALE only: a conditional load here would make the
+                // stores wait for the loads already in flight)
+                const double rs = SCALE ? rscale[row] : 1.0;
 #pragma unroll
                 for (int jt = 0; jt < BJ; ++jt) {
                     const int col = jt * 16 + col_in_tile;
-                    if (col < b) Vout[row * ldo + yoff + col] = rscale ? D[jt][q] * rs : D[jt][q];
+                    if (col < b) Vout[row * ldo + yoff + col] = SCALE ? D[jt][q] * rs : D[jt][q];
                 }
             }
         }
@@ -712,15 +706,9 @@ template <class TT>
 static void launch_a(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int cv, int b,
                      const TT* T, int BW, const int32_t* grp, const double* cs, const double* Rtab,
                      const double* LC, int lcw, int m, const double* Utab, double* part, const int* skip) {
-#define SF_PASS_A(BJV, RTV)                                                                                   \
-    do {                                                                                                        \
-        if (LC && m > 4)                                                                                        \
-            k_pass_a<BJV, TT, RTV, true><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, LC, lcw, \
-                                                                    m, Utab, part, skip);                       \
-        else                                                                                                    \
-            k_pass_a<BJV, TT, RTV, false><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, LC,    \
-                                                                     lcw, m, Utab, part, skip);                 \
-    } while (0)
+#define SF_PASS_A(BJV, RTV)                                                                                 \
+    k_pass_a<BJV, TT, RTV><<<g, kOrThreads, lds, s>>>(V, ld, n, cv, b, T, BW, grp, cs, Rtab, LC, lcw, m, Utab, \
+                                                      part, skip)
     const int rt = rt_bound(cv);
     if (BJ == 1) {
         if (rt == 4)
@@ -749,10 +737,16 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
         Vout = V;
         ldo = ld;
     }
-#define SF_PASS_U(BJV, RTV)                                                                                 \
-    k_pass_upd<BJV, GRAM, SYRK, RTV>                                                                        \
-        <<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles, rscale, \
-                                    FoldArgs{})
+#define SF_PASS_U(BJV, RTV)                                                                                   \
+    do {                                                                                                        \
+        if (!GRAM && !SYRK && rscale)                                                                           \
+            k_pass_upd<BJV, GRAM, SYRK, RTV, 0, true><<<g, kOrThreads, lds, s>>>(                               \
+                V, ld, n, coff, kin, yoff, b, cv, M, part, skip, Vout, ldo, Htiles, rscale, FoldArgs{});        \
+        else                                                                                                    \
+            k_pass_upd<BJV, GRAM, SYRK, RTV><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv, M, part, \
+                                                                        skip, Vout, ldo, Htiles, nullptr,       \
+                                                                        FoldArgs{});                            \
+    } while (0)
     // the row-tile bound matters only for the Gram product
     const int rt = GRAM ? rt_bound(cv) : kMaxRT;
     if (BJ == 1) {
@@ -808,7 +802,7 @@ int ortho_expand(const OrthoArgs& a) {
     // pass A
     const int OA = nrt * BJ * 256;
     size_t ldsA = (size_t)OA * sizeof(double);
-    if (a.lc && (a.lcw < 4 || a.m > kMaxGroups - 1 || !a.utab))
+    if (a.lc && (b > 16 || a.lcw < 4 || a.lcw % 4 != 0 || a.m > a.lcw || a.m > kMaxGroups - 1 || !a.utab))
         return set_error(SFAIRSC_E_ARG, "internal: bad constraint image lcw=%d m=%d", a.lcw, a.m);
     if (a.t_is_float)
         launch_a<float>(BJ, nblk, ldsA, s, a.V, a.ld, n, cv, b, (const float*)a.t, a.BW, a.grp, a.cs, a.rtab, a.lc,
