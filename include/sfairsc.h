@@ -247,7 +247,10 @@ typedef struct sfairsc_eigs_opts {
     int32_t max_basis;     /* basis columns before a restart (<= 192);
                               0 = automatic                                */
     int32_t max_restarts;  /* 0 = automatic (2000)                        */
-    int32_t keep;          /* Ritz vectors kept at a restart; 0 = auto    */
+    int32_t keep;          /* Ritz vectors kept at a restart; 0 = auto:
+                              k + 0.35 (basis - k) for an FP64 solve with
+                              b <= 16, max(k + b, k + (basis - k) / 2)
+                              otherwise (rounded up to a multiple of 4)   */
     uint64_t seed;         /* seed of the random start block              */
     double sigma;          /* Hotelling shift; <= 0 selects ||L_n||_1     */
     int32_t certify;       /* 1: recompute the final residuals with an

@@ -1144,7 +1144,15 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
         }
     } else {
         S.mixed = false;
-        SF_TRY(run_ks(S, tol, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
+        // The automatic kept count of an FP64 solve at block widths up to 16:
+        // k + 0.35 (ncv - k) Ritz vectors (a third more new columns per cycle
+        // than keeping half, fewer restarts; measured on three m-SBM
+        // workloads, 2k, 10k and 50k vertices: 9-16% less time).  Wider
+        // blocks and the mixed solve keep half (there fewer kept vectors
+        // cost restarts).
+        int keep = o.keep;
+        if (keep <= 0 && b <= 16) keep = k + (7 * (ncv - k) + 10) / 20;
+        SF_TRY(run_ks(S, tol, max_restarts, keep, o.x0, o.b0, o.seed, R));
         SF_TRY(ritz_vectors(S, R, Xr, nullptr));
     }
     // Exact eigenvectors of L^sigma below sigma lie in null(C^T) (Prop. 3.1);
