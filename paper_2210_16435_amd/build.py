@@ -37,12 +37,8 @@ HIP_FLAGS = [
     "-packed-fp32-ops",
 ]
 
-# The batched kernel calls many non-inlined device functions; with
-# interprocedural register allocation the compiler produced a kernel whose
-# start phase broke down on every graph (values kept across calls in the
-# frame-pointer register), while the same source built without it is
-# correct.  The batched source is therefore built without it.
-HIP_EXTRA = {"batched.hip": ["-mllvm", "-enable-ipra=false"]}
+# Per-source extra options (none: every source builds with the same flags).
+HIP_EXTRA = {}
 
 
 def _run(cmd):

@@ -234,7 +234,7 @@ __device__ __forceinline__ double rnd_pm1(uint64_t seed, uint64_t idx) {
 
 // Rows of 16 in the wavefronts' partials (wred[w * WRED + 16 r + j], r <
 // rows) summed over the wavefronts, compacted to out[r * cols + j], j < cols.
-__device__ void wg_combine(const double* wred, int rows, int cols, double* __restrict__ out) {
+__device__ __forceinline__ void wg_combine(const double* wred, int rows, int cols, double* __restrict__ out) {
     __syncthreads();
     for (int e = threadIdx.x; e < rows * 16; e += NT) {
         if ((e & 15) >= cols) continue;
@@ -252,7 +252,7 @@ __device__ void wg_combine(const double* wred, int rows, int cols, double* __res
 // stored after it at out[rows * b + i * b + j].  MFMA D layout: lane l,
 // register r hold row 4 r + l / 16, column l % 16 of a tile.
 template <int NTL, bool SYRK>
-__device__ void wg_tiles(const d4 (&acc)[NTL], int ng, int rows, int b, double* wred, double* __restrict__ out) {
+__device__ __forceinline__ void wg_tiles(const d4 (&acc)[NTL], int ng, int rows, int b, double* wred, double* __restrict__ out) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nt = ng + (SYRK ? 1 : 0);
     for (int t0 = 0; t0 < nt; t0 += 2) {
@@ -292,7 +292,7 @@ __device__ void wg_tiles(const d4 (&acc)[NTL], int ng, int rows, int b, double* 
 }
 
 // Sum of v over the workgroup (fixed order); two values at once.
-__device__ void wg_sum2(double& a, double& b, double* red) {
+__device__ __forceinline__ void wg_sum2(double& a, double& b, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -685,7 +685,7 @@ __device__ SF_ITEM_FN void w_signs(const Graph& t, const double* X, int ld, int6
 }
 
 // The signs' maximum over a set of partials (lowest row on ties), 16 columns.
-__device__ void sign_merge(const double* p, double& b0, double& i0, double& v0) {
+__device__ __forceinline__ void sign_merge(const double* p, double& b0, double& i0, double& v0) {
     const int j = threadIdx.x & 15;
     const double ob = p[j], oi = p[16 + j];
     if (ob > b0 || (ob == b0 && oi < i0)) {
@@ -700,7 +700,7 @@ __device__ void sign_merge(const double* p, double& b0, double& i0, double& v0) 
 
 // dst[e] = sum over the graph's items of part[item][e], e < cnt, in a fixed
 // order (item residues modulo 8, then a fixed tree).
-__device__ void g_reduce(const double* __restrict__ part, int item0, int nitems, int cnt, double* dst) {
+__device__ __forceinline__ void g_reduce(const double* __restrict__ part, int item0, int nitems, int cnt, double* dst) {
     for (int e = threadIdx.x; e < cnt; e += NT) {
         const double* p = part + (size_t)item0 * PSTRIDE + e;
         double a[8];
@@ -720,7 +720,7 @@ __device__ void g_reduce(const double* __restrict__ part, int item0, int nitems,
 // A_t, s < h-1), optionally stored in Sout; then S -= sigma * Ssub;
 // U = Ginv S; R_s = U_s - q (s < h-1), R_{h-1} = -q, q = sum_s p_s U_s, so
 // that (C U)_i = c_i R_{g_i}.  R and Sout may be global.
-__device__ void g_finalize(const double* A, int h, int bw, const double* __restrict__ gpar, double* Sout,
+__device__ __forceinline__ void g_finalize(const double* A, int h, int bw, const double* __restrict__ gpar, double* Sout,
                            const double* Ssub, double sigma, double* zs, double* R) {
     const int j = threadIdx.x;
     if (j < bw) {
@@ -749,7 +749,7 @@ __device__ void g_finalize(const double* A, int h, int bw, const double* __restr
 }
 
 template <int B>
-__device__ bool chol_wave(const double* G, int b, double thresh, double* R, double* Rinv) {
+__device__ __forceinline__ bool chol_wave(const double* G, int b, double thresh, double* R, double* Rinv) {
     const int j = threadIdx.x;
     double g[B], ri[B];
 #pragma unroll
@@ -773,7 +773,7 @@ __device__ bool chol_wave(const double* G, int b, double thresh, double* R, doub
 // Cholesky factor R (row-major 16 x 16, identity beyond b) and R^{-1} of the
 // b x b matrix G (row-major), by wavefront 0.  Returns false on every thread
 // of the workgroup if a pivot is <= thresh.
-__device__ __noinline__ bool g_chol(const double* G, int b, double thresh, double* R, double* Rinv, Shared& S) {
+__device__ __forceinline__ bool g_chol(const double* G, int b, double thresh, double* R, double* Rinv, Shared& S) {
     if (threadIdx.x < 64) {
         const bool ok = b <= 4   ? chol_wave<4>(G, b, thresh, R, Rinv)
                         : b <= 8 ? chol_wave<8>(G, b, thresh, R, Rinv)
@@ -798,7 +798,7 @@ __device__ __noinline__ bool g_chol(const double* G, int b, double thresh, doubl
 // rotations themselves) are skipped and blocks of two skipped pairs are not
 // touched; the sweeps stop after one without rotations (at most 40).  On
 // return diag(A) holds the eigenvalues and Z the eigenvectors as columns.
-__device__ __noinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
+__device__ __forceinline__ void g_jacobi(double* A, int m, double* Z, Shared& S) {
     const int t = threadIdx.x;
     const int mm = m + (m & 1), np = mm / 2, rr = mm - 1;
     // this thread's block (pair ba, pair bc), if any
@@ -941,7 +941,7 @@ enum Ph { PH_OP = 0, PH_A, PH_B, PH_C, PH_D, PH_RR, PH_ROT, PH_IO };
 // owner workgroup: T_m diagonalized by Jacobi in LDS, the Ritz pairs in
 // ascending order, the residual estimates ||Rc z_last||, the convergence
 // test and the restart (or final) rotation, applied by the next row phase.
-__device__ __noinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int* active, Shared& S) {
+__device__ __forceinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int* active, Shared& S) {
     const int tid = threadIdx.x;
     const uint64_t t0 = wall_clock64();
     const int b = g.b, k = g.k;
@@ -1037,7 +1037,7 @@ __device__ __noinline__ void rayleigh_ritz(const Graph& g, GState& s, int m, int
 
 // The items of the graphs still in their block steps (out: of the graphs
 // with output), in graph order, into alist / nalist.  Workgroup 0 only.
-__device__ void build_list(const Launch& L, bool out, Shared& S) {
+__device__ __forceinline__ void build_list(const Launch& L, bool out, Shared& S) {
     int base = 0;
     for (int g0 = 0; g0 < L.ng; g0 += NT) {
         const int gi = g0 + threadIdx.x;
@@ -1078,10 +1078,10 @@ __device__ __forceinline__ void add_ticks(GState& s, int ph, uint64_t t0) {
 // item's partial slot), wp (this wavefront's LDS partial), tid, wave, S,
 // t0_ (the item's start clock)) returns false, before any work, when the
 // graph does not take part (uniform for the graph).  One non-inlined
-// instance per phase: the row work is inlined into it, so registers are
-// saved once per phase rather than once per item.
+// instance per phase, the row work inlined into it.  (Every helper of the
+// kernel is inlined: the kernel makes no calls.)
 template <class F>
-__device__ __noinline__ void items_phase(Launch L, Shared& S, int ph, F f) {
+__device__ __forceinline__ void items_phase(Launch L, Shared& S, int ph, F f) {
     const int tid = threadIdx.x, wave = tid >> 6;
     for (int j_ = blockIdx.x, n_ = *L.nalist; j_ < n_; j_ += gridDim.x) {
         const int it = L.alist[j_];
