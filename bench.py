@@ -20,6 +20,7 @@ The CPU baseline is the FP64 oracle (implicit-nullspace ARPACK) on the host.
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -69,6 +70,11 @@ def main():
         help="only run the n = 200,000 backward (after one FP64 forward solve) twenty times (for profilers)",
     )
     ap.add_argument(
+        "--setup-profile",
+        action="store_true",
+        help="only create the --workload graph handle from device-resident inputs ten times (for profilers)",
+    )
+    ap.add_argument(
         "--copy-calibration",
         action="store_true",
         help="only run a plain 256 MiB device-to-device copy three times (counter calibration)",
@@ -83,6 +89,17 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 3}))
+        return
+    if args.setup_profile:
+        import torch
+
+        import paper_2210_16435_amd as sf
+        from sfairsc_inputs import WORKLOADS, workload
+
+        normalized = WORKLOADS[args.workload][1]["normalized"]
+        g = workload(args.workload, relabel_seed=2)
+        G = sf.Graph.from_msbm(g, normalized)
+        print(json.dumps({"workload": args.workload, "setup_ms": setup_times(sf, torch, G, g, 10)}))
         return
     if args.backward_profile:
         import torch
@@ -174,7 +191,8 @@ def main():
     t0 = time.perf_counter()
     G = sf.Graph.from_msbm(g, normalized, device=dev)
     torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
+    setup_first_ms = (time.perf_counter() - t0) * 1e3
+    setup_ms = statistics.median(setup_times(sf, torch, G, g, 5))
     H_out = torch.empty((k, g.n), dtype=torch.float64, device=dev)
 
     def solve(prec, timing=False):
@@ -323,6 +341,7 @@ def main():
         "restarts": r_head.info["restarts"],
         "block_steps": r_head.info["block_steps"],
         "graph_setup_ms": round(setup_ms, 3),
+        "graph_setup_first_ms": round(setup_first_ms, 3),
         "kmeans_ms": round(kmeans_ms, 3),
         "phase_breakdown": phase_break,
         "spmm_gbps": round(achieved, 1),
@@ -342,6 +361,22 @@ def main():
         "other_workloads": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def setup_times(sf, torch, G, g, reps):
+    """Milliseconds per graph creation from inputs already on the device
+    (the handle's own copies of rowptr, col and groups, the weights copied
+    once), created and destroyed reps times."""
+    va = torch.from_numpy(g.val).to(G.device)
+    out = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G2 = sf.Graph(G._rowptr, G._col, va, G._groups, G.h, G.normalized, device=G.device)
+        torch.cuda.synchronize()
+        out.append(round((time.perf_counter() - t0) * 1e3, 3))
+        G2.close()
+    return out
 
 
 def _log(msg):

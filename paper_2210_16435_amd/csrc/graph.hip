@@ -48,7 +48,15 @@ void DevBuf::release() {
 }
 
 // ---------------------------------------------------------------------------
-// validation kernels.  Error bits written with atomicOr into flags[0].
+// Set-up kernels.  Pass 1 validates the CSR and forms the degrees, pass 2
+// checks symmetry and writes the operator's values, pass 3 sums the group
+// statistics.  Every block leaves one partial record (no atomics: thousands
+// of blocks updating one address serialise) and a last kernel folds them into
+// the small record the host reads once.  Each CSR row is handled by LPR lanes
+// (a power of two from 8 to 64, from the mean degree), each lane taking
+// kUnroll entries at a time so that their loads are in flight together; each
+// per-row sum is a fixed shuffle tree, so degrees and values are
+// reproducible.
 enum : int {
     kBadRowptr = 1,
     kBadCol = 2,
@@ -58,125 +66,384 @@ enum : int {
     kBadGroup = 32,
 };
 
-__global__ void k_check_rowptr(const int32_t* __restrict__ rowptr, int64_t n, int64_t nnz,
-                               int* flags) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int32_t a = rowptr[i], b = rowptr[i + 1];
-        bool bad = a > b || a < 0 || b > nnz;
-        if (i == 0 && a != 0) bad = true;
-        if (i == n - 1 && b != nnz) bad = true;
-        if (bad) atomicOr(flags, kBadRowptr);
+constexpr int kSetupThreads = 256;
+constexpr int kSetupBlocksMax = 8192;  // passes 1 and 2
+constexpr int kStatBlocksMax = 1024;   // pass 3
+constexpr int kFoldThreads = 1024;
+constexpr int kUnroll = 4;  // entries per lane whose loads are issued together
+
+// One block's partial of pass 1 (flags, min and max degree) or pass 2 (flags,
+// max row sum in hi, stored entries above the diagonal minus those below).
+struct RowPart {
+    int flags;
+    int pad;
+    double lo, hi;
+    long long updown;
+};
+
+// What the host reads back.
+struct SetupSums {
+    int flags;
+    int pad;
+    double dmin, dmax, rsmax;
+    long long updown;
+    double cnt[kMaxGroups];   // |V_s|
+    double esum[kMaxGroups];  // sum over V_s of 1/d_i
+};
+
+template <int LPR>
+__device__ __forceinline__ double row_sum(double v) {
+    for (int o = LPR / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPR);
+    return v;
+}
+
+// Block-wide OR, min, max and integer sum; NT threads.  The result is valid
+// in thread 0.  Each of these is exact in any order.
+template <int NT>
+__device__ void block_reduce(int& f, double& lo, double& hi, long long& ud) {
+    __shared__ int sf[NT / 64];
+    __shared__ double slo[NT / 64], shi[NT / 64];
+    __shared__ long long sud[NT / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        f |= __shfl_xor(f, o);
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+        ud += __shfl_xor(ud, o);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sf[w] = f;
+        slo[w] = lo;
+        shi[w] = hi;
+        sud[w] = ud;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < NT / 64; ++t) {
+            f |= sf[t];
+            lo = fmin(lo, slo[t]);
+            hi = fmax(hi, shi[t]);
+            ud += sud[t];
+        }
     }
 }
 
-__global__ void k_check_groups(const int32_t* __restrict__ grp, int64_t n, int h, int* flags,
-                               unsigned long long* counts) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int32_t s = grp[i];
-        if (s < 0 || s >= h)
-            atomicOr(flags, kBadGroup);
-        else
-            atomicAdd(&counts[s], 1ull);
+__device__ __forceinline__ void write_part(RowPart* out, int f, double lo, double hi, long long ud) {
+    block_reduce<kSetupThreads>(f, lo, hi, ud);
+    if (threadIdx.x == 0) {
+        RowPart r;
+        r.flags = f;
+        r.pad = 0;
+        r.lo = lo;
+        r.hi = hi;
+        r.updown = ud;
+        out[blockIdx.x] = r;
     }
 }
 
-// Rows: column range, order, diagonal, values; degree by a sequential sum.
-template <class VT>
-__global__ void k_check_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                             const VT* __restrict__ val, int64_t n, int* flags,
-                             double* __restrict__ deg) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int32_t a = rowptr[i], b = rowptr[i + 1];
+// Pass 1: row pointers, column range and order, no stored diagonal, finite
+// non-negative weights, group labels in [0, h); d_i = sum_j w_ij (Section
+// 2.1).  Every access stays inside the arrays whatever the input holds: a
+// row whose pointers are out of order or range is flagged and skipped.
+template <class VT, int LPR>
+__global__ __launch_bounds__(kSetupThreads) void k_check_rows(const int32_t* __restrict__ rowptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const VT* __restrict__ val,
+                                                              const int32_t* __restrict__ grp, int64_t n,
+                                                              int64_t nnz, int h, double* __restrict__ deg,
+                                                              RowPart* __restrict__ part) {
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t stride = (int64_t)gridDim.x * (kSetupThreads / LPR);
+    int f = 0;
+    double lo = INFINITY, hi = 0.0;
+    for (int64_t i = (blockIdx.x * (int64_t)kSetupThreads + threadIdx.x) / LPR; i < n; i += stride) {
+        const int32_t a = rowptr[i], b = rowptr[i + 1];
         double d = 0.0;
-        int32_t prev = -1;
-        int f = 0;
-        for (int32_t e = a; e < b; ++e) {
-            int32_t j = col[e];
-            if (j < 0 || j >= n || j <= prev) f |= kBadCol;
-            if (j == i) f |= kDiag;
-            prev = j;
-            double w = (double)val[e];
-            if (!(w >= 0.0) || !isfinite(w)) f |= kBadValue;
-            d += w;
-        }
-        deg[i] = d;
-        if (f) atomicOr(flags, f);
-    }
-}
-
-// Symmetry: every (i, j, w) has a bitwise-equal (j, i, w).
-template <class VT>
-__global__ void k_check_sym(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                            const VT* __restrict__ val, int64_t n, int* flags) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int32_t a = rowptr[i], b = rowptr[i + 1];
-        for (int32_t e = a; e < b; ++e) {
-            int32_t j = col[e];
-            int32_t lo = rowptr[j], hi = rowptr[j + 1] - 1;
-            bool found = false;
-            while (lo <= hi) {
-                int32_t mid = (lo + hi) >> 1;
-                int32_t c = col[mid];
-                if (c == (int32_t)i) {
-                    found = (val[mid] == val[e]);
-                    break;
+        if (a < 0 || a > b || b > nnz || (i == 0 && a != 0) || (i == n - 1 && b != nnz)) {
+            f |= kBadRowptr;
+        } else {
+            for (int64_t e0 = (int64_t)a + lane; e0 < b; e0 += kUnroll * LPR) {
+                bool ok[kUnroll];
+                int32_t j[kUnroll], jp[kUnroll];
+                double w[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int64_t e = e0 + u * LPR;
+                    ok[u] = e < b;
+                    j[u] = 0;
+                    jp[u] = INT32_MIN;
+                    w[u] = 0.0;
+                    if (ok[u]) {
+                        j[u] = col[e];
+                        if (e > a) jp[u] = col[e - 1];
+                        w[u] = (double)val[e];
+                    }
                 }
-                if (c < i)
-                    lo = mid + 1;
-                else
-                    hi = mid - 1;
-            }
-            if (!found) {
-                atomicOr(flags, kAsym);
-                return;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (!ok[u]) continue;
+                    if (j[u] < 0 || j[u] >= n || jp[u] >= j[u]) f |= kBadCol;
+                    if (j[u] == i) f |= kDiag;
+                    if (!(w[u] >= 0.0) || !isfinite(w[u])) f |= kBadValue;
+                    d += w[u];
+                }
             }
         }
+        d = row_sum<LPR>(d);
+        if (lane == 0) {
+            deg[i] = d;
+            const int32_t s = grp[i];
+            if (s < 0 || s >= h) f |= kBadGroup;
+            lo = fmin(lo, d);
+            hi = fmax(hi, d);
+        }
     }
+    write_part(part, f, lo, hi, 0);
 }
 
-// Operator values.  Unnormalized: off-diagonal w, diagonal d.  Normalized:
-// w-hat = w / sqrt(d_i d_j), diagonal 1, c_i = d_i^{-1/2}; rowsum = sum_j w-hat.
-template <class VT>
-__global__ void k_setup_values(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                               const VT* __restrict__ val, const double* __restrict__ deg, int64_t n,
-                               int normalized, double* __restrict__ val64, float* __restrict__ val32,
-                               double* __restrict__ diag64, float* __restrict__ diag32,
-                               double* __restrict__ cs, double* __restrict__ rowsum) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) {
-        int32_t a = rowptr[i], b = rowptr[i + 1];
-        double di = deg[i];
-        double si = normalized ? 1.0 / sqrt(di) : 1.0;
+// Pass 2: symmetry and the operator's values.  Each stored (i, j, w) above
+// the diagonal looks up (j, i) by binary search in row j and needs an equal
+// weight; the stored entries above and below the diagonal must also be
+// equally many.  Columns strictly increasing in a row make (i, j) -> (j, i)
+// one-to-one from the entries above into those below, so with equal counts it
+// is onto as well: W is symmetric, at half the lookups of checking every
+// entry.  Unnormalized:
+// off-diagonal w, diagonal d.  Normalized (Alg. 3 step 2): w / sqrt(d_i d_j),
+// diagonal 1, c_i = d_i^{-1/2}; the row sums of the scaled weights give sigma.
+// Safe on any input (pass 1's flags decide what is reported).
+template <class VT, int LPR>
+__global__ __launch_bounds__(kSetupThreads) void k_setup_values(
+    const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col, const VT* __restrict__ val,
+    const double* __restrict__ deg, int64_t n, int64_t nnz, int normalized, double* __restrict__ val64,
+    float* __restrict__ val32, double* __restrict__ diag64, float* __restrict__ diag32, double* __restrict__ cs,
+    RowPart* __restrict__ part) {
+    const int lane = threadIdx.x & (LPR - 1);
+    const int64_t stride = (int64_t)gridDim.x * (kSetupThreads / LPR);
+    int f = 0;
+    double rsmax = 0.0;
+    long long ud = 0;
+    for (int64_t i = (blockIdx.x * (int64_t)kSetupThreads + threadIdx.x) / LPR; i < n; i += stride) {
+        const int32_t a = rowptr[i], b = rowptr[i + 1];
+        const bool rowok = a >= 0 && a <= b && b <= nnz;
+        const double di = deg[i];
+        const double si = normalized ? 1.0 / sqrt(di) : 1.0;
         double rs = 0.0;
-        for (int32_t e = a; e < b; ++e) {
-            double w = (double)val[e];
-            if (normalized) w = w * si * (1.0 / sqrt(deg[col[e]]));
-            val64[e] = w;
-            val32[e] = (float)w;
-            rs += w;
+        for (int64_t e0 = rowok ? (int64_t)a + lane : (int64_t)b; e0 < b; e0 += kUnroll * LPR) {
+            bool ok[kUnroll], act[kUnroll];
+            int32_t j[kUnroll];
+            VT wv[kUnroll];
+            int64_t lo[kUnroll], hi[kUnroll], hit[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t e = e0 + u * LPR;
+                j[u] = e < b ? col[e] : -1;
+                ok[u] = j[u] >= 0 && j[u] < n;
+                wv[u] = ok[u] ? val[e] : VT(0);
+            }
+            // the searches of the entries above the diagonal, interleaved so
+            // that their loads are in flight together; each probe stays in
+            // [rowptr[j], rowptr[j+1]) and each step shrinks it or ends
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                act[u] = ok[u] && j[u] > i;
+                lo[u] = 0;
+                hi[u] = -1;
+                hit[u] = -1;
+                if (act[u]) {
+                    ++ud;
+                    lo[u] = rowptr[j[u]];
+                    hi[u] = (int64_t)rowptr[j[u] + 1] - 1;
+                } else if (ok[u] && j[u] < i) {
+                    --ud;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) act[u] = act[u] && lo[u] >= 0 && hi[u] < nnz && lo[u] <= hi[u];
+            for (;;) {
+                bool any = false;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) any |= act[u];
+                if (!any) break;
+                int64_t mid[kUnroll];
+                int32_t c[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    mid[u] = (lo[u] + hi[u]) >> 1;
+                    c[u] = act[u] ? col[mid[u]] : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (!act[u]) continue;
+                    if (c[u] == (int32_t)i) {
+                        hit[u] = mid[u];
+                        act[u] = false;
+                    } else {
+                        if (c[u] < (int32_t)i)
+                            lo[u] = mid[u] + 1;
+                        else
+                            hi[u] = mid[u] - 1;
+                        act[u] = lo[u] <= hi[u];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (!(ok[u] && j[u] > i)) continue;
+                if (!(hit[u] >= 0 && val[hit[u]] == wv[u])) f |= kAsym;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (!ok[u]) continue;
+                double w = (double)wv[u];
+                if (normalized) w = w * si * (1.0 / sqrt(deg[j[u]]));
+                const int64_t e = e0 + u * LPR;
+                val64[e] = w;
+                val32[e] = (float)w;
+                rs += w;
+            }
         }
-        double dg = normalized ? 1.0 : di;
-        diag64[i] = dg;
-        diag32[i] = (float)dg;
-        if (normalized) cs[i] = si;
-        rowsum[i] = rs;
+        rs = row_sum<LPR>(rs);
+        if (lane == 0) {
+            const double dg = normalized ? 1.0 : di;
+            diag64[i] = dg;
+            diag32[i] = (float)dg;
+            if (normalized) cs[i] = si;
+            rsmax = fmax(rsmax, rs);
+        }
+    }
+    write_part(part, f, INFINITY, rsmax, ud);
+}
+
+// Pass 3: per group the count |V_s| and e_s = sum over V_s of 1/d_i (the
+// closed form of C^T C below needs both).  Each block sums a contiguous
+// chunk, wavefront by wavefront, in a fixed order; one partial per block.
+__global__ __launch_bounds__(kSetupThreads) void k_group_stats(const int32_t* __restrict__ grp,
+                                                               const double* __restrict__ deg, int64_t n, int h,
+                                                               int64_t chunk, double* __restrict__ part) {
+    constexpr int NW = kSetupThreads / 64;
+    __shared__ double acc[NW][2 * kMaxGroups];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int t = threadIdx.x; t < NW * 2 * kMaxGroups; t += kSetupThreads) (&acc[0][0])[t] = 0.0;
+    __syncthreads();
+    const int64_t r0 = blockIdx.x * chunk, r1 = r0 + chunk < n ? r0 + chunk : n;
+    for (int64_t base = r0 + 64 * w; base < r1; base += kSetupThreads) {
+        const int64_t i = base + lane;
+        int s = -1;
+        double r = 0.0;
+        if (i < r1) {
+            s = grp[i];
+            const double d = deg[i];
+            r = d > 0.0 ? 1.0 / d : 0.0;
+        }
+        for (int t = 0; t < h; ++t) {
+            double c = s == t ? 1.0 : 0.0, e = s == t ? r : 0.0;
+            for (int o = 32; o > 0; o >>= 1) {
+                c += __shfl_xor(c, o);
+                e += __shfl_xor(e, o);
+            }
+            if (lane == 0) {
+                acc[w][t] += c;
+                acc[w][kMaxGroups + t] += e;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxGroups) {
+        double v = 0.0;
+        for (int t = 0; t < NW; ++t) v += acc[t][threadIdx.x];
+        part[(int64_t)blockIdx.x * 2 * kMaxGroups + threadIdx.x] = v;
     }
 }
 
-static int grid_for(int64_t n) {
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
+// Folds the partials: order-free operations for passes 1 and 2; the group
+// sums of pass 3 in a fixed order (16 slices of the blocks, each summed in
+// block order with eight loads in flight, then the slices in order).
+__global__ __launch_bounds__(kFoldThreads) void k_setup_fold(const RowPart* __restrict__ p1,
+                                                             const RowPart* __restrict__ p2, int nrow,
+                                                             const double* __restrict__ gpart, int nstat,
+                                                             SetupSums* S) {
+    int f = 0;
+    double lo = INFINITY, hi = 0.0, rs = 0.0;
+    long long ud = 0;
+    for (int q = threadIdx.x; q < nrow; q += kFoldThreads) {
+        const RowPart a = p1[q], b = p2[q];
+        f |= a.flags | b.flags;
+        lo = fmin(lo, a.lo);
+        hi = fmax(hi, a.hi);
+        rs = fmax(rs, b.hi);
+        ud += b.updown;
+    }
+    block_reduce<kFoldThreads>(f, lo, hi, ud);
+    __syncthreads();  // the reduction's shared arrays are used again
+    int f2 = 0;
+    double inf = INFINITY;
+    long long zero = 0;
+    block_reduce<kFoldThreads>(f2, inf, rs, zero);
+    if (threadIdx.x == 0) {
+        S->flags = f;
+        S->pad = 0;
+        S->dmin = lo;
+        S->dmax = hi;
+        S->rsmax = rs;
+        S->updown = ud;
+    }
+
+    constexpr int NS = kFoldThreads / (2 * kMaxGroups);
+    __shared__ double red[NS][2 * kMaxGroups];
+    const int fld = threadIdx.x % (2 * kMaxGroups), q0 = threadIdx.x / (2 * kMaxGroups);
+    double v = 0.0;
+    int q = q0;
+    for (; q + 7 * NS < nstat; q += 8 * NS) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = gpart[(int64_t)(q + u * NS) * 2 * kMaxGroups + fld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
+    }
+    for (; q < nstat; q += NS) v += gpart[(int64_t)q * 2 * kMaxGroups + fld];
+    red[q0][fld] = v;
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxGroups) {
+        double t = 0.0;
+        for (int r = 0; r < NS; ++r) t += red[r][threadIdx.x];
+        if (threadIdx.x < kMaxGroups)
+            S->cnt[threadIdx.x] = t;
+        else
+            S->esum[threadIdx.x - kMaxGroups] = t;
+    }
+}
+
+// Lanes per CSR row from the mean degree: about kUnroll entries per lane.
+static int lanes_per_row(int64_t n, int64_t nnz) {
+    const double m = (double)nnz / (double)n;
+    return m >= 256 ? 64 : m >= 128 ? 32 : m >= 64 ? 16 : 8;
+}
+
+static int row_grid(int64_t n, int lpr) {
+    int64_t g = (n * lpr + kSetupThreads - 1) / kSetupThreads;
+    if (g > kSetupBlocksMax) g = kSetupBlocksMax;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+template <class VT>
+static void launch_setup_rows(const sfairsc_graph* g, const VT* val, int lpr, int gr, RowPart* p1, RowPart* p2,
+                              hipStream_t s) {
+#define SF_ROWS(L)                                                                                          \
+    do {                                                                                                    \
+        k_check_rows<VT, L><<<gr, kSetupThreads, 0, s>>>(g->rowptr, g->col, val, g->grp, g->n, g->nnz, g->h, \
+                                                         g->deg, p1);                                       \
+        k_setup_values<VT, L><<<gr, kSetupThreads, 0, s>>>(g->rowptr, g->col, val, g->deg, g->n, g->nnz,   \
+                                                           g->normalized, g->val64, g->val32, g->diag64,    \
+                                                           g->diag32, g->cs, p2);                           \
+    } while (0)
+    switch (lpr) {
+        case 64: SF_ROWS(64); break;
+        case 32: SF_ROWS(32); break;
+        case 16: SF_ROWS(16); break;
+        default: SF_ROWS(8); break;
+    }
+#undef SF_ROWS
 }
 
 // Cholesky-based inverse of a small SPD matrix (row-major m x m), host.
@@ -292,7 +559,6 @@ static int create_impl(sfairsc_graph* g, int64_t n, int64_t nnz, const int32_t* 
     g->normalized = normalized;
     g->value_dtype = value_dtype;
     SF_HIP(hipGetDevice(&g->device));
-    const size_t vsz = value_dtype == SFAIRSC_F32 ? 4 : 8;
 
     SF_TRY(dmalloc(&g->rowptr, n + 1));
     SF_TRY(dmalloc(&g->col, nnz));
@@ -308,102 +574,57 @@ static int create_impl(sfairsc_graph* g, int64_t n, int64_t nnz, const int32_t* 
     SF_HIP(hipMemcpyAsync(g->rowptr, rowptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     if (nnz) SF_HIP(hipMemcpyAsync(g->col, colidx, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     SF_HIP(hipMemcpyAsync(g->grp, group, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    // the original values are kept in the val64 buffer's storage until
-    // k_setup_values has read them: copy them into a temporary first
-    void* wtmp = nullptr;
-    SF_HIP(hipMalloc(&wtmp, nnz * vsz + 16));
-    if (nnz) SF_HIP(hipMemcpyAsync(wtmp, values, nnz * vsz, hipMemcpyDeviceToDevice, s));
-
-    int* dflags = nullptr;
-    unsigned long long* dcounts = nullptr;
-    double* rowsum = nullptr;
-    struct Cleanup {
-        void** ptrs[3];
-        ~Cleanup() {
-            for (auto p : ptrs)
-                if (*p) (void)hipFree(*p);
+    // the per-block partials of the three passes, then the folded record
+    const int lpr = lanes_per_row(n, nnz);
+    const int gr = row_grid(n, lpr);
+    int nstat = (int)std::min<int64_t>(kStatBlocksMax, (n + 2047) / 2048);
+    const int64_t chunk = (n + nstat - 1) / nstat;
+    nstat = (int)((n + chunk - 1) / chunk);
+    const size_t o_p2 = (size_t)gr * sizeof(RowPart), o_g = 2 * o_p2,
+                 o_s = o_g + (size_t)nstat * 2 * kMaxGroups * sizeof(double);
+    void* tmp = nullptr;
+    SF_HIP(hipMalloc(&tmp, o_s + sizeof(SetupSums)));
+    struct Free1 {
+        void** p;
+        ~Free1() {
+            if (*p) (void)hipFree(*p);
         }
-    } cleanup{{&wtmp, (void**)&dflags, (void**)&dcounts}};
-    SF_HIP(hipMalloc(&dflags, 64));
-    SF_HIP(hipMalloc(&dcounts, kMaxGroups * sizeof(unsigned long long)));
-    SF_HIP(hipMemsetAsync(dflags, 0, 64, s));
-    SF_HIP(hipMemsetAsync(dcounts, 0, kMaxGroups * sizeof(unsigned long long), s));
-
-    const int gr = grid_for(n);
-    k_check_rowptr<<<gr, 256, 0, s>>>(g->rowptr, n, nnz, dflags);
-    k_check_groups<<<gr, 256, 0, s>>>(g->grp, n, h, dflags, dcounts);
-    SF_HIP(hipGetLastError());
-    int hflags = 0;
-    SF_HIP(hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
-    SF_HIP(hipStreamSynchronize(s));
-    if (hflags & kBadRowptr) return set_error(SFAIRSC_E_ARG, "malformed CSR row pointers");
-    if (hflags & kBadGroup) return set_error(SFAIRSC_E_ARG, "group label outside [0, h)");
+    } free_tmp{&tmp};
+    RowPart* p1 = (RowPart*)tmp;
+    RowPart* p2 = (RowPart*)((char*)tmp + o_p2);
+    double* gpart = (double*)((char*)tmp + o_g);
+    SetupSums* dS = (SetupSums*)((char*)tmp + o_s);
 
     if (value_dtype == SFAIRSC_F32)
-        k_check_rows<float><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const float*)wtmp, n, dflags, g->deg);
+        launch_setup_rows(g, (const float*)values, lpr, gr, p1, p2, s);
     else
-        k_check_rows<double><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const double*)wtmp, n, dflags, g->deg);
+        launch_setup_rows(g, (const double*)values, lpr, gr, p1, p2, s);
+    k_group_stats<<<nstat, kSetupThreads, 0, s>>>(g->grp, g->deg, n, h, chunk, gpart);
+    k_setup_fold<<<1, kFoldThreads, 0, s>>>(p1, p2, gr, gpart, nstat, dS);
     SF_HIP(hipGetLastError());
-    SF_HIP(hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+    SetupSums hs;
+    SF_HIP(hipMemcpyAsync(&hs, dS, sizeof hs, hipMemcpyDeviceToHost, s));
     SF_HIP(hipStreamSynchronize(s));
+    const int hflags = hs.flags;
+    if (hflags & kBadRowptr) return set_error(SFAIRSC_E_ARG, "malformed CSR row pointers");
+    if (hflags & kBadGroup) return set_error(SFAIRSC_E_ARG, "group label outside [0, h)");
     if (hflags & kBadCol) return set_error(SFAIRSC_E_ARG, "column index out of range or not strictly increasing");
     if (hflags & kDiag) return set_error(SFAIRSC_E_ARG, "stored diagonal entry (w_ii must be 0 and not stored)");
     if (hflags & kBadValue) return set_error(SFAIRSC_E_ARG, "negative or non-finite weight");
-
-    if (value_dtype == SFAIRSC_F32)
-        k_check_sym<float><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const float*)wtmp, n, dflags);
-    else
-        k_check_sym<double><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const double*)wtmp, n, dflags);
-    SF_HIP(hipGetLastError());
-    SF_HIP(hipMemcpyAsync(&hflags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
-    std::vector<unsigned long long> cnt(kMaxGroups);
-    SF_HIP(hipMemcpyAsync(cnt.data(), dcounts, kMaxGroups * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    std::vector<double> hdeg(n);
-    SF_HIP(hipMemcpyAsync(hdeg.data(), g->deg, n * sizeof(double), hipMemcpyDeviceToHost, s));
-    std::vector<int32_t> hgrp(n);
-    SF_HIP(hipMemcpyAsync(hgrp.data(), g->grp, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SF_HIP(hipStreamSynchronize(s));
-    if (hflags & kAsym) return set_error(SFAIRSC_E_ASYM, "W is not symmetric");
+    if ((hflags & kAsym) || hs.updown != 0) return set_error(SFAIRSC_E_ASYM, "W is not symmetric");
+    std::vector<unsigned long long> cnt(h);
+    for (int t = 0; t < h; ++t) cnt[t] = (unsigned long long)hs.cnt[t];
     for (int t = 0; t < h; ++t)
         if (cnt[t] == 0) return set_error(SFAIRSC_E_EMPTY_GROUP, "group %d is empty", t);
-    double dmin = INFINITY, dmax = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        dmin = std::min(dmin, hdeg[i]);
-        dmax = std::max(dmax, hdeg[i]);
-    }
+    const double dmin = hs.dmin, dmax = hs.dmax;
     g->dmin = dmin;
     g->dmax = dmax;
     if (normalized && !(dmin > 0.0))
         return set_error(SFAIRSC_E_ISOLATED, "isolated vertex: the normalized variant needs d_i > 0");
 
-    SF_HIP(hipMalloc(&rowsum, n * sizeof(double) + 16));
-    struct Free1 {
-        double** p;
-        ~Free1() {
-            if (*p) (void)hipFree(*p);
-        }
-    } free_rowsum{&rowsum};
-    if (value_dtype == SFAIRSC_F32)
-        k_setup_values<float><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const float*)wtmp, g->deg, n, normalized,
-                                                 g->val64, g->val32, g->diag64, g->diag32, g->cs, rowsum);
-    else
-        k_setup_values<double><<<gr, 256, 0, s>>>(g->rowptr, g->col, (const double*)wtmp, g->deg, n, normalized,
-                                                  g->val64, g->val32, g->diag64, g->diag32, g->cs, rowsum);
-    SF_HIP(hipGetLastError());
-    std::vector<double> hrs(n);
-    SF_HIP(hipMemcpyAsync(hrs.data(), rowsum, n * sizeof(double), hipMemcpyDeviceToHost, s));
-    SF_HIP(hipStreamSynchronize(s));
-
     // sigma = ||L_n||_1 = max_j sum_i |(L_n)_ij|; W symmetric with zero diagonal
     // gives 1 + max_j sum_i w-hat_ij (normalized) or 2 max_j d_j.
-    double sig = 0.0;
-    if (normalized) {
-        double m = 0.0;
-        for (int64_t i = 0; i < n; ++i) m = std::max(m, hrs[i]);
-        sig = 1.0 + m;
-    } else {
-        sig = 2.0 * dmax;
-    }
+    double sig = normalized ? 1.0 + hs.rsmax : 2.0 * dmax;
     if (!(sig > 0.0)) sig = 1.0;  // edgeless graph: any positive shift works
     g->sigma = sig;
 
@@ -427,10 +648,9 @@ static int create_impl(sfairsc_graph* g, int64_t n, int64_t nnz, const int32_t* 
             // C^T C = diag(e_s) - e p^T - p e^T + E p p^T, e_s = sum_{V_s} 1/d_i
             std::vector<double> e(h, 0.0);
             double E = 0.0;
-            for (int64_t i = 0; i < n; ++i) {
-                double r = 1.0 / hdeg[i];
-                e[hgrp[i]] += r;
-                E += r;
+            for (int t = 0; t < h; ++t) {
+                e[t] = hs.esum[t];
+                E += e[t];
             }
             for (int a = 0; a < m; ++a)
                 for (int b = 0; b < m; ++b)

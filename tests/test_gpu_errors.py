@@ -33,6 +33,42 @@ def test_asymmetric_value():
     assert e.value.code == sf.E_ASYM
 
 
+def _drop_entry(rp, ci, va, e):
+    keep = np.ones(len(ci), bool)
+    keep[e] = False
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))[keep]
+    rp2 = np.zeros_like(rp)
+    np.cumsum(np.bincount(rows, minlength=len(rp) - 1), out=rp2[1:])
+    return rp2, ci[keep], va[keep]
+
+
+@pytest.mark.parametrize("side", ["above", "below"])
+def test_asymmetric_pattern_either_side(side):
+    # one stored copy of an edge removed, above or below the diagonal: a
+    # lookup from above finds no partner, or the counts above and below differ
+    sf = lib()
+    rp, ci, va, gr = _base()
+    rows = np.repeat(np.arange(200), np.diff(rp))
+    cand = np.flatnonzero(ci > rows) if side == "above" else np.flatnonzero(ci < rows)
+    rp2, ci2, va2 = _drop_entry(rp, ci, va, cand[len(cand) // 2])
+    for normalized in (False, True):
+        with pytest.raises(sf.SfairscError) as e:
+            _create(sf, rp2, ci2, va2, gr, normalized=normalized)
+        assert e.value.code == sf.E_ASYM
+
+
+@pytest.mark.parametrize("side", ["above", "below"])
+def test_asymmetric_value_either_side(side):
+    sf = lib()
+    rp, ci, va, gr = _base()
+    rows = np.repeat(np.arange(200), np.diff(rp))
+    cand = np.flatnonzero(ci > rows) if side == "above" else np.flatnonzero(ci < rows)
+    va[cand[-1]] = np.nextafter(va[cand[-1]], va.dtype.type(np.inf))  # one ulp of the stored dtype
+    with pytest.raises(sf.SfairscError) as e:
+        _create(sf, rp, ci, va, gr)
+    assert e.value.code == sf.E_ASYM
+
+
 def test_negative_and_nan_weights():
     sf = lib()
     for bad in (-1.0, np.nan, np.inf):
@@ -92,6 +128,34 @@ def test_malformed_csr():
     with pytest.raises(sf.SfairscError) as e:
         _create(sf, rp, ci3, va, gr)
     assert e.value.code in (sf.E_ARG, sf.E_ASYM)
+
+
+STRUCTURE_CASES = {
+    # name: how the CSR of the valid 200-vertex graph is broken
+    "rowptr_first": lambda rp, ci: rp.__setitem__(0, 1),
+    "rowptr_last_short": lambda rp, ci: rp.__setitem__(-1, rp[-1] - 1),
+    "rowptr_beyond_nnz": lambda rp, ci: rp.__setitem__(50, rp[-1] + 1000),
+    "rowptr_negative": lambda rp, ci: rp.__setitem__(30, -5),
+    "rowptr_int_min": lambda rp, ci: rp.__setitem__(30, np.iinfo(np.int32).min),
+    "col_equal_n": lambda rp, ci: ci.__setitem__(7, 200),
+    "col_negative": lambda rp, ci: ci.__setitem__(7, -1),
+    "col_int_max": lambda rp, ci: ci.__setitem__(7, np.iinfo(np.int32).max),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STRUCTURE_CASES))
+@pytest.mark.parametrize("normalized", [False, True])
+def test_malformed_structure_is_rejected(name, normalized):
+    # the set-up passes run without a host check between them, so each of
+    # these reaches every pass, whose own guards keep it in bounds
+    sf = lib()
+    rp, ci, va, gr = _base()
+    STRUCTURE_CASES[name](rp, ci)
+    with pytest.raises(sf.SfairscError) as e:
+        _create(sf, rp, ci, va, gr, normalized=normalized)
+    assert e.value.code == sf.E_ARG, name
+    # the library is still usable afterwards
+    _create(sf, *_base(), normalized=normalized).close()
 
 
 def test_bad_solver_arguments():

@@ -59,6 +59,57 @@ def test_apply_operator_fp64_and_mixed(case, b):
     assert np.abs(Ym - ref).max() <= mixed_tol(g) * scale
 
 
+SETUP_CASES = [
+    # (mean degree, h, value dtype): the set-up passes give a CSR row 8, 16,
+    # 32 or 64 lanes by mean degree (8 below 64, 64 from 256 on); h up to the
+    # maximum of 32 groups
+    (4, 2, np.float64),
+    (30, 32, np.float32),
+    (90, 5, np.float64),
+    (150, 7, np.float32),
+    (300, 3, np.float64),
+]
+
+
+def _with_hub(g, every):
+    # vertex 0 joined to every `every`-th vertex: one row far longer than a
+    # wavefront, whatever the lanes per row
+    import scipy.sparse as sp
+
+    W = g.to_scipy(g.val.dtype).tolil()
+    for j in range(every, g.n, every):
+        W[0, j] = W[j, 0] = 0.75
+    W = sp.csr_matrix(W)
+    W.sort_indices()
+    return W
+
+
+@pytest.mark.parametrize("case", range(len(SETUP_CASES)))
+@pytest.mark.parametrize("normalized", [False, True])
+def test_graph_setup_against_the_oracle(case, normalized):
+    sf = lib()
+    deg, h, dt = SETUP_CASES[case]
+    log(f"set-up mean degree {deg} h={h} {np.dtype(dt).name} normalized={normalized}")
+    g = random_sparse_graph(3001, deg, seed=11 + case, h=h, val_dtype=dt)
+    W = _with_hub(g, 3)
+    val = W.data.astype(dt)
+    G = sf.Graph(W.indptr.astype(np.int32), W.indices.astype(np.int32), val, g.groups, h, normalized)
+    W64 = W.astype(np.float64)
+    d = oracle.degrees(W64)
+    st = G.stats()
+    assert st["sigma"] == pytest.approx(oracle.shift_sigma(W64, normalized), rel=1e-13)
+    assert st["min_degree"] == pytest.approx(d.min(), rel=1e-13)
+    assert st["max_degree"] == pytest.approx(d.max(), rel=1e-13)
+    assert st["nnz"] == W.nnz and st["h"] == h
+    # the values, the diagonal and the closed form of (C^T C)^{-1} all enter
+    # the operator
+    X = np.random.default_rng(case).standard_normal((g.n, 4))
+    ref = oracle.apply_deflated_operator(W64, g.groups, h, normalized, G.sigma, X)
+    Y = to_np(G.apply_operator(torch.from_numpy(X), "fp64"))
+    assert np.abs(Y - ref).max() <= 1e-12 * G.sigma * np.abs(X).max()
+    G.close()
+
+
 def mixed_tol(g):
     deg_max = int(np.diff(g.rowptr).max())
     return 2.0 * (deg_max + 2) * 2.0**-24
