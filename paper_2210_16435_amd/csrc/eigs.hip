@@ -439,6 +439,9 @@ struct Solver {
     double *H1, *H2, *Gsave, *R1, *Rinv, *Rc, *theta, *Q, *stats;
     int64_t* imax;
     int* flag;
+    // the column of the block whose operator input the last expansion wrote
+    // (-1: none), and the blocks of its group sums
+    int xp_ready = -1, xp_nblk = 0;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> evs;
@@ -663,7 +666,8 @@ struct Solver {
     // matrix-core orthogonalisation passes into V[:, c+b : c+2b].
     // The operator on the block V[:, c : c + b] (projection, sparse product,
     // C^T T): its output feeds the orthogonalisation of the expansion.
-    int op(int c, OpOut* o) {
+    int op(int c, OpOut* o, hipStream_t st = nullptr) {
+        if (!st) st = s;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
             if (ev_used + 2 > evs.size()) {
@@ -676,9 +680,13 @@ struct Solver {
             e0 = evs[ev_used++];
             e1 = evs[ev_used++];
         }
-        SF_TRY(phase_mark(0, true));
-        SF_TRY(op_apply_t(g, V + c, ld, b, mixed, sigma, s, e0, e1, flag, o));
-        SF_TRY(phase_mark(0, false));
+        SF_TRY(phase_mark(0, true, st));
+        // the block the last expansion wrote also came out in the operator's
+        // input form (compact copy and group sums): used once
+        const int prepared = xp_ready == c ? xp_nblk : 0;
+        xp_ready = -1;
+        SF_TRY(op_apply_t(g, V + c, ld, b, mixed, sigma, st, e0, e1, flag, o, prepared));
+        SF_TRY(phase_mark(0, false, st));
         if (info) {
             info->operator_applies += b;
             info->spmm_launches[mixed ? 1 : 0] += 1;
@@ -714,8 +722,18 @@ struct Solver {
         a.rc = Rc;
         a.flag = flag;
         a.stream = s;
+        // blocks of 4 or 8: the last pass also writes the new block in the
+        // operator's input form
+        OpInput in{nullptr, nullptr};
+        if (b <= 8) SF_TRY(op_input_target(g, b, &in));
+        a.xp = in.xp;
+        a.xp_float = mixed;
+        a.xsum = in.xsum;
+        a.h = g->h;
         SF_TRY(phase_mark(1, true));
         SF_TRY(ortho_expand(a));
+        xp_ready = in.xp ? c + b : -1;
+        xp_nblk = ortho_nblk(n);
         return phase_mark(1, false);
     }
 
@@ -735,8 +753,9 @@ struct Solver {
         return SFAIRSC_OK;
     }
 
-    int phase_mark(int kind, bool begin) {
+    int phase_mark(int kind, bool begin, hipStream_t st = nullptr) {
         if (!timing) return SFAIRSC_OK;
+        if (!st) st = s;
         if (begin) {
             if (pev_used + 2 > pev.size()) {
                 for (int i = 0; i < 64; ++i) {
@@ -747,9 +766,9 @@ struct Solver {
                 pkind.resize(pev.size() / 2);
             }
             pkind[pev_used / 2] = kind;
-            SF_HIP(hipEventRecord(pev[pev_used], s));
+            SF_HIP(hipEventRecord(pev[pev_used], st));
         } else {
-            SF_HIP(hipEventRecord(pev[pev_used + 1], s));
+            SF_HIP(hipEventRecord(pev[pev_used + 1], st));
             pev_used += 2;
         }
         return SFAIRSC_OK;
@@ -783,11 +802,16 @@ struct Solver {
         return SFAIRSC_OK;
     }
 
-    // The Rayleigh-Ritz step on the projected matrix T[0:c, 0:c], enqueued on
-    // the second stream after everything on the solve's stream so far; the
-    // caller joins the streams (ev_join) before it reads the results.
+    // The Rayleigh-Ritz step on the projected matrix T[0:c, 0:c], on the
+    // solve's stream; the second stream is released (ev_fork) for the
+    // look-ahead operator application (op_ahead), which the solve's stream
+    // joins (ev_join) before anything reads the results.
     int rayleigh_ritz(int c, double tol, int keep_opt) {
         EigWork& w = g->eig;
+        // the second stream may start the look-ahead operator application
+        // from here on; the Rayleigh-Ritz kernel goes first on the solve's
+        // stream, so that its one workgroup is placed before the sparse
+        // product's fill the GPU
         SF_HIP(hipEventRecord(w.ev_fork, s));
         SF_HIP(hipStreamWaitEvent(s2, w.ev_fork, 0));
         if (timing) {
@@ -798,7 +822,7 @@ struct Solver {
                     rr_evs.push_back(e);
                 }
             }
-            SF_HIP(hipEventRecord(rr_evs[rr_ev_used], s2));
+            SF_HIP(hipEventRecord(rr_evs[rr_ev_used], s));
         }
         RrArgs a;
         a.T = T;
@@ -818,12 +842,21 @@ struct Solver {
         a.Qch = Q;
         a.Zk = rb.zk;
         a.rec = rb.rec;
-        SF_TRY(rr_launch(a, s2));
+        SF_TRY(rr_launch(a, s));
         if (timing) {
-            SF_HIP(hipEventRecord(rr_evs[rr_ev_used + 1], s2));
+            SF_HIP(hipEventRecord(rr_evs[rr_ev_used + 1], s));
             rr_ev_used += 2;
         }
+        return SFAIRSC_OK;
+    }
+
+    // The look-ahead operator application on the second stream beside the
+    // Rayleigh-Ritz step; the solve's stream waits for it (ev_join).
+    int op_ahead(int c, OpOut* o) {
+        EigWork& w = g->eig;
+        SF_TRY(op(c, o, s2));
         SF_HIP(hipEventRecord(w.ev_join, s2));
+        SF_HIP(hipStreamWaitEvent(s, w.ev_join, 0));
         return SFAIRSC_OK;
     }
 
@@ -849,6 +882,7 @@ struct Solver {
 static int repair_block(Solver& S, int cact, uint64_t seed, int attempt, int stage) {
     const int b = S.b;
     const int cv = cact + b;
+    S.xp_ready = -1;  // the block changes here
     int zero = 0;
     SF_TRY(S.upload(S.flag, &zero, sizeof(int)));
     auto gram = [&](const double* M, std::vector<double>& G) -> int {
@@ -950,6 +984,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     const int b = S.b, ncv = S.ncv, k = S.k;
     const int64_t n = S.n;
     SF_TRY(S.setup());
+    S.xp_ready = -1;
     // start block
     int c = 0;
     if (x0 && b0 > 0) k_copy_in<<<grid_for(n * b0, 256, 8192), 256, 0, S.s>>>(x0, b0, S.V, S.ld, n, 0);
@@ -988,9 +1023,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         // stream meanwhile (wasted if this cycle converges).  Both skip their
         // work if the last expansion broke down (flag).
         SF_TRY(S.rayleigh_ritz(c, tol, keep_opt));
-        SF_TRY(S.op(c, &pre));
+        SF_TRY(S.op_ahead(c, &pre));
         ahead = true;
-        SF_HIP(hipStreamWaitEvent(S.s, S.g->eig.ev_join, 0));
         // the record carries the expansion's flag words too: one download
         SF_TRY(S.download(rec.data(), S.rb.rec, rec.size() * sizeof(double)));
         SF_TRY(S.sync());
@@ -1027,6 +1061,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         // slices followed by the identity in S.Q, and all Ritz values in theta
         SF_TRY(S.phase_mark(2, true));
         SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
+        S.xp_ready = -1;
         SF_TRY(S.phase_mark(2, false));
         std::swap(S.V, S.V2);
         k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.rb.theta);

@@ -24,6 +24,19 @@ constexpr int kLdMax = kMaxBasis + kMaxBlock;  // basis leading dimension
 // tolerance marks the k-dimensional eigenspace as not determined.
 constexpr double kDegenerateGap = 100.0;
 
+// Output-major partial sums by XCD: consecutive workgroups run on different
+// XCDs (round robin over 8), so block blk's slot is (blk mod 8) per + blk / 8
+// with per = ceil(nblk / 8): each XCD's blocks fill whole lines of a row
+// (its L2 writes them back whole) and a row of 8 per slots is read
+// contiguously.  Slots past nblk are never written and never read.
+__host__ __device__ inline int xcd_row(int nblk) { return 8 * ((nblk + 7) >> 3); }
+__host__ __device__ inline int xcd_slot(int blk, int nblk) { return (blk & 7) * ((nblk + 7) >> 3) + (blk >> 3); }
+__device__ inline bool xcd_valid(int slot, int nblk) {
+    const int per = (nblk + 7) >> 3;
+    const int x = slot / per;
+    return (slot - x * per) * 8 + x < nblk;
+}
+
 int set_error(int code, const char* fmt, ...);
 
 #define SF_HIP(call)                                                          \
@@ -241,8 +254,19 @@ struct OpOut {
 // L C and C^T L C for the operator's reassociated form (group constraint,
 // h >= 2); a no-op otherwise or when already formed.
 int op_prepare_lc(sfairsc_graph* g, hipStream_t s);
+// prepared_nblk > 0: the compact input (op.xp) and its per-block group sums
+// (op.part_in, that many blocks) were already written, by the
+// orthogonalisation pass that produced X (see op_input_target).
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
-               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out);
+               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out, int prepared_nblk = 0);
+// Where a producer of the operator's next input writes it (compact copy,
+// group-sum partials), when op_apply_t takes a prepared input for block
+// width b: both null otherwise.
+struct OpInput {
+    void* xp;
+    double* xsum;
+};
+int op_input_target(sfairsc_graph* g, int b, OpInput* in);
 
 // Raw sparse product T = L X (no projection), X/T compact row-major n x b.
 int op_spmm_raw(sfairsc_graph* g, const void* X, void* T, int b, int mixed,

@@ -20,6 +20,7 @@
 //
 // Every reduction has a fixed order (per-block partials combined in block
 // order), so results are bitwise reproducible run to run.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 
@@ -150,19 +151,6 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_partial_p2(const double* 
         for (int w = 0; w < NWV; ++w) sum += wsum[w][o];
         part[(size_t)blockIdx.x * h * b + o] = sum;
     }
-}
-
-// Output-major partial sums by XCD: consecutive workgroups run on different
-// XCDs (round robin over 8), so block blk's slot is (blk mod 8) per + blk / 8
-// with per = ceil(nblk / 8): each XCD's blocks fill whole lines of a row
-// (its L2 writes them back whole) and a row of 8 per slots is read
-// contiguously.  Slots past nblk are never written and never read.
-__host__ __device__ inline int xcd_row(int nblk) { return 8 * ((nblk + 7) >> 3); }
-__host__ __device__ inline int xcd_slot(int blk, int nblk) { return (blk & 7) * ((nblk + 7) >> 3) + (blk >> 3); }
-__device__ inline bool xcd_valid(int slot, int nblk) {
-    const int per = (nblk + 7) >> 3;
-    const int x = slot / per;
-    return (slot - x * per) * 8 + x < nblk;
 }
 
 // X compacted (row stride b) in type OT and the per-block sums of c_i X~_i
@@ -587,7 +575,9 @@ static int ensure_op(sfairsc_graph* g) {
     w.nblk_spmm = grid_rows(n, kSpmmWaves, kSpmmMaxBlocks);
     w.nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
     // (rows of the output-major layouts round the block count up to 8)
-    SF_TRY(w.part_in.ensure((size_t)xcd_row(w.nblk_proj) * g->h * 32 * sizeof(double)));
+    // (the input sums may also come from the orthogonalisation's last pass,
+    // over up to 256 blocks)
+    SF_TRY(w.part_in.ensure((size_t)xcd_row(std::max(w.nblk_proj, 256)) * g->h * 32 * sizeof(double)));
     SF_TRY(w.part_out.ensure((size_t)xcd_row(w.nblk_spmm) * g->h * 32 * sizeof(double)));
     SF_TRY(w.small.ensure((size_t)5 * kMaxGroups * 32 * sizeof(double)));
     SF_TRY(w.xp.ensure((size_t)n * 32 * sizeof(double)));
@@ -752,29 +742,36 @@ int op_prepare_lc(sfairsc_graph* g, hipStream_t s) {
 // The reassociated operator: X compacted (no projection), T0 = L_n X with
 // both epilogue sums, then the two tables (R_out for C, U_in for L_n C).
 static int op_apply_fused(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma,
-                          hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
+                          hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out,
+                          int prepared_nblk) {
     OpWork& w = g->op;
     const int BW = pad_width(b);
     const int64_t n = g->n;
     const int h = g->h;
     double* Rout = w.small.as<double>() + 2 * kMaxGroups * 32;
     double* Uin = w.small.as<double>() + 3 * kMaxGroups * 32;
+    // the compact input and its group sums: already written by the last
+    // orthogonalisation pass (prepared_nblk > 0 blocks of sums), or here
+    const bool prep = prepared_nblk > 0;
+    const int nblk_x = prep ? prepared_nblk : w.nblk_proj;
     if (mixed) {
-        k_compact_sums<float><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h, w.xp.as<float>(),
-                                                                 w.part_in.as<double>(), skip);
+        if (!prep)
+            k_compact_sums<float><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h,
+                                                                     w.xp.as<float>(), w.part_in.as<double>(), skip);
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<float>(g, BW, w.xp.as<float>(), w.t.as<float>(), g->val32, g->diag32, b,
                            w.part_out.as<double>(), w.nblk_spmm, s, skip, 1);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
     } else {
-        k_compact_sums<double><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h,
-                                                                  w.xp.as<double>(), w.part_in.as<double>(), skip);
+        if (!prep)
+            k_compact_sums<double><<<w.nblk_proj, kProjThreads, 0, s>>>(X, ldx, b, n, g->grp, g->cs, h,
+                                                                      w.xp.as<double>(), w.part_in.as<double>(), skip);
         if (ev_begin) SF_HIP(hipEventRecord(ev_begin, s));
         launch_spmm<double>(g, BW, w.xp.as<double>(), w.t.as<double>(), g->val64, g->diag64, b,
                             w.part_out.as<double>(), w.nblk_spmm, s, skip, 1);
         if (ev_end) SF_HIP(hipEventRecord(ev_end, s));
     }
-    k_group_finalize2<<<32, kFin2Threads, 0, s>>>(w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(),
+    k_group_finalize2<<<32, kFin2Threads, 0, s>>>(w.part_in.as<double>(), nblk_x, w.part_out.as<double>(),
                                                   w.nblk_spmm, h, b, g->gpar, w.ctlc.as<double>(), sigma, Rout, Uin,
                                                   skip);
     SF_HIP(hipGetLastError());
@@ -789,8 +786,18 @@ static int op_apply_fused(sfairsc_graph* g, const double* X, int ldx, int b, int
     return SFAIRSC_OK;
 }
 
+int op_input_target(sfairsc_graph* g, int b, OpInput* in) {
+    in->xp = nullptr;
+    in->xsum = nullptr;
+    if (g->qbas || g->memb || !fused_fits(g, b)) return SFAIRSC_OK;
+    SF_TRY(ensure_op(g));
+    in->xp = g->op.xp.p;
+    in->xsum = g->op.part_in.as<double>();
+    return SFAIRSC_OK;
+}
+
 int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, double sigma, hipStream_t s,
-               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out) {
+               hipEvent_t ev_begin, hipEvent_t ev_end, const int* skip, OpOut* out, int prepared_nblk) {
     if (b < 1 || b > kMaxBlock) return set_error(SFAIRSC_E_ARG, "block width %d outside [1, 32]", b);
     SF_TRY(ensure_op(g));
     if (g->qbas || g->memb) {
@@ -803,7 +810,9 @@ int op_apply_t(sfairsc_graph* g, const double* X, int ldx, int b, int mixed, dou
         out->rtab = nullptr;
         return SFAIRSC_OK;
     }
-    if (fused_fits(g, b)) return op_apply_fused(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, out);
+    if (fused_fits(g, b))
+        return op_apply_fused(g, X, ldx, b, mixed, sigma, s, ev_begin, ev_end, skip, out, prepared_nblk);
+    if (prepared_nblk > 0) return set_error(SFAIRSC_E_ARG, "internal: prepared operator input on the general path");
     OpWork& w = g->op;
     const OpBufs B{w.part_in.as<double>(), w.nblk_proj, w.part_out.as<double>(), w.nblk_spmm, w.small.as<double>(),
                    w.xp.p, w.t.p};

@@ -32,7 +32,18 @@ struct OrthoArgs {
     int* flag;          // flag[0] = failure, flag[1] = its column,
                         // flag[2] = 1 (first Cholesky) or 2 (second)
     hipStream_t stream;
+    // optional (block widths 4 and 8): the new block as the operator's next
+    // input, written by the last pass: its compact copy (n x b, float when
+    // xp_float) and per-block sums of c_i x_i per group (h groups, output-
+    // major by XCD slot over ortho_nblk(n) blocks)
+    void* xp = nullptr;
+    bool xp_float = false;
+    double* xsum = nullptr;
+    int h = 0;
 };
+
+// Workgroups of the expansion's passes (the blocks of xsum).
+int ortho_nblk(int64_t n);
 
 size_t ortho_part_doubles(int64_t n);
 size_t ortho_small_doubles();

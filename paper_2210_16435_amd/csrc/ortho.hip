@@ -30,6 +30,8 @@
 // summed in a fixed order by k_reduce_partials: bitwise reproducible results.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "internal.h"
 #include "ortho.h"
 #include "reduce.h"
@@ -308,9 +310,15 @@ struct FoldArgs {
     double* T;
     double* Rc;
     int* flag;
+    // pass D with XPT > 0: the next operator input (see OrthoArgs)
+    void* xp;
+    double* xsum;
+    const int32_t* grp;
+    const double* cs;
+    int h;
 };
 
-template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT, int CB = 0, bool SCALE = false>
+template <int BJ, bool GRAM, bool SYRK, int RT = kMaxRT, int CB = 0, bool SCALE = false, int XPT = 0>
 __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int64_t n, int coff, int kin, int yoff,
                                                           int b, int cv, const double* __restrict__ M,
                                                           double* __restrict__ part, const int* skip, double* Vout,
@@ -422,6 +430,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
     constexpr int NG = GRAM ? RT * BJ : 1;
     d4 accg[NG];
     d4 accs[BJ * BJ];
+    d4 accx[2] = {d4{0, 0, 0, 0}, d4{0, 0, 0, 0}};  // XPT: group sums, groups 0-15 and 16-31
 #pragma unroll
     for (int t = 0; t < NG; ++t) accg[t] = d4{0, 0, 0, 0};
 #pragma unroll
@@ -430,6 +439,18 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
     const int64_t wstride = (int64_t)gridDim.x * kOrWaves;
     for (int64_t tile = (int64_t)blockIdx.x * kOrWaves + (threadIdx.x >> 6); tile < ntiles; tile += wstride) {
         const int64_t row0 = tile * 16;
+        // XPT: groups and scales of the rows this lane feeds to the sums
+        [[maybe_unused]] int gq[4];
+        [[maybe_unused]] double cq[4];
+        if constexpr (XPT > 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = row0 + 4 * q + lk;
+                const int64_t rs = row < n ? row : 0;
+                gq[q] = row < n ? F.grp[rs] : -1;
+                cq[q] = F.cs ? F.cs[rs] : 1.0;
+            }
+        }
         // update: D[jt] (16 rows x 16 cols) = In(rows) M
         d4 D[BJ];
 #pragma unroll
@@ -477,6 +498,22 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
                 }
             }
         }
+        if constexpr (XPT > 0) {
+            // the operator's next input: the compact copy, and on the matrix
+            // cores S += C_tile^T X~_tile with C_tile[r][s] = c_r [g_r = s]
+            // (A operand: group li, row lk of the step; B operand: this
+            // lane's own output value, already in place)
+            using OT = typename std::conditional<XPT == 1, float, double>::type;
+            OT* xo = static_cast<OT*>(F.xp);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = row0 + 4 * q + lk;
+                const OT xv = (OT)D[0][q];
+                if (row < n && li < b) xo[row * b + li] = xv;
+                accx[0] = mfma(gq[q] == li ? cq[q] : 0.0, (double)xv, accx[0]);
+                if (F.h > 16) accx[1] = mfma(gq[q] == li + 16 ? cq[q] : 0.0, (double)xv, accx[1]);
+            }
+        }
         // Gram and Syrk from registers (rows past n hold zeros)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -519,6 +556,24 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
 #pragma unroll
                     for (int i2 = 0; i2 < BJ; ++i2) accs[i1 * BJ + i2] = mfma(D[i1][q], D[i2][q], accs[i1 * BJ + i2]);
             }
+        }
+    }
+    if constexpr (XPT > 0) {
+        // the waves' sum tiles in wave order, one partial per block
+        __shared__ double xs[kOrWaves][2 * 256];
+        const int wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xs[wv][t * 256 + (4 * r + lk) * 16 + li] = accx[t][r];
+        __syncthreads();
+        const int rowlen = xcd_row(gridDim.x), sl = xcd_slot(blockIdx.x, gridDim.x);
+        for (int o = threadIdx.x; o < F.h * b; o += kOrThreads) {
+            const int g = o / b, j = o - g * b;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < kOrWaves; ++w) sum += xs[w][g * 16 + j];
+            F.xsum[(size_t)o * rowlen + sl] = sum;
         }
     }
     if (GRAM || SYRK) {
@@ -768,19 +823,32 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
 }
 
 // Pass C (SYRK) or D with the finalisation before it folded in (CB = b <= 8).
+// xpt (pass D only): 1 or 2 also writes the operator's next input, its
+// compact copy in float or double and the group sums.
 template <bool SYRK>
 static void launch_fold(int b, dim3 g, size_t lds, hipStream_t s, double* V, int ld, int64_t n, int coff, int kin,
-                        int yoff, int cv, double* part, const int* skip, const FoldArgs& F) {
-#define SF_FOLD(BJV, CBV)                                                                                    \
-    k_pass_upd<BJV, false, SYRK, kMaxRT, CBV><<<g, kOrThreads, lds, s>>>(V, ld, n, coff, kin, yoff, b, cv,     \
-                                                                         nullptr, part, skip, V, ld, nullptr, \
-                                                                         nullptr, F)
+                        int yoff, int cv, double* part, const int* skip, const FoldArgs& F, int xpt = 0) {
+#define SF_FOLD(BJV, CBV, XP)                                                                                   \
+    k_pass_upd<BJV, false, SYRK, kMaxRT, CBV, false, XP><<<g, kOrThreads, lds, s>>>(                           \
+        V, ld, n, coff, kin, yoff, b, cv, nullptr, part, skip, V, ld, nullptr, nullptr, F)
+#define SF_FOLD_X(CBV)                     \
+    do {                                   \
+        if (SYRK || xpt == 0)              \
+            SF_FOLD(1, CBV, 0);            \
+        else if (xpt == 1)                 \
+            SF_FOLD(1, CBV, SYRK ? 0 : 1); \
+        else                               \
+            SF_FOLD(1, CBV, SYRK ? 0 : 2); \
+    } while (0)
     if (b == 4)
-        SF_FOLD(1, 4);
+        SF_FOLD_X(4);
     else
-        SF_FOLD(1, 8);
+        SF_FOLD_X(8);
+#undef SF_FOLD_X
 #undef SF_FOLD
 }
+
+int ortho_nblk(int64_t n) { return nblk_for(n); }
 
 int ortho_expand(const OrthoArgs& a) {
     const int b = a.b, cv = a.cv, BJ = b > 16 ? 2 : 1;
@@ -833,7 +901,18 @@ int ortho_expand(const OrthoArgs& a) {
         F.mode = 2;
         F.sumB = sumA;
         F.thresh = 0.25;
-        launch_fold<false>(b, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, cv, nullptr, a.flag, F);
+        int xpt = 0;
+        if (a.xp) {
+            if (!a.xsum || !a.grp || a.h < 2 || a.h > kMaxGroups)
+                return set_error(SFAIRSC_E_ARG, "internal: bad operator-input request h=%d", a.h);
+            F.xp = a.xp;
+            F.xsum = a.xsum;
+            F.grp = a.grp;
+            F.cs = a.cs;
+            F.h = a.h;
+            xpt = a.xp_float ? 1 : 2;
+        }
+        launch_fold<false>(b, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, cv, nullptr, a.flag, F, xpt);
         SF_HIP(hipGetLastError());
         return SFAIRSC_OK;
     }

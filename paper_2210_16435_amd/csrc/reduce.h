@@ -1,15 +1,18 @@
 // Deterministic reduction of per-block partial sums: out[e] = sum over
-// blocks b of part[b][e], in a fixed order (16 interleaved slices, each
-// split over four accumulators, combined in slice order).  Each workgroup covers 64 elements with 16 slices, so the
-// partials are read by ceil(O / 64) workgroups in parallel.
+// blocks b of part[b][e], in a fixed order (64 interleaved slices, each
+// split over four accumulators, combined in slice order).  Each workgroup
+// covers 16 elements with 64 slices, so the partials are read by
+// ceil(O / 16) workgroups in parallel and, with at most 256 partials, every
+// thread issues all of its loads at once: the kernel is one load latency
+// deep rather than four.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace sfairsc {
 
-constexpr int kRedElems = 64;
-constexpr int kRedSlices = 16;
+constexpr int kRedElems = 16;
+constexpr int kRedSlices = 64;
 
 template <int UNUSED = 0>
 __global__ __launch_bounds__(kRedElems * kRedSlices) void k_reduce_partials(const double* __restrict__ part,
