@@ -1057,8 +1057,8 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         out.converged = nconv == k;
         if (out.converged || restart + 1 >= max_restarts) return SFAIRSC_OK;
         if (p < 1 || p + b > S.ld || p > c) return set_error(SFAIRSC_E_HIP, "internal: restart keeps %d of %d", p, c);
-        // V <- [V Z[:, 0:p], V_next]; the kernel left Z[:, 0:p] in 32-column
-        // slices followed by the identity in S.Q, and all Ritz values in theta
+        // V <- [V Z[:, 0:p], V_next]; the kernel left the rotation's factor
+        // in S.Q (layout: rot_whole), and all Ritz values in theta
         SF_TRY(S.phase_mark(2, true));
         SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
         S.xp_ready = -1;

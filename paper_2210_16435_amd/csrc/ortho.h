@@ -64,6 +64,16 @@ int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double
 int ortho_product(double* V, int ld, int64_t n, int kin, const double* M, int b, double* Out, int ldo,
                   const double* rscale, hipStream_t s);
 
+// Layout of the thick-restart rotation's factor, which the Rayleigh-Ritz
+// kernel writes and ortho_rotate reads (c basis columns, p kept, block b):
+//  * rot_whole(c, b): M = [Z[:, 0:p] 0; 0 I_b] ((c + b) x (p + b)) in slices
+//    of 48 columns (slice t: (c + b) x wt row-major), one update per slice
+//    (while a slice fits 64 KB of LDS);
+//  * otherwise Z[:, 0:p] in slices of 32 columns (slice t: c x wt), then the
+//    b x b identity, which moves the next block in an update of its own
+//    (reading b columns rather than c + b for every slice).
+__host__ __device__ inline bool rot_whole(int c, int b) { return (c + b) * 48 * 8 <= 64 * 1024; }
+
 // Thick-restart rotation into a second basis buffer (see ortho.hip).
 int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
                  hipStream_t s);

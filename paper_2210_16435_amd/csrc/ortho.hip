@@ -804,6 +804,13 @@ static void launch_upd(int BJ, dim3 g, size_t lds, hipStream_t s, double* V, int
     } while (0)
     // the row-tile bound matters only for the Gram product
     const int rt = GRAM ? rt_bound(cv) : kMaxRT;
+    if constexpr (!GRAM && !SYRK) {
+        // up to 48 output columns (the restart rotation's slices)
+        if (BJ == 3) {
+            SF_PASS_U(3, kMaxRT);
+            return;
+        }
+    }
     if (BJ == 1) {
         if (rt == 4)
             SF_PASS_U(1, 4);
@@ -978,26 +985,38 @@ int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double
     return SFAIRSC_OK;
 }
 
-// Thick restart: Vout[:, 0:p] = V[:, 0:c] Q (Q: c x p row-major, device)
-// and Vout[:, p:p+b] = V[:, c:c+b].  Qchunks holds Q split into 32-column
-// slices (slice t: c x wt row-major, wt = min(32, p - 32 t)) followed by the
-// b x b identity.
-int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
+// Thick restart: Vout[:, 0:p] = V[:, 0:c] Z[:, 0:p] and Vout[:, p:p+b] =
+// V[:, c:c+b], with the factor laid out as rot_whole selects: one
+// matrix-core update per slice of the whole factor [Z 0; 0 I] (V read once
+// per slice), or per 32-column slice of Z plus one update that moves the
+// next block.
+int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Mchunks,
                  hipStream_t s) {
-    if (c % 4 != 0 || ld % 4 != 0 || c > kLdMax || p + b > ld)
-        return set_error(SFAIRSC_E_ARG, "internal: bad rotation shape c=%d p=%d", c, p);
+    if (c % 4 != 0 || b % 4 != 0 || ld % 4 != 0 || c + b > kLdMax || p + b > ld || c + b > ld)
+        return set_error(SFAIRSC_E_ARG, "internal: bad rotation shape c=%d p=%d b=%d", c, p, b);
     const int nblk = nblk_for(n);
-    const double* q = Qchunks;
-    for (int j0 = 0; j0 < p; j0 += 32) {
-        const int wt = std::min(32, p - j0);
-        const int BJ = wt > 16 ? 2 : 1;
-        const size_t lds = (size_t)c * BJ * 16 * sizeof(double);
-        launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, c, j0, wt, c, q, nullptr, nullptr, Vout, ld);
-        q += (size_t)c * wt;
+    const double* q = Mchunks;
+    if (rot_whole(c, b)) {
+        const int kin = c + b, pw = p + b;
+        for (int j0 = 0; j0 < pw; j0 += 48) {
+            const int wt = std::min(48, pw - j0);
+            const int BJ = (wt + 15) / 16;
+            const size_t lds = (size_t)kin * BJ * 16 * sizeof(double);
+            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, kin, j0, wt, kin, q, nullptr, nullptr, Vout, ld);
+            q += (size_t)kin * wt;
+        }
+    } else {
+        for (int j0 = 0; j0 < p; j0 += 32) {
+            const int wt = std::min(32, p - j0);
+            const int BJ = wt > 16 ? 2 : 1;
+            const size_t lds = (size_t)c * BJ * 16 * sizeof(double);
+            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, c, j0, wt, c, q, nullptr, nullptr, Vout, ld);
+            q += (size_t)c * wt;
+        }
+        const int BJ = b > 16 ? 2 : 1;
+        launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, c, b, p, b, c, q,
+                                 nullptr, nullptr, Vout, ld);
     }
-    const int BJ = b > 16 ? 2 : 1;
-    launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, c, b, p, b, c, q, nullptr,
-                             nullptr, Vout, ld);
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;
 }

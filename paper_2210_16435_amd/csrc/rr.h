@@ -38,7 +38,7 @@ struct RrArgs {
     double tol = 0.0, sigma = 0.0;
     // outputs
     double* theta = nullptr;  // [c] all eigenvalues, ascending
-    double* Qch = nullptr;    // mode 0: Z[:, 0:p] in 32-column slices, then the b x b identity
+    double* Qch = nullptr;    // mode 0: the restart rotation's factor (layout: rot_whole)
     double* Zk = nullptr;     // mode 0: Z[:, 0:k] row-major c x k (may be null)
     double* rec = nullptr;    // mode 0: rr_rec_doubles(k) (see above)
     double* Zout = nullptr;   // mode 1: Z[:, 0:m] row-major c x m

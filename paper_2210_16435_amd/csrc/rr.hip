@@ -861,16 +861,29 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
         }
         res_s[tid] = sqrt(ss);
     }
-    // Z[:, 0:p] in 32-column slices (slice s: c x wt row-major at c * 32 s)
-    for (int idx = tid; idx < c * p; idx += kRrT) {
-        const int j0 = (idx / (c * 32)) * 32;
-        const int wt = min(32, p - j0);
-        const int rem = idx - c * j0;
-        const int r = rem / wt, q = rem - r * wt;
-        a.Qch[idx] = Zs[(size_t)r * kRrLd + j0 + q];
+    // the rotation's factor in the layout rot_whole selects: the kept Ritz
+    // vectors, then the next block unchanged
+    if (rot_whole(c, b)) {
+        // M = [Z[:, 0:p] 0; 0 I_b] in 48-column slices ((c + b) x wt each)
+        const int kin = c + b, pw = p + b;
+        for (int idx = tid; idx < kin * pw; idx += kRrT) {
+            const int j0 = (idx / (kin * 48)) * 48;
+            const int wt = min(48, pw - j0);
+            const int rem = idx - kin * j0;
+            const int r = rem / wt, j = j0 + (rem - r * wt);
+            a.Qch[idx] = j < p ? (r < c ? Zs[(size_t)r * kRrLd + j] : 0.0) : (r - c == j - p ? 1.0 : 0.0);
+        }
+    } else {
+        // Z[:, 0:p] in 32-column slices (c x wt each), then the identity
+        for (int idx = tid; idx < c * p; idx += kRrT) {
+            const int j0 = (idx / (c * 32)) * 32;
+            const int wt = min(32, p - j0);
+            const int rem = idx - c * j0;
+            const int r = rem / wt, q = rem - r * wt;
+            a.Qch[idx] = Zs[(size_t)r * kRrLd + j0 + q];
+        }
+        for (int idx = tid; idx < b * b; idx += kRrT) a.Qch[(size_t)c * p + idx] = (idx / b == idx % b) ? 1.0 : 0.0;
     }
-    // then the b x b identity (the next block moves unchanged)
-    for (int idx = tid; idx < b * b; idx += kRrT) a.Qch[(size_t)c * p + idx] = (idx / b == idx % b) ? 1.0 : 0.0;
     if (a.Zk)
         for (int idx = tid; idx < c * k; idx += kRrT) {
             const int r = idx / k, q = idx - r * k;
