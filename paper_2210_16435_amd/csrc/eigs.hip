@@ -326,7 +326,9 @@ __global__ void k_zero_i32(int* __restrict__ X, int count) {
 }
 
 // T[0:p, 0:p] = diag(theta).
-__global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta) {
+__global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta,
+                           const int* skip) {
+    if (skip && *skip) return;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * p; idx += gridDim.x * blockDim.x) {
         int i = idx / p, j = idx - i * p;
         T[i * ldt + j] = i == j ? theta[i] : 0.0;
@@ -422,6 +424,10 @@ static int poll_wait(hipEvent_t e) {
         }
     }
 }
+
+// The word of the solver's flag array that gates a restart rotation
+// enqueued ahead of the Rayleigh-Ritz record (words 0-2: expansion failure).
+constexpr int kRotSkipWord = 4;
 
 struct Solver {
     sfairsc_graph* g;
@@ -806,7 +812,7 @@ struct Solver {
     // solve's stream; the second stream is released (ev_fork) for the
     // look-ahead operator application (op_ahead), which the solve's stream
     // joins (ev_join) before anything reads the results.
-    int rayleigh_ritz(int c, double tol, int keep_opt) {
+    int rayleigh_ritz(int c, double tol, int keep_opt, int p_pred) {
         EigWork& w = g->eig;
         // the second stream may start the look-ahead operator application
         // from here on; the Rayleigh-Ritz kernel goes first on the solve's
@@ -842,6 +848,8 @@ struct Solver {
         a.Qch = Q;
         a.Zk = rb.zk;
         a.rec = rb.rec;
+        a.rot_skip = flag + kRotSkipWord;
+        a.p_pred = p_pred;
         SF_TRY(rr_launch(a, s));
         if (timing) {
             SF_HIP(hipEventRecord(rr_evs[rr_ev_used + 1], s));
@@ -1022,13 +1030,36 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         // kept Ritz vectors), so its operator application runs on the solve's
         // stream meanwhile (wasted if this cycle converges).  Both skip their
         // work if the last expansion broke down (flag).
-        SF_TRY(S.rayleigh_ritz(c, tol, keep_opt));
+        // The kept count the kernel will choose unless equal eigenvalues
+        // extend it (rare): the restart for it is enqueued before the record
+        // is read, and runs only if the kernel confirms it (not converged,
+        // same count), so the GPU goes on while the host reads the record.
+        int p_pred = keep_opt > 0 ? keep_opt : std::max(k + b, k + (c - k) / 2);
+        p_pred = std::min(p_pred, ncv - b);
+        p_pred = std::max(p_pred, std::min(k, ncv - b));
+        p_pred = std::min((p_pred + 3) & ~3, ncv - b);
+        const bool spec = restart + 1 < max_restarts && p_pred >= 1 && p_pred <= c && p_pred + b <= S.ld;
+        SF_TRY(S.rayleigh_ritz(c, tol, keep_opt, spec ? p_pred : 0));
         SF_TRY(S.op_ahead(c, &pre));
         ahead = true;
         // the record carries the expansion's flag words too: one download
         SF_TRY(S.download(rec.data(), S.rb.rec, rec.size() * sizeof(double)));
-        SF_TRY(S.sync());
-        SF_TRY(S.harvest_timing());
+        SF_HIP(hipEventRecord(S.g->eig.ev_wait, S.s));
+        const int* rot_skip = S.flag + kRotSkipWord;
+        if (spec) {
+            SF_TRY(S.phase_mark(2, true));
+            SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p_pred, b, S.Q, S.s, rot_skip));
+            SF_TRY(S.phase_mark(2, false));
+            k_set_diag<<<grid_for((int64_t)p_pred * p_pred, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p_pred,
+                                                                                      S.rb.theta, rot_skip);
+            SF_HIP(hipGetLastError());
+        }
+        if (S.timing) {
+            SF_TRY(S.sync());  // every timing event complete before they are read
+            SF_TRY(S.harvest_timing());
+        } else {
+            SF_TRY(S.sync_to(S.g->eig.ev_wait));
+        }
         const int hflag[3] = {(int)rec[kRrRecFlag], (int)rec[kRrRecFlag + 1], (int)rec[kRrRecFlag + 2]};
         if (hflag[0]) {
             // everything after the failed expansion at hflag[1] was skipped
@@ -1058,14 +1089,17 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         if (out.converged || restart + 1 >= max_restarts) return SFAIRSC_OK;
         if (p < 1 || p + b > S.ld || p > c) return set_error(SFAIRSC_E_HIP, "internal: restart keeps %d of %d", p, c);
         // V <- [V Z[:, 0:p], V_next]; the kernel left the rotation's factor
-        // in S.Q (layout: rot_whole), and all Ritz values in theta
-        SF_TRY(S.phase_mark(2, true));
-        SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
+        // in S.Q (layout: rot_whole), and all Ritz values in theta.  Already
+        // enqueued above when p was predicted.
+        if (!(spec && p == p_pred)) {
+            SF_TRY(S.phase_mark(2, true));
+            SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
+            SF_TRY(S.phase_mark(2, false));
+            k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.rb.theta, nullptr);
+            SF_HIP(hipGetLastError());
+        }
         S.xp_ready = -1;
-        SF_TRY(S.phase_mark(2, false));
         std::swap(S.V, S.V2);
-        k_set_diag<<<grid_for((int64_t)p * p, 256, 1024), 256, 0, S.s>>>(S.T, S.ld, p, S.rb.theta);
-        SF_HIP(hipGetLastError());
         c = p;
     }
 }

@@ -74,8 +74,9 @@ int ortho_product(double* V, int ld, int64_t n, int kin, const double* M, int b,
 //    (reading b columns rather than c + b for every slice).
 __host__ __device__ inline bool rot_whole(int c, int b) { return (c + b) * 48 * 8 <= 64 * 1024; }
 
-// Thick-restart rotation into a second basis buffer (see ortho.hip).
+// Thick-restart rotation into a second basis buffer (see ortho.hip); every
+// launch returns at once while *skip is nonzero.
 int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Qchunks,
-                 hipStream_t s);
+                 hipStream_t s, const int* skip = nullptr);
 
 }  // namespace sfairsc

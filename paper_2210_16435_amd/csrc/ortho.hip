@@ -991,7 +991,7 @@ int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double
 // per slice), or per 32-column slice of Z plus one update that moves the
 // next block.
 int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b, const double* Mchunks,
-                 hipStream_t s) {
+                 hipStream_t s, const int* skip) {
     if (c % 4 != 0 || b % 4 != 0 || ld % 4 != 0 || c + b > kLdMax || p + b > ld || c + b > ld)
         return set_error(SFAIRSC_E_ARG, "internal: bad rotation shape c=%d p=%d b=%d", c, p, b);
     const int nblk = nblk_for(n);
@@ -1002,7 +1002,7 @@ int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b
             const int wt = std::min(48, pw - j0);
             const int BJ = (wt + 15) / 16;
             const size_t lds = (size_t)kin * BJ * 16 * sizeof(double);
-            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, kin, j0, wt, kin, q, nullptr, nullptr, Vout, ld);
+            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, kin, j0, wt, kin, q, nullptr, skip, Vout, ld);
             q += (size_t)kin * wt;
         }
     } else {
@@ -1010,12 +1010,12 @@ int ortho_rotate(double* V, double* Vout, int ld, int64_t n, int c, int p, int b
             const int wt = std::min(32, p - j0);
             const int BJ = wt > 16 ? 2 : 1;
             const size_t lds = (size_t)c * BJ * 16 * sizeof(double);
-            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, c, j0, wt, c, q, nullptr, nullptr, Vout, ld);
+            launch_upd<false, false>(BJ, nblk, lds, s, V, ld, n, 0, c, j0, wt, c, q, nullptr, skip, Vout, ld);
             q += (size_t)c * wt;
         }
         const int BJ = b > 16 ? 2 : 1;
         launch_upd<false, false>(BJ, nblk, (size_t)b * BJ * 16 * sizeof(double), s, V, ld, n, c, b, p, b, c, q,
-                                 nullptr, nullptr, Vout, ld);
+                                 nullptr, skip, Vout, ld);
     }
     SF_HIP(hipGetLastError());
     return SFAIRSC_OK;

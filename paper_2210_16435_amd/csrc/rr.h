@@ -42,6 +42,13 @@ struct RrArgs {
     double* Zk = nullptr;     // mode 0: Z[:, 0:k] row-major c x k (may be null)
     double* rec = nullptr;    // mode 0: rr_rec_doubles(k) (see above)
     double* Zout = nullptr;   // mode 1: Z[:, 0:m] row-major c x m
+    // mode 0, optional: the solver may enqueue the restart rotation for a
+    // predicted kept count p_pred before it reads the record; that work runs
+    // only while *rot_skip is 0.  The kernel sets it to 1 first (so that it
+    // stays 1 if the kernel skips or stops early) and at the end to 0 exactly
+    // when the cycle did not converge and p == p_pred.
+    int* rot_skip = nullptr;
+    int p_pred = 0;
 };
 
 size_t rr_work_doubles();

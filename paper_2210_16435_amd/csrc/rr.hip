@@ -209,6 +209,7 @@ __device__ int sturm_laguerre(const double2* __restrict__ de, int c, double x, d
 template <int NR, int NC>
 __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
     if (a.mode == 0 && a.rec && threadIdx.x < 3) a.rec[kRrRecFlag + threadIdx.x] = a.skip ? (double)a.skip[threadIdx.x] : 0.0;
+    if (a.mode == 0 && a.rot_skip && threadIdx.x == 0) *a.rot_skip = 1;
     if (a.skip && *a.skip) return;
     constexpr int NT = 4 * NC;  // rows per lane in the back-transformation
     __shared__ double vs[2][kRrMax];
@@ -896,6 +897,7 @@ __global__ __launch_bounds__(kRrT) void k_rr(RrArgs a) {
         a.rec[0] = (double)nconv;
         a.rec[1] = (double)p;
         a.rec[2] = (double)m;
+        if (a.rot_skip) *a.rot_skip = (nconv < k && p == a.p_pred) ? 0 : 1;
         a.rec[3] = c > k ? (ldexp(th[k], sexp) - ldexp(th[k - 1], sexp)) / a.sigma : 0.0;
     }
     for (int i = tid; i < k; i += kRrT) {
