@@ -134,6 +134,11 @@ REASSOC = [
     (1400, 12, 24, 5, False, 6, 32, "fp64"),
     (1100, 8, 25, 3, True, 4, 16, "mixed"),
     (1600, 10, 26, 5, True, 5, 4, "fp64"),
+    # many groups: the last orthogonalisation pass forms the operator's input
+    # group sums in two 16-group tiles (h > 16), up to the maximum of 32
+    (2000, 12, 27, 24, True, 5, 8, "fp64"),
+    (2000, 12, 28, 32, False, 4, 4, "fp64"),
+    (2000, 12, 29, 32, True, 5, 8, "mixed"),
 ]
 
 
@@ -223,6 +228,32 @@ def _fair_cliques(nc, per):
     W = sp.csr_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(n, n))
     W.sort_indices()
     return W, (np.arange(n) % 2).astype(np.int32)
+
+
+@pytest.mark.parametrize("normalized", [False, True])
+def test_many_equal_eigenvalues_across_restarts(normalized):
+    # 24 disjoint fair cliques of 12: the fair eigenvalue 0 has multiplicity 24
+    # and every clique contributes the same nonzero eigenvalues, so Ritz
+    # values coincide in large clusters; a restart may then keep more vectors
+    # than the rule's count (the cluster is not split), which the solver
+    # learns only from the Rayleigh-Ritz record.  k = 24 takes the whole zero
+    # eigenspace.
+    sf = lib()
+    nc, per = 24, 12
+    W, groups = _fair_cliques(nc, per)
+    G = sf.Graph(W.indptr.astype(np.int32), W.indices.astype(np.int32), W.data, groups, 2, normalized)
+    r = G.eigs(nc, tol=1e-10, block_width=8, max_basis=96)
+    log(f"  info {r.info}")
+    assert r.status == sf.OK
+    assert np.all(np.abs(r.eigenvalues) < 1e-8 * G.sigma)
+    H = to_np(r.H)
+    d = np.asarray(W.sum(1)).ravel()
+    M = H.T @ (d[:, None] * H) if normalized else H.T @ H
+    assert np.abs(M - np.eye(nc)).max() < 1e-9
+    ind = np.kron(np.eye(nc), np.ones((per, 1)))
+    assert oracle.max_principal_angle(H, ind, d if normalized else None) < 1e-6
+    res = oracle.residual_norms(W, groups, 2, normalized, r.eigenvalues, H)
+    assert res.max() <= 1e-10 * G.sigma + 2e-12 * G.sigma
 
 
 @pytest.mark.parametrize("normalized", [False, True])
