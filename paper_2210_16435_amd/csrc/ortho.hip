@@ -79,7 +79,8 @@ __device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, doub
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
+    if (out)
+        for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
 }
 
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
@@ -310,6 +311,10 @@ struct FoldArgs {
     double* T;
     double* Rc;
     int* flag;
+    // mode 2 with gpart: G2 not yet reduced; the per-block partials (B x B
+    // row-major each, gnblk blocks) are summed here by every workgroup
+    const double* gpart;
+    int gnblk;
     // pass D with XPT > 0: the next operator input (see OrthoArgs)
     void* xp;
     double* xsum;
@@ -336,12 +341,40 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
         const double* H2 = F.sumB;
         const double* gt = F.mode == 1 ? F.sumB + (size_t)nrtf * F.BJ * 256 : F.sumB;
         const bool w0 = blockIdx.x == 0;
+        // mode 2 from the partials: every thread sums a fixed slice of the
+        // blocks for one entry (eight loads in flight), the slices then in
+        // order, so that every workgroup forms the same G2
+        constexpr int NSL = kOrThreads / (B * B);
+        __shared__ double gsl[NSL][B * B];
+        if (F.gpart) {
+            const int v = threadIdx.x % (B * B), q = threadIdx.x / (B * B);
+            double acc = 0.0;
+            int blk = q;
+            for (; blk + 7 * NSL < F.gnblk; blk += 8 * NSL) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = F.gpart[(size_t)(blk + u * NSL) * (B * B) + v];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += x[u];
+            }
+            for (; blk < F.gnblk; blk += NSL) acc += F.gpart[(size_t)blk * (B * B) + v];
+            gsl[q][v] = acc;
+            __syncthreads();
+        }
         if (threadIdx.x < 64) {
             const int j = threadIdx.x;
             double g[B], ri[B];
 #pragma unroll
             for (int i = 0; i < B; ++i) {
-                g[i] = j < B ? tile_at(gt, F.BJ, i, j) : 0.0;
+                double gv = 0.0;
+                if (j < B) {
+                    if (F.gpart) {
+                        for (int q = 0; q < NSL; ++q) gv += gsl[q][i * B + j];
+                    } else {
+                        gv = tile_at(gt, F.BJ, i, j);
+                    }
+                }
+                g[i] = gv;
                 ri[i] = 0.0;
                 if (w0 && j < B) F.Gsave[i * B + j] = g[i];
             }
@@ -576,7 +609,14 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
             F.xsum[(size_t)o * rowlen + sl] = sum;
         }
     }
-    if (GRAM || SYRK) {
+    if constexpr (CB > 0 && SYRK && !GRAM) {
+        // the folded pass C: its block's B x B Gram, row-major, for the next
+        // pass to sum (no separate reduction)
+        __syncthreads();
+        block_store_tiles(accs, 1, lds, nullptr);
+        for (int e = threadIdx.x; e < CB * CB; e += kOrThreads)
+            part[(size_t)blockIdx.x * (CB * CB) + e] = tile_at(lds, 1, e / CB, e % CB);
+    } else if (GRAM || SYRK) {
         __syncthreads();  // Ms no longer needed: reuse LDS for the block sums
         const size_t gsz = (size_t)nrt * BJ * 256;
         if (GRAM) block_store_tiles(accg, nrt * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256));
@@ -903,10 +943,12 @@ int ortho_expand(const OrthoArgs& a) {
         // then Y1 = [V | Y'] M2 and its Syrk
         FoldArgs F{1, sumA, sumB, BJ, cv, cact, a.ldt, a.thresh, R1, a.gsave, a.T, a.rc, a.flag};
         launch_fold<true>(b, nblk, ldsC, s, a.V, a.ld, n, 0, kin, cv, cv, a.part, a.flag, F);
-        k_reduce_partials<<<reduce_grid(OC), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OC, sumA, a.flag);
-        // pass D: R2 = chol(G2), the coupling R2 R1 (folded in), Y2 = Y1 R2^{-1}
+        // pass D: G2 summed from pass C's block partials, R2 = chol(G2), the
+        // coupling R2 R1 (folded in), Y2 = Y1 R2^{-1}
         F.mode = 2;
-        F.sumB = sumA;
+        F.sumB = nullptr;
+        F.gpart = a.part;
+        F.gnblk = nblk;
         F.thresh = 0.25;
         int xpt = 0;
         if (a.xp) {
