@@ -277,10 +277,10 @@ typedef struct sfairsc_eigs_info {
     double phase1_ms;          /* mixed precision: host wall time of the
                                   FP32-SpMM phase; 0 otherwise             */
     double rr_ms;              /* time_kernels: GPU time of the Rayleigh-
-                                  Ritz kernels (small dense eigensolves on
-                                  a second stream, beside the look-ahead
-                                  operator application), all phases; 0
-                                  otherwise                                 */
+                                  Ritz kernels (small dense eigensolves,
+                                  with the look-ahead operator application
+                                  beside them on a second stream), all
+                                  phases; 0 otherwise                       */
     /* time_kernels: summed GPU time between event pairs around the block
        steps' operator applications (projections, sparse product, C^T T),
        their orthogonalisation (CGS2 + Cholesky-QR) and the restart
@@ -288,7 +288,9 @@ typedef struct sfairsc_eigs_info {
     double operator_ms, ortho_ms, restart_ms;
     int32_t degenerate;        /* 1: gap_ratio <= 100 tol (the status is then
                                   SFAIRSC_E_DEGENERATE unless not converged) */
-    int32_t reserved;
+    int32_t restarts_unpredicted; /* restarts whose kept count the rule did
+                                  not give (equal Ritz values extended it):
+                                  their rotation waited for the host         */
 } sfairsc_eigs_info;
 
 /* Fill *opts with the defaults (all automatic, seed 0, certify 1). */

@@ -93,7 +93,7 @@ class EigsInfo(ctypes.Structure):
         ("ortho_ms", ctypes.c_double),
         ("restart_ms", ctypes.c_double),
         ("degenerate", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("restarts_unpredicted", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -114,6 +114,7 @@ class EigsInfo(ctypes.Structure):
             "ortho_ms": self.ortho_ms,
             "restart_ms": self.restart_ms,
             "degenerate": self.degenerate,
+            "restarts_unpredicted": self.restarts_unpredicted,
         }
 
 

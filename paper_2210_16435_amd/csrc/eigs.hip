@@ -1092,6 +1092,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
         // in S.Q (layout: rot_whole), and all Ritz values in theta.  Already
         // enqueued above when p was predicted.
         if (!(spec && p == p_pred)) {
+            if (spec && S.info) S.info->restarts_unpredicted += 1;
             SF_TRY(S.phase_mark(2, true));
             SF_TRY(ortho_rotate(S.V, S.V2, S.ld, n, c, p, b, S.Q, S.s));
             SF_TRY(S.phase_mark(2, false));

@@ -245,6 +245,7 @@ def test_many_equal_eigenvalues_across_restarts(normalized):
     r = G.eigs(nc, tol=1e-10, block_width=8, max_basis=96)
     log(f"  info {r.info}")
     assert r.status == sf.OK
+    assert 0 <= r.info["restarts_unpredicted"] < r.info["restarts"]
     assert np.all(np.abs(r.eigenvalues) < 1e-8 * G.sigma)
     H = to_np(r.H)
     d = np.asarray(W.sum(1)).ravel()

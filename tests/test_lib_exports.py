@@ -58,7 +58,7 @@ def test_struct_layouts_match_header(tmp_path):
         "sfairsc_eigs_opts": (L.EigsOpts, ["seed", "sigma", "x0", "b0"]),
         "sfairsc_graph_stats": (L.GraphStats, ["sigma", "max_degree"]),
         "sfairsc_eigs_info": (L.EigsInfo, ["operator_applies", "spmm_ms", "max_rel_residual", "phase1_ms", "rr_ms",
-                                            "operator_ms", "restart_ms"]),
+                                            "operator_ms", "restart_ms", "degenerate", "restarts_unpredicted"]),
         "sfairsc_batch_info": (L.BatchInfo, ["batch_status", "double_spmm", "converged", "max_rel_residual",
                                              "graph_ms", "batch_ms", "phase_ms"]),
     }
