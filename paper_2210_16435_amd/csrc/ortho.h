@@ -42,7 +42,8 @@ struct OrthoArgs {
     int h = 0;
 };
 
-// Workgroups of the expansion's passes (the blocks of xsum).
+// Workgroups of the expansion's last pass when it writes the operator's
+// input (the blocks of xsum).
 int ortho_nblk(int64_t n);
 
 size_t ortho_part_doubles(int64_t n);

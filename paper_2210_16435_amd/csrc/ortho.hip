@@ -895,7 +895,9 @@ static void launch_fold(int b, dim3 g, size_t lds, hipStream_t s, double* V, int
 #undef SF_FOLD
 }
 
-int ortho_nblk(int64_t n) { return nblk_for(n); }
+// (a multiple of 8, so that every slot of the output-major sums is written:
+// their reader then keeps eight loads in flight)
+int ortho_nblk(int64_t n) { return (nblk_for(n) + 7) & ~7; }
 
 int ortho_expand(const OrthoArgs& a) {
     const int b = a.b, cv = a.cv, BJ = b > 16 ? 2 : 1;
@@ -961,7 +963,8 @@ int ortho_expand(const OrthoArgs& a) {
             F.h = a.h;
             xpt = a.xp_float ? 1 : 2;
         }
-        launch_fold<false>(b, nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, cv, nullptr, a.flag, F, xpt);
+        launch_fold<false>(b, xpt ? ortho_nblk(n) : nblk, ldsD, s, a.V, a.ld, n, cv, b, cv, cv, nullptr, a.flag, F,
+                           xpt);
         SF_HIP(hipGetLastError());
         return SFAIRSC_OK;
     }
