@@ -386,6 +386,47 @@ __global__ __launch_bounds__(256) void k_col_stats(const double* __restrict__ X,
     }
 }
 
+// Sign convention of the output: per column the entry of largest magnitude
+// (after the row scale) made positive, ties to the smallest row.  Block j
+// combines column j's per-block maxima of k_col_stats by that rule (the
+// result does not depend on the order) and writes sgn[j] = -1 when the
+// entry is negative, else 1.
+__global__ __launch_bounds__(256) void k_sign_pick(const double* __restrict__ part,
+                                                    const int64_t* __restrict__ imax, int nb, int k, int64_t n,
+                                                    const double* __restrict__ X, double* __restrict__ sgn) {
+    __shared__ double mx[256];
+    __shared__ int64_t mi[256];
+    const int j = blockIdx.x, t = threadIdx.x;
+    double m = -1.0;
+    int64_t at = INT64_MAX;
+    for (int blk = t; blk < nb; blk += 256) {
+        const double m2 = part[(size_t)blk * 2 * k + k + j];
+        const int64_t i2 = imax[(size_t)blk * k + j];
+        if (m2 > m || (m2 == m && i2 < at)) {
+            m = m2;
+            at = i2;
+        }
+    }
+    mx[t] = m;
+    mi[t] = at;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            const double m2 = mx[t + w];
+            const int64_t i2 = mi[t + w];
+            if (m2 > mx[t] || (m2 == mx[t] && i2 < mi[t])) {
+                mx[t] = m2;
+                mi[t] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const int64_t r = mi[0];
+        sgn[j] = (r >= 0 && r < n && X[r * k + j] < 0.0) ? -1.0 : 1.0;
+    }
+}
+
 // Column-major output H[:, j] = sign_j * scale_i * X[:, j] (row-major X, ld).
 __global__ void k_write_out(const double* __restrict__ X, int ld, int64_t n, int k, const double* __restrict__ sgn,
                             const double* __restrict__ scale, double* __restrict__ H) {
@@ -1116,30 +1157,41 @@ static int ritz_vectors(Solver& S, const KsResult& R, double* Xo, const double* 
     return SFAIRSC_OK;
 }
 
-// FP64 residual norms ||L^sigma x_i - theta_i x_i|| of row-major X (n x k).
-static int certify(Solver& S, const double* X, double* Ybuf, const std::vector<double>& theta,
-                   std::vector<double>& res) {
+// FP64 residual norms ||L^sigma x_i - theta_i x_i|| of row-major X (n x k),
+// theta the last Rayleigh-Ritz step's (read from its record on the device).
+// certify_enqueue leaves the per-block sums of squares staged for the next
+// sync; certify_finish adds them up.
+static int certify_enqueue(Solver& S, const double* X, double* Ybuf, std::vector<double>& part) {
     const int k = S.k;
     const bool was_mixed = S.mixed;
     S.mixed = false;
-    int zero = 0;
-    SF_TRY(S.upload(S.flag, &zero, sizeof(int)));
+    k_zero_i32<<<1, 64, 0, S.s>>>(S.flag, 1);
     for (int j0 = 0; j0 < k; j0 += kMaxBlock) {
         int bb = std::min(kMaxBlock, k - j0);
         SF_TRY(op_apply(S.g, X + j0, k, Ybuf + j0, k, bb, 0, S.sigma, S.s, nullptr, nullptr, nullptr));
     }
     S.mixed = was_mixed;
-    SF_TRY(S.upload(S.theta, theta.data(), k * sizeof(double)));
     const int nb = grid_for(S.n, 256, kStatBlocks);
-    k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.theta, S.stats, S.imax, nullptr);
+    k_col_stats<<<nb, 256, 0, S.s>>>(X, Ybuf, k, S.n, k, S.rb.rec + kRrRecHead, S.stats, S.imax, nullptr);
     SF_HIP(hipGetLastError());
-    std::vector<double> part((size_t)nb * 2 * k);
-    SF_TRY(S.download(part.data(), S.stats, part.size() * sizeof(double)));
-    SF_TRY(S.sync());
+    part.assign((size_t)nb * 2 * k, 0.0);
+    return S.download(part.data(), S.stats, part.size() * sizeof(double));
+}
+
+static void certify_finish(const Solver& S, const std::vector<double>& part, std::vector<double>& res) {
+    const int k = S.k;
+    const int nb = (int)(part.size() / (2 * (size_t)k));
     res.assign(k, 0.0);
     for (int blk = 0; blk < nb; ++blk)
         for (int j = 0; j < k; ++j) res[j] += part[(size_t)blk * 2 * k + j];
     for (int j = 0; j < k; ++j) res[j] = std::sqrt(res[j]);
+}
+
+static int certify(Solver& S, const double* X, double* Ybuf, std::vector<double>& res) {
+    std::vector<double> part;
+    SF_TRY(certify_enqueue(S, X, Ybuf, part));
+    SF_TRY(S.sync());
+    certify_finish(S, part, res);
     return SFAIRSC_OK;
 }
 
@@ -1191,8 +1243,7 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
         const double tol1 = std::max(tol, kMixedTol1);
         SF_TRY(run_ks(S, tol1, max_restarts, o.keep, o.x0, o.b0, o.seed, R));
         SF_TRY(ritz_vectors(S, R, Xr, nullptr));
-        std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
-        SF_TRY(certify(S, Xr, Yr, th, res));
+        SF_TRY(certify(S, Xr, Yr, res));
         if (info) info->phase1_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ok = true;
         for (int i = 0; i < k; ++i) ok = ok && res[i] <= tol * S.sigma;
@@ -1230,52 +1281,29 @@ static int eigs_impl(sfairsc_graph* g, int k, double tol, int precision, const s
     // vectors so the returned H satisfies F^T H = 0 to rounding.
     for (int j0 = 0; j0 < k; j0 += kMaxBlock) SF_TRY(op_project(g, Xr + j0, k, std::min(kMaxBlock, k - j0), s));
     std::vector<double> th(R.theta.begin(), R.theta.begin() + k);
-    if (o.certify || precision == SFAIRSC_PREC_MIXED) {
-        SF_TRY(certify(S, Xr, Yr, th, res));
-    } else {
+    // certification and output in one pass of device work, one sync at the
+    // end: the residual sums are staged, the signs chosen on the device
+    const bool cert = o.certify || precision == SFAIRSC_PREC_MIXED;
+    std::vector<double> cpart;
+    if (cert) SF_TRY(certify_enqueue(S, Xr, Yr, cpart));
+    // sign convention on H = D^{-1/2} X (normalized) or X: the entry of
+    // largest magnitude of each column is made positive
+    const int nb = grid_for(n, 256, kStatBlocks);
+    k_col_stats<<<nb, 256, 0, s>>>(Xr, nullptr, k, n, k, nullptr, S.stats, S.imax, scale);
+    k_sign_pick<<<k, 256, 0, s>>>(S.stats, S.imax, nb, k, n, Xr, S.theta);
+    k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, scale, H);
+    SF_HIP(hipGetLastError());
+    SF_TRY(S.sync());
+    if (cert)
+        certify_finish(S, cpart, res);
+    else
         res.assign(R.res.begin(), R.res.begin() + k);
-    }
     double worst = 0.0;
     int nconv = 0;
     for (int i = 0; i < k; ++i) {
         worst = std::max(worst, res[i] / S.sigma);
         if (res[i] <= tol * S.sigma) ++nconv;
     }
-    // sign convention on H = D^{-1/2} X (normalized) or X: the entry of
-    // largest magnitude of each column is made positive
-    const int nb = grid_for(n, 256, kStatBlocks);
-    k_col_stats<<<nb, 256, 0, s>>>(Xr, nullptr, k, n, k, nullptr, S.stats, S.imax, scale);
-    SF_HIP(hipGetLastError());
-    std::vector<double> part((size_t)nb * 2 * k);
-    std::vector<int64_t> pidx((size_t)nb * k);
-    SF_TRY(S.download(part.data(), S.stats, part.size() * sizeof(double)));
-    SF_TRY(S.download(pidx.data(), S.imax, pidx.size() * sizeof(int64_t)));
-    SF_TRY(S.sync());
-    std::vector<double> sgn(k, 1.0);
-    std::vector<double> hx(k, 0.0);
-    std::vector<int64_t> at_row(k, -1);
-    for (int j = 0; j < k; ++j) {
-        double m = -1.0;
-        int64_t at = INT64_MAX;
-        for (int blk = 0; blk < nb; ++blk) {
-            double m2 = part[(size_t)blk * 2 * k + k + j];
-            int64_t i2 = pidx[(size_t)blk * k + j];
-            if (m2 > m || (m2 == m && i2 < at)) {
-                m = m2;
-                at = i2;
-            }
-        }
-        if (at >= 0 && at < n) {
-            at_row[j] = at;
-            SF_TRY(S.download(&hx[j], Xr + at * k + j, sizeof(double)));
-        }
-    }
-    SF_TRY(S.sync());
-    for (int j = 0; j < k; ++j) sgn[j] = (at_row[j] >= 0 && hx[j] < 0) ? -1.0 : 1.0;
-    SF_TRY(S.upload(S.theta, sgn.data(), k * sizeof(double)));
-    k_write_out<<<grid_for(n * k, 256, 8192), 256, 0, s>>>(Xr, k, n, k, S.theta, scale, H);
-    SF_HIP(hipGetLastError());
-    SF_TRY(S.sync());
     for (int i = 0; i < k; ++i) eigvals[i] = th[i];
     // The wanted subspace is well defined only with a gap after theta_k
     // (Proposition 3.3 and the angle bound need lambda_k < lambda_{k+1}):
