@@ -326,12 +326,13 @@ __global__ void k_zero_i32(int* __restrict__ X, int count) {
 }
 
 // T[0:p, 0:p] = diag(theta).
+// T[0:p, 0:p] = diag(theta) (the identity when theta is null).
 __global__ void k_set_diag(double* __restrict__ T, int ldt, int p, const double* __restrict__ theta,
                            const int* skip) {
     if (skip && *skip) return;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < p * p; idx += gridDim.x * blockDim.x) {
         int i = idx / p, j = idx - i * p;
-        T[i * ldt + j] = i == j ? theta[i] : 0.0;
+        T[i * ldt + j] = i == j ? (theta ? theta[i] : 1.0) : 0.0;
     }
 }
 
@@ -679,9 +680,8 @@ struct Solver {
     const double* identity() {
         if (!ident) {
             ident = Q + (size_t)kLdMax * kLdMax - kMaxBlock * kMaxBlock;  // tail of Q, never used by rotations here
-            std::vector<double> I(b * b, 0.0);
-            for (int i = 0; i < b; ++i) I[i * b + i] = 1.0;
-            if (upload(ident, I.data(), b * b * sizeof(double)) != SFAIRSC_OK) return nullptr;
+            k_set_diag<<<1, 256, 0, s>>>(ident, b, b, nullptr, nullptr);  // written on the device, no transfer
+            if (hipGetLastError() != hipSuccess) return nullptr;
         }
         return ident;
     }
@@ -1041,14 +1041,11 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
     SF_HIP(hipGetLastError());
     // A random start vector is not orthogonal to range(C) or to the trivial
     // vector: harmless, the operator treats every direction exactly.
+    // A rank-deficient start block sets the flag words (column -1): every
+    // kernel after it skips its work and the first Rayleigh-Ritz record
+    // reports it, so the expansions are enqueued without waiting here.
     SF_TRY(ortho_start(S.V, S.ld, n, b, S.identity(), S.thresh, S.g->eig.opart.as<double>(),
                        S.g->eig.osmall.as<double>(), S.Gsave, S.Rc, S.flag, S.s));
-    {
-        int hflag[2];
-        SF_TRY(S.download(hflag, S.flag, 2 * sizeof(int)));
-        SF_TRY(S.sync());
-        if (hflag[0]) return set_error(SFAIRSC_E_ARG, "start block is rank deficient");
-    }
     int repairs = 0;
     std::vector<double> rec(rr_rec_doubles(k));
     // operator output computed ahead, during the previous Rayleigh-Ritz step
@@ -1102,6 +1099,7 @@ static int run_ks(Solver& S, double tol, int max_restarts, int keep_opt, const d
             SF_TRY(S.sync_to(S.g->eig.ev_wait));
         }
         const int hflag[3] = {(int)rec[kRrRecFlag], (int)rec[kRrRecFlag + 1], (int)rec[kRrRecFlag + 2]};
+        if (hflag[0] && hflag[1] < 0) return set_error(SFAIRSC_E_ARG, "start block is rank deficient");
         if (hflag[0]) {
             // everything after the failed expansion at hflag[1] was skipped
             const int cact = hflag[1];

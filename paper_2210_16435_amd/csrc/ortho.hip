@@ -992,7 +992,8 @@ int ortho_expand(const OrthoArgs& a) {
 // Start block: Cholesky-QR twice of V[:, 0:b] in place on the matrix
 // cores (Syrk pass, Cholesky, update + Syrk, Cholesky, update).  ident is
 // the b x b identity, R1 receives the first factor (its pivot test uses
-// thresh), flag[0] = 1 if either factorisation fails.
+// thresh), flag[0] = 1 and flag[1] = -1 (no expansion's column) if either
+// factorisation fails.
 int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double thresh, double* part, double* small,
                 double* gsave, double* rc, int* flag, hipStream_t s) {
     const int BJ = b > 16 ? 2 : 1;
@@ -1004,7 +1005,7 @@ int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double
     const int OS = BJ * BJ * 256;
     const size_t lds = std::max((size_t)b * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
 #define SF_FINC(BB, R1IN, MOUT, TH)                                                                            \
-    k_fin_c<BB><<<1, 256, 0, s>>>(sumA, BJ, R1IN, MOUT, rc, gsave, 0, flag, flag, TH)
+    k_fin_c<BB><<<1, 256, 0, s>>>(sumA, BJ, R1IN, MOUT, rc, gsave, -1, flag, flag, TH)
 #define SF_FINC_B(R1IN, MOUT, TH)                \
     switch (b) {                                 \
         case 4: SF_FINC(4, R1IN, MOUT, TH); break;   \

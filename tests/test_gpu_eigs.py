@@ -298,6 +298,23 @@ def test_degenerate_status_in_a_batch():
     assert [r.status for r in rs] == [sf.E_DEGENERATE, sf.OK, sf.OK], [r.info for r in rs]
 
 
+def test_rank_deficient_start_block_is_reported():
+    # a warm start whose two columns coincide: the start block's Cholesky-QR
+    # fails; the solver learns it from the first Rayleigh-Ritz record (every
+    # kernel in between skips its work) and reports E_ARG
+    sf = lib()
+    g = random_sparse_graph(1200, 10, seed=31, h=3)
+    G = sf.Graph.from_msbm(g, False)
+    v = torch.from_numpy(np.random.default_rng(4).standard_normal((g.n, 1)))
+    with pytest.raises(sf.SfairscError) as e:
+        G.eigs(4, tol=1e-8, x0=torch.cat([v, v], dim=1))
+    assert e.value.code == sf.E_ARG and "rank deficient" in str(e.value)
+    # the handle is still good: a valid warm start and a plain solve
+    r = G.eigs(4, tol=1e-8, x0=torch.cat([v, 2 * v + 1], dim=1))
+    r2 = G.eigs(4, tol=1e-8)
+    assert np.abs(r.eigenvalues - r2.eigenvalues).max() <= 1e-8 * G.sigma
+
+
 def test_not_converged_returns_partial_result():
     sf = lib()
     g = workload("msbm-2k-h2")
