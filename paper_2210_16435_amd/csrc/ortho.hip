@@ -765,8 +765,13 @@ __global__ __launch_bounds__(256) void k_fin_c(const double* __restrict__ sumC, 
 // ---------------------------------------------------------------------------
 // host side
 
+// One 16-row tile per wavefront, at most 256 blocks of 512 threads (a
+// block's partial tiles are reduced afterwards in a fixed order).  The Gram
+// passes hold ~200 registers per lane, so a compute unit takes one block:
+// fewer than 256 blocks leave compute units idle (two tiles per wavefront
+// gave 196 blocks at n = 50,000 and a 0.7% slower solve).
 #ifndef SF_ORTHO_TILES_PER_WAVE
-#define SF_ORTHO_TILES_PER_WAVE 2
+#define SF_ORTHO_TILES_PER_WAVE 1
 #endif
 #ifndef SF_ORTHO_MAX_BLOCKS
 #define SF_ORTHO_MAX_BLOCKS 256
