@@ -358,6 +358,33 @@ __global__ void k_relabel(const int32_t* __restrict__ lab, int64_t n, const int3
         out[i] = map[lab[i]];
 }
 
+// The first k-means++ pick of a restart (drawn on the host).
+__global__ void k_set_index(int64_t* __restrict__ idx, int64_t v) { *idx = v; }
+
+// The restart's inertia: the per-block partial sums of k_sum added in block
+// order by one thread (the order the host used); kst[0] holds the best
+// inertia so far (+inf before the first restart), kst[1] is set to 1 when
+// this restart is strictly better (ties keep the earliest), else 0.
+__global__ void k_inertia_pick(const double* __restrict__ part, int nb, double* __restrict__ kst) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    const bool better = s < kst[0];
+    if (better) kst[0] = s;
+    kst[1] = better ? 1.0 : 0.0;
+}
+
+__global__ void k_copy_if(const double* __restrict__ flag, const int32_t* __restrict__ src, int64_t n,
+                          int32_t* __restrict__ dst) {
+    if (flag[1] == 0.0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_set_inf(double* __restrict__ kst) {
+    kst[0] = INFINITY;
+    kst[1] = 0.0;
+}
+
 static int grid_n(int64_t n, int cap) {
     int64_t g = (n + kKmThreads - 1) / kKmThreads;
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
@@ -384,13 +411,13 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     int32_t* best = w.best.as<int32_t>();
     double* part = w.part.as<double>();
     int64_t* idxp = reinterpret_cast<int64_t*>(w.misc.p);
-    int* state = reinterpret_cast<int*>(idxp + 8);
+    double* kst = reinterpret_cast<double*>(idxp + 8);  // best inertia, improved flag
+    int* state = reinterpret_cast<int*>(kst + 8);
     int* changed_part = state + 8;
     int* cpart = changed_part + nb;
     const size_t sum_lds = (size_t)(kKmThreads / 64) * K * (kdim + 1) * sizeof(double);
 
-    double best_inertia = INFINITY;
-    std::vector<double> ipart(nb);
+    k_set_inf<<<1, 1, 0, s>>>(kst);
     for (int r = 0; r < R; ++r) {
         // k-means++ seeding
         for (int t = 0; t < K; ++t) {
@@ -398,8 +425,7 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
             if (t == 0) {
                 int64_t i0 = (int64_t)(u * (double)n);
                 if (i0 >= n) i0 = n - 1;
-                SF_HIP(hipMemcpyAsync(idxp, &i0, sizeof(int64_t), hipMemcpyHostToDevice, s));
-                SF_HIP(hipStreamSynchronize(s));
+                k_set_index<<<1, 1, 0, s>>>(idxp, i0);
             } else {
                 k_chunk_sums<<<nchunks, kKmThreads, 0, s>>>(d2, n, csum);
                 k_pp_pick<<<1, 64, 0, s>>>(d2, csum, nchunks, n, u, idxp);
@@ -423,17 +449,14 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
             SF_HIP(hipStreamSynchronize(s));
             if (hstate[0]) break;
         }
+        // the best restart so far kept on the device (no host round trip)
         k_sum<<<nb, kKmThreads, 0, s>>>(d2, n, csum);
+        k_inertia_pick<<<1, 1, 0, s>>>(csum, nb, kst);
+        k_copy_if<<<grid_n(n, 2048), kKmThreads, 0, s>>>(kst, lab, n, best);
         SF_HIP(hipGetLastError());
-        SF_HIP(hipMemcpyAsync(ipart.data(), csum, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-        SF_HIP(hipStreamSynchronize(s));
-        double inertia = 0.0;
-        for (int b = 0; b < nb; ++b) inertia += ipart[b];
-        if (inertia < best_inertia) {
-            best_inertia = inertia;
-            SF_HIP(hipMemcpyAsync(best, lab, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        }
     }
+    double best_inertia = INFINITY;
+    SF_HIP(hipMemcpyAsync(&best_inertia, kst, sizeof(double), hipMemcpyDeviceToHost, s));
     // renumber by first appearance
     long long* first = reinterpret_cast<long long*>(part);
     std::vector<long long> hfirst(K, (long long)INT64_MAX);
