@@ -29,13 +29,13 @@ constexpr int kKmThreads = 256;
 constexpr int kKmMaxBlocks = 1024;
 constexpr int kChunk = 1024;  // rows per prefix-sum chunk in the seeding
 
-uint64_t sm_mix(uint64_t z) {
+__host__ __device__ inline uint64_t sm_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
 
-double sm_uniform(uint64_t seed, uint64_t restart, uint64_t draw) {
+__host__ __device__ inline double sm_uniform(uint64_t seed, uint64_t restart, uint64_t draw) {
     const uint64_t idx = (restart << 32) + draw + 1;
     const uint64_t z = sm_mix(seed + idx * 0x9E3779B97F4A7C15ull);
     return (double)(z >> 11) * (1.0 / 9007199254740992.0);
@@ -44,11 +44,17 @@ double sm_uniform(uint64_t seed, uint64_t restart, uint64_t draw) {
 }  // namespace
 
 // cent[t] = H[idx]; d2 = (t == 0) ? dist : min(d2, dist) to that centre.
-__global__ __launch_bounds__(kKmThreads) void k_pp_update(const double* __restrict__ H, int64_t n, int kdim,
+// All restarts at once: restart r = blockIdx.y works on its own slices
+// (idxp[r], cent + r K kdim, d2 + r n); the same holds for every kernel
+// below that takes a restart index.
+__global__ __launch_bounds__(kKmThreads) void k_pp_update(const double* __restrict__ H, int64_t n, int kdim, int K,
                                                           const int64_t* __restrict__ idxp, int t,
                                                           double* __restrict__ cent, double* __restrict__ d2) {
     __shared__ double c[kMaxK];
-    const int64_t idx = *idxp;
+    const int r = blockIdx.y;
+    cent += (size_t)r * K * kdim;
+    d2 += (size_t)r * n;
+    const int64_t idx = idxp[r];
     if (threadIdx.x < kdim) c[threadIdx.x] = H[(int64_t)threadIdx.x * n + idx];
     __syncthreads();
     if (blockIdx.x == 0 && threadIdx.x < kdim) cent[t * kdim + threadIdx.x] = c[threadIdx.x];
@@ -64,8 +70,10 @@ __global__ __launch_bounds__(kKmThreads) void k_pp_update(const double* __restri
 
 // Chunk sums of d2 (chunk = kChunk rows, one block per chunk, fixed tree).
 __global__ __launch_bounds__(kKmThreads) void k_chunk_sums(const double* __restrict__ d2, int64_t n,
-                                                           double* __restrict__ csum) {
+                                                           double* __restrict__ csum, int cst) {
     __shared__ double red[kKmThreads];
+    d2 += (size_t)blockIdx.y * n;
+    csum += (size_t)blockIdx.y * cst;
     const int64_t base = (int64_t)blockIdx.x * kChunk;
     double s = 0.0;
     for (int q = threadIdx.x; q < kChunk; q += kKmThreads) {
@@ -89,8 +97,13 @@ __global__ __launch_bounds__(kKmThreads) void k_chunk_sums(const double* __restr
 // fixed, so the pick is reproducible; where rounding leaves no prefix above
 // the target, the last row of the range is taken.
 __global__ __launch_bounds__(64) void k_pp_pick(const double* __restrict__ d2, const double* __restrict__ csum,
-                                                int nchunks, int64_t n, double u, int64_t* __restrict__ idxp) {
-    const int lane = threadIdx.x;
+                                                int cst, int nchunks, int64_t n, uint64_t seed, int t,
+                                                int64_t* __restrict__ idxp) {
+    const int lane = threadIdx.x, r = blockIdx.y;
+    d2 += (size_t)r * n;
+    csum += (size_t)r * cst;
+    idxp += r;
+    const double u = sm_uniform(seed, (uint64_t)r, (uint64_t)t);
     const int S = (nchunks + 63) / 64;
     const int c0 = min(nchunks, lane * S), c1 = min(nchunks, c0 + S);
     double seg = 0.0;
@@ -153,6 +166,14 @@ __global__ __launch_bounds__(kKmThreads) void k_assign(const double* __restrict_
                                                        const double* __restrict__ cent, int32_t* __restrict__ lab,
                                                        double* __restrict__ mind, int* __restrict__ changed_part,
                                                        const int* __restrict__ done) {
+    {
+        const int r = blockIdx.y;
+        cent += (size_t)r * K * kdim;
+        lab += (size_t)r * n;
+        mind += (size_t)r * n;
+        changed_part += (size_t)r * gridDim.x;
+        done += 2 * r;
+    }
     if (*done) return;
     __shared__ double c[kMaxK * kMaxK];
     __shared__ int cnt[kKmThreads];
@@ -194,6 +215,13 @@ __global__ __launch_bounds__(kKmThreads) void k_cluster_sums(const double* __res
                                                              int K, const int32_t* __restrict__ lab,
                                                              double* __restrict__ part, int* __restrict__ cpart,
                                                              const int* __restrict__ done) {
+    {
+        const int r = blockIdx.y;
+        lab += (size_t)r * n;
+        part += (size_t)r * gridDim.x * K * kdim;
+        cpart += (size_t)r * gridDim.x * K;
+        done += 2 * r;
+    }
     if (*done) return;
     constexpr int kWaves = kKmThreads / 64;
     extern __shared__ double sh[];  // [kWaves][K][kdim] sums, then [kWaves][K] counts (as double)
@@ -238,6 +266,15 @@ __global__ __launch_bounds__(1024) void k_update(const double* __restrict__ H, i
     __shared__ double bestv[1024];
     __shared__ int64_t besti[1024];
     __shared__ int64_t used[kMaxK];
+    {
+        const int r = blockIdx.y;
+        changed_part += (size_t)r * nb_assign;
+        part += (size_t)r * nb_sum * K * kdim;
+        cpart += (size_t)r * nb_sum * K;
+        mind += (size_t)r * n;
+        cent += (size_t)r * K * kdim;
+        state += 2 * r;
+    }
     if (state[0]) return;
     // the counts are integers: shared atomics give the exact sums
     if (threadIdx.x == 0) changed = 0;
@@ -327,8 +364,10 @@ __global__ __launch_bounds__(1024) void k_update(const double* __restrict__ H, i
 
 // Per-block sums of mind (inertia), fixed tree.
 __global__ __launch_bounds__(kKmThreads) void k_sum(const double* __restrict__ v, int64_t n,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, int cst) {
     __shared__ double red[kKmThreads];
+    v += (size_t)blockIdx.y * n;
+    part += (size_t)blockIdx.y * cst;
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         s += v[i];
@@ -358,31 +397,39 @@ __global__ void k_relabel(const int32_t* __restrict__ lab, int64_t n, const int3
         out[i] = map[lab[i]];
 }
 
-// The first k-means++ pick of a restart (drawn on the host).
-__global__ void k_set_index(int64_t* __restrict__ idx, int64_t v) { *idx = v; }
-
-// The restart's inertia: the per-block partial sums of k_sum added in block
-// order by one thread (the order the host used); kst[0] holds the best
-// inertia so far (+inf before the first restart), kst[1] is set to 1 when
-// this restart is strictly better (ties keep the earliest), else 0.
-__global__ void k_inertia_pick(const double* __restrict__ part, int nb, double* __restrict__ kst) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    const bool better = s < kst[0];
-    if (better) kst[0] = s;
-    kst[1] = better ? 1.0 : 0.0;
+// The first k-means++ pick of every restart: row floor(u n) of its first draw.
+__global__ void k_first_pick(int R, int64_t n, uint64_t seed, int64_t* __restrict__ idxp) {
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        int64_t i0 = (int64_t)(sm_uniform(seed, (uint64_t)r, 0) * (double)n);
+        if (i0 >= n) i0 = n - 1;
+        idxp[r] = i0;
+    }
 }
 
-__global__ void k_copy_if(const double* __restrict__ flag, const int32_t* __restrict__ src, int64_t n,
-                          int32_t* __restrict__ dst) {
-    if (flag[1] == 0.0) return;
+// The best restart: each restart's inertia is its per-block partial sums of
+// k_sum added in block order; the smallest wins, ties to the earliest
+// restart.  kst[0] = its inertia, kst[1] = its index.
+__global__ void k_best_restart(const double* __restrict__ part, int nb, int cst, int R, double* __restrict__ kst) {
+    double best = INFINITY;
+    int br = 0;
+    for (int r = 0; r < R; ++r) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[(size_t)r * cst + b];
+        if (s < best) {
+            best = s;
+            br = r;
+        }
+    }
+    kst[0] = best;
+    kst[1] = (double)br;
+}
+
+// The best restart's labels.
+__global__ void k_copy_best(const double* __restrict__ kst, const int32_t* __restrict__ lab, int64_t n,
+                            int32_t* __restrict__ dst) {
+    const int64_t off = (int64_t)kst[1] * n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
-__global__ void k_set_inf(double* __restrict__ kst) {
-    kst[0] = INFINITY;
-    kst[1] = 0.0;
+        dst[i] = lab[off + i];
 }
 
 static int grid_n(int64_t n, int cap) {
@@ -397,64 +444,64 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     const int nchunks = (int)((n + kChunk - 1) / kChunk);
     const int nb = grid_n(n, kKmMaxBlocks);
     const int nbs = std::max(1, std::min<int>(nb, 256));
-    SF_TRY(w.d2.ensure((size_t)n * sizeof(double)));
-    SF_TRY(w.cs.ensure((size_t)std::max(std::max(nchunks, nb), K) * sizeof(double)));
-    SF_TRY(w.cent.ensure((size_t)K * kdim * sizeof(double)));
-    SF_TRY(w.lab.ensure((size_t)n * sizeof(int32_t)));
+    const int cst = std::max(std::max(nchunks, nb), K);  // per-restart stride of csum
+    // every restart has its own slices: the restarts run side by side, each
+    // kernel launch covering all of them (restart = blockIdx.y), each
+    // restart's arithmetic exactly that of a restart run alone
+    SF_TRY(w.d2.ensure((size_t)R * n * sizeof(double)));
+    SF_TRY(w.cs.ensure((size_t)R * cst * sizeof(double)));
+    SF_TRY(w.cent.ensure((size_t)R * K * kdim * sizeof(double)));
+    SF_TRY(w.lab.ensure((size_t)R * n * sizeof(int32_t)));
     SF_TRY(w.best.ensure((size_t)n * sizeof(int32_t)));
-    SF_TRY(w.part.ensure((size_t)nbs * K * kdim * sizeof(double)));
-    SF_TRY(w.misc.ensure((size_t)(nb + nbs * K + 64) * sizeof(int) + 64 * sizeof(int64_t)));
+    SF_TRY(w.part.ensure((size_t)R * nbs * std::max(K * kdim, 2 * K) * sizeof(double)));
+    SF_TRY(w.misc.ensure((size_t)R * (nb + nbs * K + 2) * sizeof(int) + ((size_t)R + 16) * sizeof(int64_t)));
     double* d2 = w.d2.as<double>();  // D^2 during seeding, then min distances
     double* csum = w.cs.as<double>();
     double* cent = w.cent.as<double>();
     int32_t* lab = w.lab.as<int32_t>();
     int32_t* best = w.best.as<int32_t>();
     double* part = w.part.as<double>();
-    int64_t* idxp = reinterpret_cast<int64_t*>(w.misc.p);
-    double* kst = reinterpret_cast<double*>(idxp + 8);  // best inertia, improved flag
-    int* state = reinterpret_cast<int*>(kst + 8);
-    int* changed_part = state + 8;
-    int* cpart = changed_part + nb;
+    int64_t* idxp = reinterpret_cast<int64_t*>(w.misc.p);                        // [R]
+    double* kst = reinterpret_cast<double*>(idxp + R);                            // best inertia, restart
+    int* state = reinterpret_cast<int*>(kst + 8);                                 // [R][2]
+    int* changed_part = state + 2 * (size_t)R;                                    // [R][nb]
+    int* cpart = changed_part + (size_t)R * nb;                                   // [R][nbs][K]
     const size_t sum_lds = (size_t)(kKmThreads / 64) * K * (kdim + 1) * sizeof(double);
 
-    k_set_inf<<<1, 1, 0, s>>>(kst);
-    for (int r = 0; r < R; ++r) {
-        // k-means++ seeding
-        for (int t = 0; t < K; ++t) {
-            const double u = sm_uniform(seed, (uint64_t)r, (uint64_t)t);
-            if (t == 0) {
-                int64_t i0 = (int64_t)(u * (double)n);
-                if (i0 >= n) i0 = n - 1;
-                k_set_index<<<1, 1, 0, s>>>(idxp, i0);
-            } else {
-                k_chunk_sums<<<nchunks, kKmThreads, 0, s>>>(d2, n, csum);
-                k_pp_pick<<<1, 64, 0, s>>>(d2, csum, nchunks, n, u, idxp);
-            }
-            k_pp_update<<<grid_n(n, 2048), kKmThreads, 0, s>>>(H, n, kdim, idxp, t, cent, d2);
+    // k-means++ seeding, all restarts at once
+    k_first_pick<<<1, 256, 0, s>>>(R, n, seed, idxp);
+    for (int t = 0; t < K; ++t) {
+        if (t > 0) {
+            k_chunk_sums<<<dim3(nchunks, R), kKmThreads, 0, s>>>(d2, n, csum, cst);
+            k_pp_pick<<<dim3(1, R), 64, 0, s>>>(d2, csum, cst, nchunks, n, seed, t, idxp);
         }
-        SF_HIP(hipGetLastError());
-        // Lloyd
-        k_fill_i32<<<grid_n(n, 2048), kKmThreads, 0, s>>>(lab, n, -1);
-        SF_HIP(hipMemsetAsync(state, 0, 2 * sizeof(int), s));
-        int hstate[2] = {0, 0};
-        while (true) {
-            for (int it = 0; it < 8; ++it) {
-                k_assign<<<nb, kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
-                k_cluster_sums<<<nbs, kKmThreads, sum_lds, s>>>(H, n, kdim, K, lab, part, cpart, state);
-                k_update<<<1, 1024, 0, s>>>(H, n, kdim, K, changed_part, nb, part, cpart, nbs, d2, cent, state,
-                                            max_iter);
-            }
-            SF_HIP(hipGetLastError());
-            SF_HIP(hipMemcpyAsync(hstate, state, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            SF_HIP(hipStreamSynchronize(s));
-            if (hstate[0]) break;
-        }
-        // the best restart so far kept on the device (no host round trip)
-        k_sum<<<nb, kKmThreads, 0, s>>>(d2, n, csum);
-        k_inertia_pick<<<1, 1, 0, s>>>(csum, nb, kst);
-        k_copy_if<<<grid_n(n, 2048), kKmThreads, 0, s>>>(kst, lab, n, best);
-        SF_HIP(hipGetLastError());
+        k_pp_update<<<dim3(grid_n(n, 2048), R), kKmThreads, 0, s>>>(H, n, kdim, K, idxp, t, cent, d2);
     }
+    SF_HIP(hipGetLastError());
+    // Lloyd, all restarts at once; a finished restart's launches return at
+    // once, and every eighth round the host checks whether all have finished
+    k_fill_i32<<<grid_n((int64_t)R * n, 4096), kKmThreads, 0, s>>>(lab, (int64_t)R * n, -1);
+    SF_HIP(hipMemsetAsync(state, 0, 2 * (size_t)R * sizeof(int), s));
+    std::vector<int> hstate(2 * (size_t)R, 0);
+    while (true) {
+        for (int it = 0; it < 8; ++it) {
+            k_assign<<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+            k_cluster_sums<<<dim3(nbs, R), kKmThreads, sum_lds, s>>>(H, n, kdim, K, lab, part, cpart, state);
+            k_update<<<dim3(1, R), 1024, 0, s>>>(H, n, kdim, K, changed_part, nb, part, cpart, nbs, d2, cent, state,
+                                                 max_iter);
+        }
+        SF_HIP(hipGetLastError());
+        SF_HIP(hipMemcpyAsync(hstate.data(), state, 2 * (size_t)R * sizeof(int), hipMemcpyDeviceToHost, s));
+        SF_HIP(hipStreamSynchronize(s));
+        bool all = true;
+        for (int r = 0; r < R; ++r) all = all && hstate[2 * (size_t)r] != 0;
+        if (all) break;
+    }
+    // inertias and the best restart on the device
+    k_sum<<<dim3(nb, R), kKmThreads, 0, s>>>(d2, n, csum, cst);
+    k_best_restart<<<1, 1, 0, s>>>(csum, nb, cst, R, kst);
+    k_copy_best<<<grid_n(n, 2048), kKmThreads, 0, s>>>(kst, lab, n, best);
+    SF_HIP(hipGetLastError());
     double best_inertia = INFINITY;
     SF_HIP(hipMemcpyAsync(&best_inertia, kst, sizeof(double), hipMemcpyDeviceToHost, s));
     // renumber by first appearance
