@@ -242,12 +242,17 @@ def main():
             "rayleigh_ritz_ms": round(ph["rr_ms"], 3),
         }
 
-    # labels (Alg. 3 step 4) once, for the record
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # labels (Alg. 3 step 4): one warm-up call (it sizes the workspace),
+    # then the median of three
     lab, _ = G.labels(results[precs[0]][1].H, k, n_restarts=10, seed=0)
-    torch.cuda.synchronize()
-    kmeans_ms = (time.perf_counter() - t0) * 1e3
+    km = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab, _ = G.labels(results[precs[0]][1].H, k, n_restarts=10, seed=0)
+        torch.cuda.synchronize()
+        km.append((time.perf_counter() - t0) * 1e3)
+    kmeans_ms = statistics.median(km)
     from sfairsc_inputs.msbm import MSBMGraph  # noqa: F401
 
     # the headline is the faster of the solves (both FP64-certified to the
