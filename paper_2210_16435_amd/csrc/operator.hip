@@ -25,7 +25,6 @@
 #include <mutex>
 
 #include "internal.h"
-#include "ortho.h"
 #include "reduce.h"
 
 namespace sfairsc {
@@ -577,8 +576,8 @@ static int ensure_op(sfairsc_graph* g) {
     w.nblk_proj = grid_rows(n, kProjThreads / 32, kProjMaxBlocks);
     // (rows of the output-major layouts round the block count up to 8)
     // (the input sums may also come from the orthogonalisation's last pass,
-    // over ortho_nblk(n) blocks)
-    SF_TRY(w.part_in.ensure((size_t)xcd_row(std::max(w.nblk_proj, ortho_nblk(n))) * g->h * 32 * sizeof(double)));
+    // over up to 256 blocks)
+    SF_TRY(w.part_in.ensure((size_t)xcd_row(std::max(w.nblk_proj, 256)) * g->h * 32 * sizeof(double)));
     SF_TRY(w.part_out.ensure((size_t)xcd_row(w.nblk_spmm) * g->h * 32 * sizeof(double)));
     SF_TRY(w.small.ensure((size_t)5 * kMaxGroups * 32 * sizeof(double)));
     SF_TRY(w.xp.ensure((size_t)n * 32 * sizeof(double)));
