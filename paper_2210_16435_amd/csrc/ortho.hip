@@ -776,6 +776,9 @@ __global__ __launch_bounds__(256) void k_fin_c(const double* __restrict__ sumC, 
 #ifndef SF_ORTHO_MAX_BLOCKS
 #define SF_ORTHO_MAX_BLOCKS 256
 #endif
+// the operator's input-sum buffer, which the last pass may fill, holds the
+// sums of at most 256 blocks
+static_assert(((SF_ORTHO_MAX_BLOCKS + 7) & ~7) <= 256, "ortho_nblk() exceeds the operator's input-sum rows");
 static int nblk_for(int64_t n) {
     const int64_t ntiles = (n + 15) / 16;
     constexpr int per = kOrWaves * SF_ORTHO_TILES_PER_WAVE;  // 16-row tiles per block
