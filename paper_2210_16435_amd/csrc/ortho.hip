@@ -83,6 +83,41 @@ __device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, doub
         for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
 }
 
+// The same for two register sets at once (tiles of the first, then of the
+// second, in one LDS area and one partial): one wave-ordered sequence of
+// barriers instead of two, each element summed in the same order.
+template <int NA, int NB>
+__device__ __forceinline__ void block_store_tiles2(d4 (&acca)[NA], int na, d4 (&accb)[NB], int nb, double* lds,
+                                                   double* __restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int w = 0; w < kOrWaves; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < NA + NB; ++t) {
+                const bool first = t < NA;
+                const int tt = first ? t : t - NA;
+                if (first ? tt < na : tt < nb) {
+                    const d4 v = first ? acca[first ? tt : 0] : accb[first ? 0 : tt];
+                    double* p = lds + ((size_t)(first ? tt : na + tt) * 64 + lane) * 4;
+                    if (w == 0) {
+                        p[0] = v[0];
+                        p[1] = v[1];
+                        p[2] = v[2];
+                        p[3] = v[3];
+                    } else {
+                        p[0] += v[0];
+                        p[1] += v[1];
+                        p[2] += v[2];
+                        p[3] += v[3];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < (na + nb) * 256; e += kOrThreads) out[e] = lds[e];
+}
+
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
 __device__ __forceinline__ double tile_at(const double* __restrict__ t, int BJ, int i, int j) {
     const int tile = (i >> 4) * BJ + (j >> 4);
@@ -619,9 +654,10 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
     } else if (GRAM || SYRK) {
         __syncthreads();  // Ms no longer needed: reuse LDS for the block sums
         const size_t gsz = (size_t)nrt * BJ * 256;
-        if (GRAM) block_store_tiles(accg, nrt * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256));
-        __syncthreads();
-        block_store_tiles(accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256) + gsz);
+        if constexpr (GRAM)
+            block_store_tiles2(accg, nrt * BJ, accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256));
+        else
+            block_store_tiles(accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256) + gsz);
     }
 }
 
@@ -940,7 +976,7 @@ int ortho_expand(const OrthoArgs& a) {
     // pass B: Y' = [V | Y0] [-H1; I] (built from pass A's tiles), Gram + Syrk
     const int kin = cv + b;
     const int OB = (nrt * BJ + BJ * BJ) * 256;
-    size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)nrt * BJ * 256) * sizeof(double);
+    size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)(nrt * BJ + BJ * BJ) * 256) * sizeof(double);
     launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, nullptr, a.part, a.flag, nullptr, 0,
                            sumA);
     k_reduce_partials<<<reduce_grid(OB), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
