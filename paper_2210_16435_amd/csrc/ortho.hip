@@ -52,70 +52,69 @@ constexpr int kOrThreads = SF_ORTHO_THREADS;
 constexpr int kOrWaves = kOrThreads / 64;
 constexpr int kMaxRT = (kLdMax + 15) / 16;  // 14 row tiles of the Gram products
 
-// Sum the 4 waves' register tiles (ntile tiles of 64 x d4) in LDS in wave
-// order and write the block partial.
-template <int NT>
-__device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, double* lds, double* __restrict__ out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < kOrWaves; ++w) {
-        if (wave == w) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                if (t < ntile) {
-                    double* p = lds + ((size_t)t * 64 + lane) * 4;
-                    if (w == 0) {
-                        p[0] = acc[t][0];
-                        p[1] = acc[t][1];
-                        p[2] = acc[t][2];
-                        p[3] = acc[t][3];
-                    } else {
-                        p[0] += acc[t][0];
-                        p[1] += acc[t][1];
-                        p[2] += acc[t][2];
-                        p[3] += acc[t][3];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (out)
-        for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
+// A block partial of ntile tiles is summed either from one LDS slot per
+// wave (one barrier; kOrWaves x ntile x 2 KiB of LDS, at most 64 KiB) or
+// wave after wave in one area (a barrier per wave).  Either way each
+// element is w_0 + w_1 + ... in wave order, so the two give the same bits.
+__host__ __device__ inline bool store_wide(int ntile) { return ntile * kOrWaves * 256 * 8 <= 64 * 1024; }
+inline size_t store_lds_bytes(int ntile) {
+    return (size_t)(store_wide(ntile) ? kOrWaves : 1) * ntile * 256 * sizeof(double);
 }
 
-// The same for two register sets at once (tiles of the first, then of the
-// second, in one LDS area and one partial): one wave-ordered sequence of
-// barriers instead of two, each element summed in the same order.
+// Sum the block's waves' register tiles (na tiles of acca, then nb of accb,
+// each 64 x d4) in LDS in wave order and write the block partial (out may be
+// null); the sums are left in lds[0 : (na + nb) * 256] for every thread.
 template <int NA, int NB>
 __device__ __forceinline__ void block_store_tiles2(d4 (&acca)[NA], int na, d4 (&accb)[NB], int nb, double* lds,
                                                    double* __restrict__ out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int w = 0; w < kOrWaves; ++w) {
-        if (wave == w) {
+    const int tot = (na + nb) * 256;
+    auto put = [&](double* base, bool add) {
 #pragma unroll
-            for (int t = 0; t < NA + NB; ++t) {
-                const bool first = t < NA;
-                const int tt = first ? t : t - NA;
-                if (first ? tt < na : tt < nb) {
-                    const d4 v = first ? acca[first ? tt : 0] : accb[first ? 0 : tt];
-                    double* p = lds + ((size_t)(first ? tt : na + tt) * 64 + lane) * 4;
-                    if (w == 0) {
-                        p[0] = v[0];
-                        p[1] = v[1];
-                        p[2] = v[2];
-                        p[3] = v[3];
-                    } else {
-                        p[0] += v[0];
-                        p[1] += v[1];
-                        p[2] += v[2];
-                        p[3] += v[3];
-                    }
+        for (int t = 0; t < NA + NB; ++t) {
+            const bool first = t < NA;
+            const int tt = first ? t : t - NA;
+            if (first ? tt < na : tt < nb) {
+                const d4 v = first ? acca[first ? tt : 0] : accb[first ? 0 : tt];
+                double* p = base + ((size_t)(first ? tt : na + tt) * 64 + lane) * 4;
+                if (add) {
+                    p[0] += v[0];
+                    p[1] += v[1];
+                    p[2] += v[2];
+                    p[3] += v[3];
+                } else {
+                    p[0] = v[0];
+                    p[1] = v[1];
+                    p[2] = v[2];
+                    p[3] = v[3];
                 }
             }
         }
+    };
+    if (store_wide(na + nb)) {
+        put(lds + (size_t)wave * tot, false);
+        __syncthreads();
+        for (int e = threadIdx.x; e < tot; e += kOrThreads) {
+            double sum = lds[e];
+            for (int w = 1; w < kOrWaves; ++w) sum += lds[(size_t)w * tot + e];
+            lds[e] = sum;
+            if (out) out[e] = sum;
+        }
+        __syncthreads();
+        return;
+    }
+    for (int w = 0; w < kOrWaves; ++w) {
+        if (wave == w) put(lds, w != 0);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < (na + nb) * 256; e += kOrThreads) out[e] = lds[e];
+    if (out)
+        for (int e = threadIdx.x; e < tot; e += kOrThreads) out[e] = lds[e];
+}
+
+template <int NT>
+__device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, double* lds, double* __restrict__ out) {
+    d4 none[1] = {d4{0, 0, 0, 0}};
+    block_store_tiles2(acc, ntile, none, 0, lds, out);
 }
 
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
@@ -962,7 +961,7 @@ int ortho_expand(const OrthoArgs& a) {
 
     // pass A
     const int OA = nrt * BJ * 256;
-    size_t ldsA = (size_t)OA * sizeof(double);
+    size_t ldsA = store_lds_bytes(nrt * BJ);
     if (a.lc && (b > 16 || a.lcw < 4 || a.lcw % 4 != 0 || a.m > a.lcw || a.m > kMaxGroups - 1 || !a.utab))
         return set_error(SFAIRSC_E_ARG, "internal: bad constraint image lcw=%d m=%d", a.lcw, a.m);
     if (a.t_is_float)
@@ -976,13 +975,13 @@ int ortho_expand(const OrthoArgs& a) {
     // pass B: Y' = [V | Y0] [-H1; I] (built from pass A's tiles), Gram + Syrk
     const int kin = cv + b;
     const int OB = (nrt * BJ + BJ * BJ) * 256;
-    size_t ldsB = std::max((size_t)kin * BJ * 16, (size_t)(nrt * BJ + BJ * BJ) * 256) * sizeof(double);
+    size_t ldsB = std::max((size_t)kin * BJ * 16 * sizeof(double), store_lds_bytes(nrt * BJ + BJ * BJ));
     launch_upd<true, true>(BJ, nblk, ldsB, s, a.V, a.ld, n, 0, kin, cv, b, cv, nullptr, a.part, a.flag, nullptr, 0,
                            sumA);
     k_reduce_partials<<<reduce_grid(OB), kRedElems * kRedSlices, 0, s>>>(a.part, nblk, OB, sumB, a.flag);
 
     const int OC = BJ * BJ * 256;
-    size_t ldsC = std::max((size_t)kin * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
+    size_t ldsC = std::max((size_t)kin * BJ * 16 * sizeof(double), store_lds_bytes(BJ * BJ));
     size_t ldsD = (size_t)b * BJ * 16 * sizeof(double);
     if (b <= 8) {
         // pass C: R1 = chol(G) and M2 = [-H2 R1^{-1}; R1^{-1}] (folded in),
@@ -1047,7 +1046,7 @@ int ortho_start(double* V, int ld, int64_t n, int b, const double* ident, double
     double* M3 = R1 + kMaxBlock * kMaxBlock;
     double* M = sumA + (size_t)(kMaxRT * 2 + 4) * 256 * 2;  // the H1 slot: b x b
     const int OS = BJ * BJ * 256;
-    const size_t lds = std::max((size_t)b * BJ * 16, (size_t)BJ * BJ * 256) * sizeof(double);
+    const size_t lds = std::max((size_t)b * BJ * 16 * sizeof(double), store_lds_bytes(BJ * BJ));
 #define SF_FINC(BB, R1IN, MOUT, TH)                                                                            \
     k_fin_c<BB><<<1, 256, 0, s>>>(sumA, BJ, R1IN, MOUT, rc, gsave, -1, flag, flag, TH)
 #define SF_FINC_B(R1IN, MOUT, TH)                \
