@@ -53,10 +53,10 @@ constexpr int kOrWaves = kOrThreads / 64;
 constexpr int kMaxRT = (kLdMax + 15) / 16;  // 14 row tiles of the Gram products
 
 // A block partial of ntile tiles is summed either from one LDS slot per
-// wave (one barrier; kOrWaves x ntile x 2 KiB of LDS, at most 64 KiB) or
+// wave (one barrier; kOrWaves x ntile x 2 KiB of LDS, at most 96 KiB) or
 // wave after wave in one area (a barrier per wave).  Either way each
 // element is w_0 + w_1 + ... in wave order, so the two give the same bits.
-__host__ __device__ inline bool store_wide(int ntile) { return ntile * kOrWaves * 256 * 8 <= 64 * 1024; }
+__host__ __device__ inline bool store_wide(int ntile) { return ntile * kOrWaves * 256 * 8 <= 96 * 1024; }
 inline size_t store_lds_bytes(int ntile) {
     return (size_t)(store_wide(ntile) ? kOrWaves : 1) * ntile * 256 * sizeof(double);
 }
