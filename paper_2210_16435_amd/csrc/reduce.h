@@ -38,8 +38,16 @@ __global__ __launch_bounds__(kRedElems * kRedSlices) void k_reduce_partials(cons
     red[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (sl == 0 && e < O) {
+        // the slices in order, read sixteen at a time so that the reads
+        // are in flight together
         double t = 0.0;
-        for (int q = 0; q < kRedSlices; ++q) t += red[q * kRedElems + el];
+        for (int q0 = 0; q0 < kRedSlices; q0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = red[(q0 + u) * kRedElems + el];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) t += v[u];
+        }
         out[e] = t;
     }
 }
