@@ -24,10 +24,11 @@
 //    4q..4q+3 in exactly the operand layout of a Gram step, so the new block
 //    feeds the following Gram/Syrk products straight from registers.
 //
-// Each block has 4 waves; a wave owns 16-row tiles (grid-stride) and keeps
-// its products in registers; the 4 waves add into LDS in a fixed order and
-// the block writes one partial (tile layout: [tile][lane][4]).  Partials are
-// summed in a fixed order by k_reduce_partials: bitwise reproducible results.
+// Each block has kOrWaves waves; a wave owns 16-row tiles (grid-stride) and
+// keeps its products in registers; the waves' tiles are summed in LDS in wave
+// order and the block writes one partial (tile layout: [tile][lane][4]).
+// Partials are summed in a fixed order by k_reduce_partials: bitwise
+// reproducible results.
 #include <algorithm>
 
 #include <type_traits>
