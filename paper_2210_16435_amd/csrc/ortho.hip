@@ -65,7 +65,10 @@ inline size_t store_lds_bytes(int ntile) {
 // Sum the block's waves' register tiles (na tiles of acca, then nb of accb,
 // each 64 x d4) in LDS in wave order and write the block partial (out may be
 // null); the sums are left in lds[0 : (na + nb) * 256] for every thread.
-template <int NA, int NB>
+// WIDE: the one-barrier form may be taken (compiled for small register sets
+// only: with the wide passes' 28 tiles a second copy of the stores costs
+// registers, which those kernels spill).
+template <bool WIDE, int NA, int NB>
 __device__ __forceinline__ void block_store_tiles2(d4 (&acca)[NA], int na, d4 (&accb)[NB], int nb, double* lds,
                                                    double* __restrict__ out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -92,7 +95,7 @@ __device__ __forceinline__ void block_store_tiles2(d4 (&acca)[NA], int na, d4 (&
             }
         }
     };
-    if (store_wide(na + nb)) {
+    if (WIDE && store_wide(na + nb)) {
         put(lds + (size_t)wave * tot, false);
         __syncthreads();
         for (int e = threadIdx.x; e < tot; e += kOrThreads) {
@@ -112,10 +115,39 @@ __device__ __forceinline__ void block_store_tiles2(d4 (&acca)[NA], int na, d4 (&
         for (int e = threadIdx.x; e < tot; e += kOrThreads) out[e] = lds[e];
 }
 
-template <int NT>
+template <bool WIDE, int NT>
 __device__ __forceinline__ void block_store_tiles(d4 (&acc)[NT], int ntile, double* lds, double* __restrict__ out) {
-    d4 none[1] = {d4{0, 0, 0, 0}};
-    block_store_tiles2(acc, ntile, none, 0, lds, out);
+    if constexpr (WIDE) {
+        d4 none[1] = {d4{0, 0, 0, 0}};
+        block_store_tiles2<true>(acc, ntile, none, 0, lds, out);
+    } else {
+        // wave after wave only (the same sums)
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int w = 0; w < kOrWaves; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (t < ntile) {
+                        double* p = lds + ((size_t)t * 64 + lane) * 4;
+                        if (w == 0) {
+                            p[0] = acc[t][0];
+                            p[1] = acc[t][1];
+                            p[2] = acc[t][2];
+                            p[3] = acc[t][3];
+                        } else {
+                            p[0] += acc[t][0];
+                            p[1] += acc[t][1];
+                            p[2] += acc[t][2];
+                            p[3] += acc[t][3];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (out)
+            for (int e = threadIdx.x; e < ntile * 256; e += kOrThreads) out[e] = lds[e];
+    }
 }
 
 // Element (i, j) of a tile-layout matrix with BJ column tiles.
@@ -315,7 +347,7 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_a(double* __restrict__ V, i
             }
         }
     }
-    block_store_tiles(acc, nrt * BJ, lds, part + (size_t)blockIdx.x * nrt * BJ * 256);
+    block_store_tiles<RT * BJ <= 8>(acc, nrt * BJ, lds, part + (size_t)blockIdx.x * nrt * BJ * 256);
 }
 
 // Passes B, C, D (and the restart rotation).  Ynew = In M with
@@ -648,16 +680,24 @@ __global__ __launch_bounds__(kOrThreads) void k_pass_upd(double* V, int ld, int6
         // the folded pass C: its block's B x B Gram, row-major, for the next
         // pass to sum (no separate reduction)
         __syncthreads();
-        block_store_tiles(accs, 1, lds, nullptr);
+        block_store_tiles<true>(accs, 1, lds, nullptr);
         for (int e = threadIdx.x; e < CB * CB; e += kOrThreads)
             part[(size_t)blockIdx.x * (CB * CB) + e] = tile_at(lds, 1, e / CB, e % CB);
     } else if (GRAM || SYRK) {
         __syncthreads();  // Ms no longer needed: reuse LDS for the block sums
         const size_t gsz = (size_t)nrt * BJ * 256;
-        if constexpr (GRAM)
-            block_store_tiles2(accg, nrt * BJ, accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256));
-        else
-            block_store_tiles(accs, BJ * BJ, lds, part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256) + gsz);
+        double* dst = part + (size_t)blockIdx.x * (gsz + BJ * BJ * 256);
+        if constexpr (GRAM && NG <= 8) {
+            block_store_tiles2<true>(accg, nrt * BJ, accs, BJ * BJ, lds, dst);
+        } else if constexpr (GRAM) {
+            // (the wide Gram: the two sets one after the other, as in its
+            // tuned form)
+            block_store_tiles<false>(accg, nrt * BJ, lds, dst);
+            __syncthreads();
+            block_store_tiles<false>(accs, BJ * BJ, lds, dst + gsz);
+        } else {
+            block_store_tiles<true>(accs, BJ * BJ, lds, dst + gsz);
+        }
     }
 }
 
