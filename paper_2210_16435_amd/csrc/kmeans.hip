@@ -16,6 +16,7 @@
 // H is read column-major (n x kdim) so consecutive threads read consecutive
 // rows.  Sums use fixed per-block partials combined in block order.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <numeric>
 
@@ -385,10 +386,26 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
         p[i] = v;
 }
 
-// first[j] = smallest row with label j (atomicMin: order independent).
-__global__ void k_first(const int32_t* __restrict__ lab, int64_t n, long long* __restrict__ first) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicMin(&first[lab[i]], (long long)i);
+// first[j] = smallest row with label j (labels < K <= 64; atomicMin: order
+// independent).  A thread's rows increase, so only the first row of each
+// label it meets can be its minimum: one shared atomic per thread and label,
+// then one global atomic per block and label.
+__global__ __launch_bounds__(kKmThreads) void k_first(const int32_t* __restrict__ lab, int64_t n, int K,
+                                                       long long* __restrict__ first) {
+    __shared__ long long smin[kMaxK];
+    for (int j = threadIdx.x; j < K; j += kKmThreads) smin[j] = LLONG_MAX;
+    __syncthreads();
+    uint64_t seen = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = lab[i];
+        if (!((seen >> l) & 1)) {
+            seen |= 1ull << l;
+            atomicMin(&smin[l], (long long)i);
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < K; j += kKmThreads)
+        if (smin[j] != LLONG_MAX) atomicMin(&first[j], smin[j]);
 }
 
 __global__ void k_relabel(const int32_t* __restrict__ lab, int64_t n, const int32_t* __restrict__ map,
@@ -407,21 +424,52 @@ __global__ void k_first_pick(int R, int64_t n, uint64_t seed, int64_t* __restric
 }
 
 // The best restart: each restart's inertia is its per-block partial sums of
-// k_sum added in block order; the smallest wins, ties to the earliest
-// restart.  kst[0] = its inertia, kst[1] = its index.
-__global__ void k_best_restart(const double* __restrict__ part, int nb, int cst, int R, double* __restrict__ kst) {
+// k_sum added in block order (one thread per restart); the smallest wins,
+// ties to the earliest restart, and a restart whose inertia is not below
+// infinity (or NaN) never does (restart 0 if none is).  kst[0] = its
+// inertia, kst[1] = its index.
+__global__ __launch_bounds__(kKmThreads) void k_best_restart(const double* __restrict__ part, int nb, int cst, int R,
+                                                              double* __restrict__ kst) {
+    __shared__ double sb[kKmThreads];
+    __shared__ int si[kKmThreads];
+    const int none = 0x7fffffff;
     double best = INFINITY;
-    int br = 0;
-    for (int r = 0; r < R; ++r) {
+    int bi = none;
+    for (int r = threadIdx.x; r < R; r += kKmThreads) {
+        const double* p = part + (size_t)r * cst;
         double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += part[(size_t)r * cst + b];
+        int b = 0;
+        for (; b + 16 <= nb; b += 16) {
+            double x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) x[u] = p[b + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += x[u];
+        }
+        for (; b < nb; ++b) s += p[b];
         if (s < best) {
             best = s;
-            br = r;
+            bi = r;
         }
     }
-    kst[0] = best;
-    kst[1] = (double)br;
+    sb[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = kKmThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const double ob = sb[threadIdx.x + w];
+            const int oi = si[threadIdx.x + w];
+            if (ob < sb[threadIdx.x] || (ob == sb[threadIdx.x] && oi < si[threadIdx.x])) {
+                sb[threadIdx.x] = ob;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        kst[0] = sb[0];
+        kst[1] = (double)(si[0] == none ? 0 : si[0]);
+    }
 }
 
 // The best restart's labels.
@@ -499,7 +547,7 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     }
     // inertias and the best restart on the device
     k_sum<<<dim3(nb, R), kKmThreads, 0, s>>>(d2, n, csum, cst);
-    k_best_restart<<<1, 1, 0, s>>>(csum, nb, cst, R, kst);
+    k_best_restart<<<1, kKmThreads, 0, s>>>(csum, nb, cst, R, kst);
     k_copy_best<<<grid_n(n, 2048), kKmThreads, 0, s>>>(kst, lab, n, best);
     SF_HIP(hipGetLastError());
     double best_inertia = INFINITY;
@@ -508,7 +556,7 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     long long* first = reinterpret_cast<long long*>(part);
     std::vector<long long> hfirst(K, (long long)INT64_MAX);
     SF_HIP(hipMemcpyAsync(first, hfirst.data(), K * sizeof(long long), hipMemcpyHostToDevice, s));
-    k_first<<<grid_n(n, 2048), kKmThreads, 0, s>>>(best, n, first);
+    k_first<<<grid_n(n, 2048), kKmThreads, 0, s>>>(best, n, K, first);
     SF_HIP(hipMemcpyAsync(hfirst.data(), first, K * sizeof(long long), hipMemcpyDeviceToHost, s));
     SF_HIP(hipStreamSynchronize(s));
     std::vector<int> order(K);
