@@ -163,6 +163,8 @@ __global__ __launch_bounds__(64) void k_pp_pick(const double* __restrict__ d2, c
 }
 
 // Assignment: label_i = argmin_j ||H_i - c_j||^2; per-block changed count.
+// KD bounds kdim (8, 16, 32 or 64) so that the row stays in registers.
+template <int KD>
 __global__ __launch_bounds__(kKmThreads) void k_assign(const double* __restrict__ H, int64_t n, int kdim, int K,
                                                        const double* __restrict__ cent, int32_t* __restrict__ lab,
                                                        double* __restrict__ mind, int* __restrict__ changed_part,
@@ -182,15 +184,19 @@ __global__ __launch_bounds__(kKmThreads) void k_assign(const double* __restrict_
     __syncthreads();
     int changed = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double x[kMaxK];
-        for (int l = 0; l < kdim; ++l) x[l] = H[(int64_t)l * n + i];
+        double x[KD];
+#pragma unroll
+        for (int l = 0; l < KD; ++l) x[l] = l < kdim ? H[(int64_t)l * n + i] : 0.0;
         double best = INFINITY;
         int bj = 0;
         for (int j = 0; j < K; ++j) {
             double s = 0.0;
-            for (int l = 0; l < kdim; ++l) {
-                const double d = x[l] - c[j * kdim + l];
-                s += d * d;
+#pragma unroll
+            for (int l = 0; l < KD; ++l) {
+                if (l < kdim) {
+                    const double d = x[l] - c[j * kdim + l];
+                    s += d * d;
+                }
             }
             if (s < best) {
                 best = s;
@@ -533,7 +539,14 @@ static int labels_impl(sfairsc_graph* g, const double* H, int kdim, int K, int R
     std::vector<int> hstate(2 * (size_t)R, 0);
     while (true) {
         for (int it = 0; it < 8; ++it) {
-            k_assign<<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+            if (kdim <= 8)
+                k_assign<8><<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+            else if (kdim <= 16)
+                k_assign<16><<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+            else if (kdim <= 32)
+                k_assign<32><<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
+            else
+                k_assign<64><<<dim3(nb, R), kKmThreads, 0, s>>>(H, n, kdim, K, cent, lab, d2, changed_part, state);
             k_cluster_sums<<<dim3(nbs, R), kKmThreads, sum_lds, s>>>(H, n, kdim, K, lab, part, cpart, state);
             k_update<<<dim3(1, R), 1024, 0, s>>>(H, n, kdim, K, changed_part, nb, part, cpart, nbs, d2, cent, state,
                                                  max_iter);
