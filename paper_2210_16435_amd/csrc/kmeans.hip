@@ -243,7 +243,23 @@ __global__ __launch_bounds__(kKmThreads) void k_cluster_sums(const double* __res
     const int64_t per_wave = (r1 - r0 + kWaves - 1) / kWaves;
     const int64_t w0 = r0 + wave * per_wave, w1 = min(r1, w0 + per_wave);
     double* ws = sums + wave * K * kdim;
-    for (int64_t i = w0; i < w1; ++i) {
+    // rows in order, eight at a time with their loads issued first
+    int64_t i = w0;
+    for (; i + 8 <= w1; i += 8) {
+        int jj[8];
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            jj[u] = lab[i + u];
+            hv[u] = lane < kdim ? H[(int64_t)lane * n + i + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (lane < kdim) ws[jj[u] * kdim + lane] += hv[u];
+            if (lane == 0) cnts[wave * K + jj[u]] += 1.0;
+        }
+    }
+    for (; i < w1; ++i) {
         const int j = lab[i];
         if (lane < kdim) ws[j * kdim + lane] += H[(int64_t)lane * n + i];
         if (lane == 0) cnts[wave * K + j] += 1.0;
