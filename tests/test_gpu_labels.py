@@ -53,6 +53,22 @@ def test_labels_match_oracle_on_overlapping_blobs(seed, shape):
     assert np.array_equal(to_np(lab_gpu), lab_ref)
 
 
+@pytest.mark.parametrize("n,K,dim,R", [(1500, 64, 20, 3), (900, 12, 40, 260), (700, 5, 3, 257)])
+def test_labels_edge_shapes(n, K, dim, R):
+    # the most clusters (64: every bit of the first-appearance mask), rows
+    # of 20 and 40 values (the wider register layouts of the assignment)
+    # and more restarts than the best-restart workgroup has threads
+    sf = lib()
+    rng = np.random.default_rng(5)
+    X = (4.0 * rng.standard_normal((K, dim)))[rng.integers(0, K, n)] + 0.6 * rng.standard_normal((n, dim))
+    G = _graph_for(sf, n)
+    lab_gpu, inertia_gpu = G.labels(torch.from_numpy(X), K, n_restarts=R, seed=5)
+    lab_ref, inertia_ref = oracle.kmeans(X, K, R, 5)
+    log(f"edge shape n={n} K={K} dim={dim} R={R}: inertia {inertia_gpu} vs {inertia_ref}")
+    assert inertia_gpu == pytest.approx(inertia_ref, rel=1e-10)
+    assert np.array_equal(to_np(lab_gpu), lab_ref)
+
+
 def test_labels_rotation_invariant_and_bruteforce_small():
     sf = lib()
     rng = np.random.default_rng(3)
