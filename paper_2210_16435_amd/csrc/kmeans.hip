@@ -324,7 +324,16 @@ __global__ __launch_bounds__(1024) void k_update(const double* __restrict__ H, i
         if (t < P * O) {
             const int o = t % O, sl = t / O;
             double s0 = 0.0;
-            for (int b = sl; b < nb_sum; b += P) s0 += part[(size_t)b * O + o];
+            int b = sl;
+            // blocks sl, sl + P, ... in order, eight loads in flight
+            for (; b + 7 * P < nb_sum; b += 8 * P) {
+                double x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = part[(size_t)(b + u * P) * O + o];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s0 += x[u];
+            }
+            for (; b < nb_sum; b += P) s0 += part[(size_t)b * O + o];
             bestv[t] = s0;
         }
         __syncthreads();
