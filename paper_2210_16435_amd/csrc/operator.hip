@@ -312,7 +312,7 @@ __global__ __launch_bounds__(kFinThreads) void k_group_finalize(const double* __
 // (C^T Z as in the file header).  Nothing here mixes the block's columns:
 // one workgroup per column j (32 of them, those past b write zeros), one
 // wavefront per sum with its lanes over the blocks.
-constexpr int kFin2Threads = 256;
+constexpr int kFin2Threads = 1024;
 __global__ __launch_bounds__(kFin2Threads) void k_group_finalize2(const double* __restrict__ partx, int nbx,
                                                                    const double* __restrict__ partt, int nbt, int h,
                                                                    int b, const double* __restrict__ gpar,
