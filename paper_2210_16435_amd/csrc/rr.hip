@@ -956,6 +956,8 @@ int rr_launch(const RrArgs& a, hipStream_t s) {
     }
     if (a.c <= 64)
         k_rr<4, 1><<<1, kRrT, 0, s>>>(a);
+    else if (a.c <= 80)
+        k_rr<5, 2><<<1, kRrT, 0, s>>>(a);
     else if (a.c <= 96)
         k_rr<6, 2><<<1, kRrT, 0, s>>>(a);
     else if (a.c <= 128)
